@@ -1,0 +1,195 @@
+"""FP64 CPU oracle for iterative PCA (NIPALS-PCA and GS-PCA) -- TEST INFRASTRUCTURE.
+
+Only the test-suite, the package's ``smoke()`` check and the benchmark's
+CPU-baseline leg may import this module.  The GPU library never does, and the
+two share no code.  The arithmetic lives in plain C (``pca_oracle.c``,
+``codec_oracle.c``); this module builds it with gcc on first use and marshals
+numpy arrays to it.  See the header of ``pca_oracle.c`` for the paper passages
+each routine follows (Andrecut, arXiv:0811.1081, Secs. 2.2-2.3).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+import threading
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SOURCES = ("pca_oracle.c", "codec_oracle.c")
+LIB_PATH = os.path.join(_HERE, "liboracle.so")
+CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
+          "-Wall", "-Wextra", "-Wno-unused-parameter"]
+
+ALGO_GS, ALGO_NIPALS = 0, 1
+INIT_MAXNORM, INIT_COLUMN_K, INIT_GIVEN = 0, 1, 2
+OK, NOT_CONVERGED, EINVAL, ENONFINITE = 0, 1, -1, -4
+DBL_MIN = np.finfo(np.float64).tiny
+FLT_MIN = float(np.finfo(np.float32).tiny)
+
+_lock = threading.Lock()
+_lib = None
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc into ``oracle/liboracle.so``."""
+    srcs = [os.path.join(_HERE, s) for s in _SOURCES]
+    if not force and os.path.exists(LIB_PATH):
+        newest = max(os.path.getmtime(s) for s in srcs)
+        if os.path.getmtime(LIB_PATH) >= newest:
+            return LIB_PATH
+    tmp = LIB_PATH + ".tmp%d" % os.getpid()
+    subprocess.run(["gcc", *CFLAGS, "-o", tmp, *srcs, "-lm"], check=True)
+    os.replace(tmp, LIB_PATH)
+    return LIB_PATH
+
+
+def lib() -> ctypes.CDLL:
+    global _lib
+    with _lock:
+        if _lib is None:
+            build(force=False)
+            L = ctypes.CDLL(LIB_PATH)
+            i64, i32, dbl = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+            vp = ctypes.c_void_p
+            L.oracle_fit.restype = ctypes.c_int
+            L.oracle_fit.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, i64, i64, i64, dbl, i32,
+                                     ctypes.c_int, vp, vp, vp, dbl, vp, vp, vp, vp, vp, vp]
+            L.oracle_score_step.restype = ctypes.c_int
+            L.oracle_score_step.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
+            L.oracle_jacobi_eig.restype = ctypes.c_int
+            L.oracle_jacobi_eig.argtypes = [vp, i64, vp, vp]
+            L.oracle_bf16_encode.restype = ctypes.c_uint16
+            L.oracle_bf16_encode.argtypes = [ctypes.c_float]
+            L.oracle_bf16_decode.restype = ctypes.c_float
+            L.oracle_bf16_decode.argtypes = [ctypes.c_uint16]
+            L.oracle_e4m3_encode.restype = ctypes.c_uint8
+            L.oracle_e4m3_encode.argtypes = [ctypes.c_float]
+            L.oracle_e4m3_decode.restype = ctypes.c_double
+            L.oracle_e4m3_decode.argtypes = [ctypes.c_uint8]
+            L.oracle_quantize.restype = ctypes.c_int
+            L.oracle_quantize.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp]
+            L.oracle_dequantize.restype = ctypes.c_int
+            L.oracle_dequantize.argtypes = [vp, vp, i64, i64, ctypes.c_int, vp]
+            _lib = L
+    return _lib
+
+
+def _ptr(a):
+    return None if a is None else a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _f64_fortran(X):
+    return np.asfortranarray(np.asarray(X, dtype=np.float64))
+
+
+class Fit:
+    """Result of one oracle fit: T (M x K), P (N x K), sigma, lam = sigma^2,
+    iters, start_col, status, and R (residual) when requested."""
+
+    def __init__(self, **kw):
+        self.__dict__.update(kw)
+
+    @property
+    def V(self):
+        """Normalised scores T / sigma (zero columns where sigma == 0)."""
+        s = np.where(self.sigma > 0, self.sigma, 1.0)
+        return self.T / s
+
+
+def fit(X, K, tol=1e-10, max_iter=1000, algo="gs", implicit=False, init="maxnorm",
+        T0=None, replay_iters=None, replay_start=None, tiny=DBL_MIN, want_R=False) -> Fit:
+    """Run NIPALS-PCA (algo='nipals') or GS-PCA (algo='gs') in FP64.
+
+    X is widened to float64 (an FP32 input is consumed exactly).  ``replay_iters``
+    forces the number of iterations per component and ``replay_start`` the start
+    column (entries < 0 fall back to ``init``)."""
+    X = _f64_fortran(X)
+    M, N = X.shape
+    T = np.zeros((M, K), order="F")
+    P = np.zeros((N, K), order="F")
+    sigma = np.zeros(K)
+    iters = np.zeros(K, dtype=np.int32)
+    start = np.zeros(K, dtype=np.int32)
+    R = np.zeros((M, N), order="F") if want_R else None
+    algo_i = {"gs": ALGO_GS, "nipals": ALGO_NIPALS}[algo]
+    init_i = {"maxnorm": INIT_MAXNORM, "column_k": INIT_COLUMN_K, "given": INIT_GIVEN}[init]
+    T0a = _f64_fortran(T0) if T0 is not None else None
+    ri = np.ascontiguousarray(replay_iters, dtype=np.int32) if replay_iters is not None else None
+    rs = np.ascontiguousarray(replay_start, dtype=np.int32) if replay_start is not None else None
+    st = lib().oracle_fit(algo_i, int(bool(implicit)), _ptr(X), M, N, M, K, float(tol),
+                          int(max_iter), init_i, _ptr(T0a), _ptr(ri), _ptr(rs), float(tiny),
+                          _ptr(T), _ptr(P), _ptr(sigma), _ptr(iters), _ptr(start), _ptr(R))
+    return Fit(T=T, P=P, sigma=sigma, lam=sigma ** 2, iters=iters, start_col=start,
+               status=st, R=R, algo=algo)
+
+
+def score_step(X, k, V, sigma, P, p):
+    """One GS-PCA score step on R_k = X - V diag(sigma) P^T (first k columns):
+    returns (v, s) with s v = (I - V V^T) R_k p."""
+    X = _f64_fortran(X)
+    M, N = X.shape
+    Vk = _f64_fortran(np.asarray(V)[:, :k]) if k > 0 else None
+    Pk = _f64_fortran(np.asarray(P)[:, :k]) if k > 0 else None
+    sk = np.ascontiguousarray(np.asarray(sigma, dtype=np.float64)[:k]) if k > 0 else None
+    pv = np.ascontiguousarray(p, dtype=np.float64)
+    v = np.zeros(M)
+    s = ctypes.c_double(0.0)
+    st = lib().oracle_score_step(_ptr(X), M, N, M, k, _ptr(Vk), _ptr(sk), _ptr(Pk), _ptr(pv),
+                                 _ptr(v), ctypes.byref(s))
+    if st != OK:
+        raise ValueError("oracle_score_step failed: %d" % st)
+    return v, s.value
+
+
+def jacobi_eig(A):
+    """Eigen-decomposition of a symmetric matrix by cyclic Jacobi: (w desc, Q)."""
+    A = _f64_fortran(A).copy(order="F")
+    n = A.shape[0]
+    w = np.zeros(n)
+    Q = np.zeros((n, n), order="F")
+    lib().oracle_jacobi_eig(_ptr(A), n, _ptr(w), _ptr(Q))
+    return w, Q
+
+
+def bf16_encode(x: float) -> int:
+    return int(lib().oracle_bf16_encode(float(x)))
+
+
+def bf16_decode(c: int) -> float:
+    return float(lib().oracle_bf16_decode(int(c)))
+
+
+def e4m3_encode(x: float) -> int:
+    return int(lib().oracle_e4m3_encode(float(x)))
+
+
+def e4m3_decode(c: int) -> float:
+    return float(lib().oracle_e4m3_decode(int(c)))
+
+
+FMT_BF16, FMT_E4M3 = 0, 1
+
+
+def quantize(X, fmt):
+    """Per-column-scaled codes of a binary32 matrix: (codes M x N, scales N)."""
+    fmt_i = {"bf16": FMT_BF16, "e4m3": FMT_E4M3}[fmt] if isinstance(fmt, str) else int(fmt)
+    X = np.asfortranarray(np.asarray(X, dtype=np.float32))
+    M, N = X.shape
+    codes = np.zeros((M, N), dtype=np.uint16 if fmt_i == FMT_BF16 else np.uint8, order="F")
+    scale = np.zeros(N, dtype=np.float32)
+    st = lib().oracle_quantize(_ptr(X), M, N, M, fmt_i, _ptr(codes), _ptr(scale))
+    if st != 0:
+        raise ValueError("oracle_quantize failed: %d" % st)
+    return codes, scale
+
+
+def dequantize(codes, scale, fmt):
+    fmt_i = {"bf16": FMT_BF16, "e4m3": FMT_E4M3}[fmt] if isinstance(fmt, str) else int(fmt)
+    codes = np.asfortranarray(codes)
+    M, N = codes.shape
+    out = np.zeros((M, N), order="F")
+    sc = np.ascontiguousarray(scale, dtype=np.float32)
+    lib().oracle_dequantize(_ptr(codes), _ptr(sc), M, N, fmt_i, _ptr(out))
+    return out

@@ -1,0 +1,123 @@
+/*
+ * codec_oracle.c -- reference encoders/decoders for the reduced-precision
+ * storage of X (BF16 and OCP FP8 E4M3 "fn") with per-column FP32 scales.
+ *
+ * TEST INFRASTRUCTURE.  Only the test-suite and the benchmark's CPU-baseline
+ * leg load this file; it shares no code with the GPU library.
+ *
+ * The storage form is not in the paper (whose Sec. 3 notes only that the
+ * double-precision programs convert directly to single precision); it is
+ * this project's reduced-precision variant of the residual products.
+ * Formats, from their public definitions:
+ *   - bfloat16: the upper 16 bits of an IEEE binary32 (1 sign, 8 exponent,
+ *     7 fraction bits); conversion rounds to nearest, ties to even.
+ *   - E4M3 "fn" (OCP 8-bit floating point, v1.0): 1 sign, 4 exponent bits
+ *     (bias 7), 3 fraction bits; no infinities; S.1111.111 is NaN; largest
+ *     finite magnitude 448; subnormals (exponent field 0) are m/8 * 2^-6.
+ *     Encoding here rounds to nearest, ties to even, and saturates to +-448.
+ * Per-column scale: s_j = amax_j / Qmax (binary32), Qmax = 448 for E4M3 and
+ * 1 for BF16; an all-zero column has s_j = 1.  Code = encode(x / s_j) with
+ * the division in binary32.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <string.h>
+
+static uint32_t f32_bits(float x) { uint32_t u; memcpy(&u, &x, 4); return u; }
+static float bits_f32(uint32_t u) { float x; memcpy(&x, &u, 4); return x; }
+
+float oracle_bf16_decode(uint16_t c) { return bits_f32((uint32_t)c << 16); }
+
+/* Round-to-nearest-even on the 16 discarded bits. */
+uint16_t oracle_bf16_encode(float x)
+{
+    uint32_t u = f32_bits(x);
+    if (isnan(x))
+        return (uint16_t)((u >> 16) | 0x0040u); /* quiet NaN, sign kept */
+    const uint32_t upper = u >> 16, lower = u & 0xFFFFu;
+    uint32_t r = upper;
+    if (lower > 0x8000u || (lower == 0x8000u && (upper & 1u)))
+        r = upper + 1u; /* carries into the exponent correctly, to Inf at the top */
+    return (uint16_t)r;
+}
+
+double oracle_e4m3_decode(uint8_t c)
+{
+    const int s = (c >> 7) & 1, e = (c >> 3) & 0xF, m = c & 7;
+    double v;
+    if (e == 0xF && m == 7)
+        return NAN;
+    if (e == 0)
+        v = ldexp((double)m / 8.0, -6);
+    else
+        v = ldexp(1.0 + (double)m / 8.0, e - 7);
+    return s ? -v : v;
+}
+
+/* Nearest representable magnitude by exhaustive search over the 127 finite
+ * non-negative codes, ties to the code with an even fraction field; values
+ * above 448 saturate to 448. */
+uint8_t oracle_e4m3_encode(float x)
+{
+    if (isnan(x))
+        return 0x7F;
+    const int neg = signbit(x) ? 1 : 0;
+    const double a = fabs((double)x);
+    if (a >= 448.0)
+        return (uint8_t)(0x7E | (neg << 7));
+    int best = 0;
+    double bestd = INFINITY;
+    for (int c = 0; c <= 0x7E; ++c) {
+        const double d = fabs(oracle_e4m3_decode((uint8_t)c) - a);
+        if (d < bestd || (d == bestd && (c & 1) == 0 && (best & 1) == 1)) {
+            bestd = d;
+            best = c;
+        }
+    }
+    return (uint8_t)(best | (neg << 7));
+}
+
+/* fmt 0 = BF16 (codes uint16), 1 = E4M3 (codes uint8).  X binary32 column-major
+ * (ld >= M); codes column-major with leading dimension M. */
+int oracle_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int fmt,
+                    void *codes, float *scale)
+{
+    if (!X || !codes || !scale || M < 1 || N < 1 || ldx < M || (fmt != 0 && fmt != 1))
+        return -1;
+    const float qmax = fmt == 1 ? 448.0f : 1.0f;
+    for (int64_t n = 0; n < N; ++n) {
+        float amax = 0.0f;
+        for (int64_t m = 0; m < M; ++m) {
+            const float a = fabsf(X[m + n * ldx]);
+            if (!(a <= amax))
+                amax = a; /* propagates NaN */
+        }
+        if (!isfinite(amax))
+            return -4;
+        const float s = amax > 0.0f ? amax / qmax : 1.0f;
+        scale[n] = s;
+        for (int64_t m = 0; m < M; ++m) {
+            const float q = X[m + n * ldx] / s;
+            if (fmt == 0)
+                ((uint16_t *)codes)[m + n * M] = oracle_bf16_encode(q);
+            else
+                ((uint8_t *)codes)[m + n * M] = oracle_e4m3_encode(q);
+        }
+    }
+    return 0;
+}
+
+/* Dequantised matrix x~ = decode(code) * s_j, exact in binary64. */
+int oracle_dequantize(const void *codes, const float *scale, int64_t M, int64_t N, int fmt,
+                      double *Xt)
+{
+    if (!codes || !scale || !Xt || M < 1 || N < 1 || (fmt != 0 && fmt != 1))
+        return -1;
+    for (int64_t n = 0; n < N; ++n)
+        for (int64_t m = 0; m < M; ++m) {
+            const double d = fmt == 0 ? (double)oracle_bf16_decode(((const uint16_t *)codes)[m + n * M])
+                                      : oracle_e4m3_decode(((const uint8_t *)codes)[m + n * M]);
+            Xt[m + n * M] = d * (double)scale[n];
+        }
+    return 0;
+}

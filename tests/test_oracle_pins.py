@@ -1,0 +1,314 @@
+"""Pins of the FP64 oracle against facts fixed by the mathematics, not by its code.
+
+Each test names the paper passage it pins (Andrecut, arXiv:0811.1081) and the
+independent fact it uses: closed forms, hand-worked fixtures, a brute-force
+Jacobi eigensolver and a library eigensolver, the power-iteration closed form
+of the projected operator, and invariants of eqs. (2), (4) and (5).
+"""
+import json
+import os
+
+import numpy as np
+import pytest
+
+from metrics import angle, col_angles, orth_err
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _constructed(M, N, s, seed):
+    rng = np.random.default_rng(seed)
+    U, _ = np.linalg.qr(rng.standard_normal((M, len(s))))
+    W, _ = np.linalg.qr(rng.standard_normal((N, len(s))))
+    return (U * s) @ W.T, U, W
+
+
+# --------------------------------------------------------------------------
+# Brute-force reference itself: Jacobi against closed forms and a library solver.
+
+def test_jacobi_2x2_closed_form(orc):
+    a, b, c = 2.0, 0.75, -1.25
+    w, Q = orc.jacobi_eig(np.array([[a, b], [b, c]]))
+    h = np.hypot((a - c) / 2, b)
+    assert abs(w[0] - ((a + c) / 2 + h)) <= 1e-15 * 4
+    assert abs(w[1] - ((a + c) / 2 - h)) <= 1e-15 * 4
+    assert orth_err(Q) <= 1e-15
+
+
+def test_jacobi_matches_library_eigh(orc):
+    rng = np.random.default_rng(7)
+    for n in (1, 3, 8, 13):
+        B = rng.standard_normal((n, n))
+        A = B + B.T
+        w, Q = orc.jacobi_eig(A)
+        wl = np.linalg.eigvalsh(A)[::-1]
+        assert np.abs(w - wl).max() <= 1e-13 * np.abs(wl).max()
+        assert np.abs(Q @ np.diag(w) @ Q.T - A).max() <= 1e-13 * np.abs(A).max()
+        assert orth_err(Q) <= 1e-13
+
+
+# --------------------------------------------------------------------------
+# Hand-worked fixtures (Secs. 2.2-2.3 applied by hand).
+
+def test_golden_rank1(orc):
+    g = json.load(open(os.path.join(GOLDEN, "rank1_3x2.json")))
+    X = np.array(g["X_rows"])
+    e = g["expect"]
+    for algo in ("gs", "nipals"):
+        f = orc.fit(X, g["K"], tol=g["tol"], max_iter=50, algo=algo)
+        assert f.status == orc.OK
+        assert abs(f.sigma[0] - e["sigma"][0]) <= 1e-14 * e["sigma"][0]
+        assert abs(f.lam[0] - e["lambda"][0]) <= 1e-13 * e["lambda"][0]
+        assert angle(f.P[:, 0], e["p"][0]) <= 1e-15
+        assert np.abs(np.abs(f.T[:, 0]) - np.abs(e["t"][0])).max() <= 1e-13
+        assert list(f.iters) == e["iters"]
+        assert list(f.start_col) == e["start_col"]
+
+
+@pytest.mark.parametrize("mode", ["maxnorm", "column_k"])
+def test_golden_orthogonal_columns(orc, mode):
+    g = json.load(open(os.path.join(GOLDEN, "orthocols_4x3.json")))
+    X = np.array(g["X_rows"])
+    e = g["expect_" + mode]
+    f = orc.fit(X, g["K"], tol=g["tol"], max_iter=50, init=mode, want_R=True)
+    assert f.status == orc.OK
+    np.testing.assert_allclose(f.sigma, e["sigma"], rtol=1e-15, atol=0)
+    for k, j in enumerate(e["p_index"]):
+        assert angle(f.P[:, k], np.eye(3)[:, j]) == 0.0
+        assert np.array_equal(np.abs(f.T[:, k]), np.abs(X[:, j]))
+    assert list(f.iters) == e["iters"]
+    assert list(f.start_col) == e["start_col"]
+    assert np.abs(f.R).max() == 0.0
+
+
+# --------------------------------------------------------------------------
+# Convergence to the exact decomposition (eq. 5) on constructed spectra.
+
+@pytest.mark.parametrize("shape", [(12, 8), (8, 12), (9, 9)])
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_converges_to_constructed_svd(orc, shape, algo):
+    M, N = shape
+    r = min(M, N)
+    s = 2.0 ** -np.arange(r)
+    X, U, W = _constructed(M, N, s, seed=M * 100 + N)
+    f = orc.fit(X, r, tol=0.0, max_iter=500, algo=algo)
+    assert f.status == orc.NOT_CONVERGED  # tol = 0 never stops early
+    assert np.all(f.iters == 500)
+    assert np.abs(f.lam - s ** 2).max() <= 1e-13 * s[0] ** 2
+    ang_p = col_angles(f.P, W)
+    ang_t = col_angles(f.T, U)
+    assert ang_p.max() <= 1e-10 and ang_t.max() <= 1e-10, (ang_p, ang_t)
+
+
+@pytest.mark.parametrize("seed", [0, 1, 2])
+def test_matches_jacobi_on_random_matrices(orc, seed):
+    rng = np.random.default_rng(seed)
+    M, N = 10, 6
+    X = rng.standard_normal((M, N))
+    w, Q = orc.jacobi_eig(X.T @ X)
+    f = orc.fit(X, N, tol=0.0, max_iter=20000)
+    assert np.abs(f.lam - w).max() <= 1e-12 * w[0]
+    gaps = np.r_[w[:-1] / w[1:], np.inf]
+    for k in range(N):
+        if gaps[k] > 1.05 and (k == 0 or w[k - 1] / w[k] > 1.05):
+            assert angle(f.P[:, k], Q[:, k]) <= 1e-9
+
+
+def test_stop_accuracy_within_power_iteration_bound(orc):
+    """At a relative sigma-stop tol the loading error vs the exact singular vector
+    obeys theta <~ sqrt(2 tol / ((1 - r^2)(1 - r^4))), r = s_{k+1}/s_k."""
+    M, N, r = 60, 20, 0.8
+    s = r ** np.arange(N)
+    X, U, W = _constructed(M, N, s, seed=5)
+    for tol in (1e-6, 1e-9):
+        f = orc.fit(X, 4, tol=tol, max_iter=5000)
+        bound = np.sqrt(2 * tol / ((1 - r ** 2) * (1 - r ** 4)))
+        ang = col_angles(f.P, W[:, :4])
+        assert ang.max() <= 1.5 * bound, (tol, ang, bound)
+
+
+# --------------------------------------------------------------------------
+# Power-iteration closed form: after j iterations the loading equals the
+# normalised (j-1)-th power of the projected operator applied to the first loading.
+
+@pytest.mark.parametrize("j", [1, 2, 5])
+def test_power_iteration_closed_form(orc, j):
+    rng = np.random.default_rng(11)
+    M, N = 9, 6
+    X = rng.standard_normal((M, N))
+    # component 0 after j iterations: p_j ~ (X^T X)^(j-1) X^T t0
+    f = orc.fit(X, 2, tol=0.0, max_iter=j)
+    t0 = X[:, f.start_col[0]]
+    p = np.linalg.matrix_power(X.T @ X, j - 1) @ (X.T @ t0)
+    assert angle(f.P[:, 0], p) <= 1e-13
+    assert abs(f.sigma[0] - np.linalg.norm(X @ (p / np.linalg.norm(p)))) <= 1e-13 * f.sigma[0]
+    # component 1: R1 = X - s0 v0 p0^T, projectors onto complements of p0 and v0
+    p0, v0, s0 = f.P[:, 0], f.V[:, 0], f.sigma[0]
+    R1 = X - s0 * np.outer(v0, p0)
+    PiP = np.eye(N) - np.outer(p0, p0)
+    PiV = np.eye(M) - np.outer(v0, v0)
+    t1 = R1[:, f.start_col[1]]
+    p1 = PiP @ (R1.T @ t1)
+    B = PiP @ R1.T @ PiV @ R1
+    p = np.linalg.matrix_power(B, j - 1) @ p1
+    assert angle(f.P[:, 1], p) <= 1e-12
+    t = PiV @ R1 @ (p / np.linalg.norm(p))
+    assert abs(f.sigma[1] - np.linalg.norm(t)) <= 1e-12 * f.sigma[1]
+    assert angle(f.V[:, 1], t) <= 1e-12
+
+
+# --------------------------------------------------------------------------
+# Invariants of eqs. (2), (4), (5).
+
+def test_invariants_small_case(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    f = orc.fit(X, 16, tol=1e-10, max_iter=1000, want_R=True)
+    assert f.status == orc.OK
+    assert orth_err(f.P) <= 1e-13
+    assert orth_err(f.V) <= 1e-13
+    G = f.T.T @ f.T
+    assert np.abs(G - np.diag(f.lam)).max() <= 1e-12 * f.lam[0]
+    assert np.allclose(np.linalg.norm(f.T, axis=0) ** 2, f.lam, rtol=1e-13)
+    # eq. (4): X = T P^T + R, and ||R_K||_F^2 = ||X||_F^2 - sum sigma^2
+    assert np.abs(f.T @ f.P.T + f.R - X).max() <= 1e-12 * np.abs(X).max()
+    lhs = np.linalg.norm(f.R) ** 2
+    rhs = np.linalg.norm(X) ** 2 - np.sum(f.lam)
+    assert abs(lhs - rhs) <= 1e-10 * np.linalg.norm(X) ** 2
+    assert np.all(np.diff(f.sigma) <= 1e-9 * f.sigma[0])
+
+
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_full_rank_reconstruction(orc, algo):
+    """Eq. (2) / Sec. 2.3: at K = N and full convergence X = T P^T and the
+    eigenvalues sum to ||X||_F^2.  (With a sigma-stop the reconstruction is only
+    as good as the loadings, ~sqrt(tol); tol = 0 runs to rounding level.)"""
+    M, N = 30, 10
+    X, _, _ = _constructed(M, N, 0.6 ** np.arange(N), seed=3)
+    f = orc.fit(X, N, tol=0.0, max_iter=400, algo=algo)
+    assert np.abs(f.T @ f.P.T - X).max() <= 1e-13 * np.abs(X).max()
+    assert abs(np.sum(f.lam) - np.linalg.norm(X) ** 2) <= 1e-13 * np.linalg.norm(X) ** 2
+
+
+def test_gs_keeps_orthogonality_before_convergence(orc):
+    """Sec. 2.3: the per-iteration re-orthogonalisation keeps loadings and scores
+    orthonormal even when the components have not converged; NIPALS (Sec. 2.2)
+    does not.  A dropped Gram-Schmidt pass fails the first assertion."""
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((40, 12))
+    g = orc.fit(X, 8, tol=0.0, max_iter=2, algo="gs")
+    n = orc.fit(X, 8, tol=0.0, max_iter=2, algo="nipals")
+    assert orth_err(g.P) <= 1e-14 and orth_err(g.V) <= 1e-14
+    # NIPALS deflation R <- R - t p^T with t = R p annihilates p exactly, so its
+    # loadings stay orthogonal; its scores do not until convergence.
+    assert orth_err(n.V) > 1e-3
+
+
+def test_collinear_full_rank_gs_vs_nipals(orc):
+    """Sec. 1 / Sec. 2.3: on collinear data NIPALS loses orthogonality of the
+    scores while GS-PCA keeps it at rounding level."""
+    from paper_0811_1081_amd import synth
+    X = synth.case_collinear_f32(M=256, N=48).astype(np.float64)
+    g = orc.fit(X, 48, tol=1e-6, max_iter=1000, algo="gs")
+    n = orc.fit(X, 48, tol=1e-6, max_iter=1000, algo="nipals")
+    assert orth_err(g.P) <= 1e-13 and orth_err(g.V) <= 1e-13
+    assert orth_err(n.V) > 1e3 * orth_err(g.V)
+
+
+# --------------------------------------------------------------------------
+# Equivalences and modes.
+
+def test_nipals_and_gs_share_first_component(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    g = orc.fit(X, 1, tol=1e-10, algo="gs")
+    n = orc.fit(X, 1, tol=1e-10, algo="nipals")
+    assert g.iters[0] == n.iters[0]
+    assert angle(g.P[:, 0], n.P[:, 0]) <= 1e-14
+    assert abs(g.sigma[0] - n.sigma[0]) <= 1e-14 * g.sigma[0]
+    assert np.abs(g.T - n.T).max() <= 1e-12 * np.abs(g.T).max()
+
+
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_implicit_equals_explicit(orc, algo):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    e = orc.fit(X, 8, tol=1e-10, algo=algo)
+    i = orc.fit(X, 8, tol=1e-10, algo=algo, implicit=True, replay_iters=e.iters,
+                replay_start=e.start_col)
+    assert col_angles(e.P, i.P).max() <= 1e-11
+    assert np.abs(e.sigma - i.sigma).max() <= 1e-12 * e.sigma[0]
+
+
+def test_replay_reproduces_bitwise(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    a = orc.fit(X, 6, tol=1e-10)
+    b = orc.fit(X, 6, tol=1e-10, replay_iters=a.iters, replay_start=a.start_col)
+    assert np.array_equal(a.T, b.T) and np.array_equal(a.P, b.P)
+
+
+def test_score_step_reproduces_final_scores(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    f = orc.fit(X, 8, tol=1e-10)
+    for k in range(8):
+        v, s = orc.score_step(X, k, f.V, f.sigma, f.P, f.P[:, k])
+        assert abs(s - f.sigma[k]) <= 1e-12 * f.sigma[0]
+        assert angle(v, f.V[:, k]) <= 1e-12
+
+
+def test_given_start_and_fallback(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    a = orc.fit(X, 3, tol=1e-10)
+    T0 = np.asfortranarray(a.T.copy())
+    T0[:, 1] = 0.0  # zero start -> falls back to the max-norm column
+    b = orc.fit(X, 3, tol=1e-10, init="given", T0=T0)
+    assert b.start_col[0] == -1 and b.start_col[2] == -1
+    assert b.start_col[1] == a.start_col[1]
+    assert b.iters[0] <= 3  # started at the converged score
+    # both stop within the sigma-test accuracy (~sqrt(tol)) of the same vectors
+    assert col_angles(a.P, b.P).max() <= 1e-4
+
+
+# --------------------------------------------------------------------------
+# Degenerate and invalid inputs.
+
+def test_zero_matrix_is_degenerate(orc):
+    X = np.zeros((5, 3))
+    f = orc.fit(X, 3, tol=1e-10)
+    assert f.status == orc.OK
+    assert np.all(f.sigma == 0) and np.all(f.T == 0) and np.all(f.iters == 0)
+    assert np.array_equal(f.P, np.eye(3))
+
+
+def test_rank_deficient_components_stay_orthonormal(orc):
+    a = np.array([1.0, 2.0, 2.0, 0.0])
+    b = np.array([3.0, 4.0, 0.0])
+    X = np.outer(a, b)
+    f = orc.fit(X, 3, tol=1e-10, max_iter=200)
+    assert abs(f.sigma[0] - 15.0) <= 1e-13 * 15
+    assert np.all(f.sigma[1:] <= 1e-13 * 15)
+    assert orth_err(f.P) <= 1e-12
+
+
+def test_nonfinite_and_invalid_rejected(orc):
+    X = np.ones((4, 3))
+    X[2, 1] = np.nan
+    assert orc.fit(X, 2).status == orc.ENONFINITE
+    X[2, 1] = np.inf
+    assert orc.fit(X, 2).status == orc.ENONFINITE
+    Y = np.ones((4, 3))
+    assert orc.fit(Y, 4).status == orc.EINVAL  # K > N
+    assert orc.fit(Y, 2, tol=-1.0).status == orc.EINVAL
+    assert orc.fit(Y, 2, max_iter=0).status == orc.EINVAL
+
+
+def test_max_iter_reports_not_converged(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.case_small_f64()
+    f = orc.fit(X, 2, tol=1e-12, max_iter=3)
+    assert f.status == orc.NOT_CONVERGED
+    assert np.all(f.iters == 3)
+    assert orth_err(f.P) <= 1e-14
