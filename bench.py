@@ -1,0 +1,160 @@
+#!/usr/bin/env python3
+"""Benchmark: GS-PCA fits of the large FP32 workload on one MI355X.
+
+One step = one complete fit (R <- X copy, K = 32 components, every iteration
+of Sec. 2.3 of Andrecut, arXiv:0811.1081, deflations, finishing) of a
+65536 x 8192 FP32 matrix with a rank-64 spectrum 100 * 0.95^i plus N(0, 1e-2)
+noise, tol 1e-6, max_iter 1000, through the C ABI, inputs resident in HBM.
+
+Prints one JSON line with whole-job throughput (components/s), the roofline
+of the dominant streaming kernel (HIP-event timed inside the timed region),
+and the FP64 CPU oracle timed on a bounded sample of the same workload.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = "GS-PCA components/s + HBM GB/s vs peak; BF16+warm-start vs FP32 at 1e-5 err"
+HBM_PEAK_GBPS = 8000.0  # MI355X HBM3E, AMD published peak
+
+
+def log(msg):
+    print("[bench] " + msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(X, mean_iters, n_short=1, n_long=6):
+    """FP64 oracle on the full input, one component with replayed iteration
+    counts n_short and n_long; per-iteration and fixed costs extrapolated to
+    the GPU's mean iterations per component."""
+    import numpy as np
+    import oracle
+    X64 = np.asfortranarray(X, dtype=np.float64)
+    times = []
+    for n in (n_short, n_long):
+        t0 = time.perf_counter()
+        oracle.fit(X64, 1, tol=0.0, max_iter=n, replay_iters=np.array([n], dtype=np.int32),
+                   tiny=oracle.FLT_MIN)
+        times.append(time.perf_counter() - t0)
+    per_iter = max((times[1] - times[0]) / (n_long - n_short), 1e-9)
+    fixed = max(times[0] - per_iter * n_short, 0.0)
+    per_comp = fixed + per_iter * mean_iters
+    return {
+        "value": 1.0 / per_comp, "unit": "components/s", "cores": 1, "kind": "oracle",
+        "sample": ("FP64 oracle GS-PCA on the full %dx%d input, 1 component with %d and %d "
+                   "replayed iterations (%.1f s and %.1f s); per-component cost = fixed %.2f s "
+                   "+ %.2f s/iteration x %.1f mean GPU iterations"
+                   % (X.shape[0], X.shape[1], n_short, n_long, times[0], times[1], fixed,
+                      per_iter, mean_iters)),
+    }
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--M", type=int, default=65536)
+    ap.add_argument("--N", type=int, default=8192)
+    ap.add_argument("--K", type=int, default=32)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--max-iter", type=int, default=1000)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
+              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+
+    gp.load()
+    M, N, K = args.M, args.N, args.K
+    log("generating %dx%d FP32 input" % (M, N))
+    t0 = time.perf_counter()
+    X = synth.case_large_f32(M, N)
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    Xd = gp.column_major(torch.from_numpy(X).to("cuda"))
+    ws_bytes = gp.workspace_bytes(Xd, K)
+    ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
+    ws_view = ws[(-ws.data_ptr()) % 256:]
+    torch.cuda.synchronize()
+
+    def step(profile=None):
+        return gp.fit(Xd, K, tol=args.tol, max_iter=args.max_iter, workspace=ws_view,
+                      profile=profile)
+
+    for i in range(args.warmup):
+        out = step()
+        torch.cuda.synchronize()
+        log("warmup %d: status %d, iters %s" % (i, out["status"], out["iters"].cpu().tolist()))
+
+    prof = gp.Profile()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    outs = []
+    for i in range(args.steps):
+        outs.append(step(prof))
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    out = outs[-1]
+    iters = out["iters"].cpu().numpy()
+    log("timed %d steps in %.3f s; status %d; iters %s" % (args.steps, elapsed, out["status"],
+                                                            iters.tolist()))
+
+    comps = K * args.steps
+    value = comps / elapsed
+    # roofline of the dominant streaming kernel: algorithmic bytes = one read of R
+    dom = "gemv_t" if prof.gemv_t_ms >= prof.gemv_n_ms else "gemv_n"
+    ms = prof.gemv_t_ms if dom == "gemv_t" else prof.gemv_n_ms
+    n_l = prof.gemv_t_launches if dom == "gemv_t" else prof.gemv_n_launches
+    avg_s = ms / max(n_l, 1) / 1e3
+    bytes_per_launch = float(prof.bytes_per_pass)
+    achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
+    total_iters = int(prof.iterations)
+    fit_gbps = 2.0 * total_iters * bytes_per_launch / elapsed / 1e9
+
+    P = out["P"].double()
+    V = (out["T"].double() / out["sigma"]).double()
+    eye = torch.eye(K, dtype=torch.float64, device="cuda")
+    orth_p = float((P.T @ P - eye).abs().max())
+    orth_v = float((V.T @ V - eye).abs().max())
+
+    res = {
+        "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "large_f32_lowrank_%dx%d_K%d" % (M, N, K), "M": M, "N": N,
+                   "K": K, "tol": args.tol, "max_iter": args.max_iter, "algo": "gs",
+                   "form": "plain_fp32_explicit_two_pass"},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
+                     "launches_timed": int(n_l)},
+        "iters_mean": float(iters.mean()),
+        "iterations_timed": total_iters,
+        "fit_stream_GBps": fit_gbps,
+        "gemv_t_avg_us": prof.gemv_t_ms / max(prof.gemv_t_launches, 1) * 1e3,
+        "gemv_n_avg_us": prof.gemv_n_ms / max(prof.gemv_n_launches, 1) * 1e3,
+        "orth_P": orth_p, "orth_V": orth_v,
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        log("timing the FP64 oracle on a bounded sample")
+        res["cpu_baseline"] = cpu_baseline(X, float(iters.mean()))
+    print(json.dumps(res), flush=True)
+
+
+if __name__ == "__main__":
+    main()

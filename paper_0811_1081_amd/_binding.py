@@ -1,0 +1,99 @@
+"""ctypes binding of ``libgspca.so`` (the C ABI declared in ``include/gspca.h``).
+
+Argument marshalling only: PyTorch supplies device memory and the stream,
+every step of the fit runs in the library's HIP kernels.  The binding refuses
+to run when the library is missing -- there is no fallback path.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import threading
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libgspca.so")
+
+# gspca_status
+OK, NOT_CONVERGED, EINVAL, EWORKSPACE, EDEVICE, ENONFINITE, ENOMEM = 0, 1, -1, -2, -3, -4, -5
+# gspca_dtype / gspca_algo / gspca_init
+F64, F32 = 0, 1
+GS, NIPALS = 0, 1
+INIT_MAXNORM, INIT_COLUMN_K, INIT_GIVEN = 0, 1, 2
+
+EXPORTS = (
+    "gspca_default_options", "gspca_workspace_bytes", "gspca_fit_ex", "gspca_fit",
+    "gspca_fit_f32", "gspca_status_string", "gspca_version",
+)
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dtype", ctypes.c_int32), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64)]
+
+
+class Options(ctypes.Structure):
+    _fields_ = [("algo", ctypes.c_int32), ("init", ctypes.c_int32), ("T0", ctypes.c_void_p),
+                ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
+                ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
+                ("profile", ctypes.c_void_p)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("gemv_t_ms", ctypes.c_double), ("gemv_n_ms", ctypes.c_double),
+                ("gemv_t_launches", ctypes.c_int64), ("gemv_n_launches", ctypes.c_int64),
+                ("iterations", ctypes.c_int64), ("bytes_per_pass", ctypes.c_int64)]
+
+
+class Result(ctypes.Structure):
+    _fields_ = [("T", ctypes.c_void_p), ("P", ctypes.c_void_p), ("lambda_", ctypes.c_void_p),
+                ("sigma", ctypes.c_void_p), ("iters", ctypes.c_void_p),
+                ("start_col", ctypes.c_void_p)]
+
+
+_lock = threading.Lock()
+_lib = None
+
+
+class LibraryMissing(RuntimeError):
+    pass
+
+
+def load() -> ctypes.CDLL:
+    """Load libgspca.so (torch is imported first so that one HIP runtime is used)."""
+    global _lib
+    with _lock:
+        if _lib is not None:
+            return _lib
+        if not os.path.exists(LIB_PATH):
+            raise LibraryMissing(
+                "libgspca.so is not built (%s); run `python -m paper_0811_1081_amd.build`" % LIB_PATH)
+        import torch  # noqa: F401  (loads the HIP runtime the library links against)
+        L = ctypes.CDLL(LIB_PATH)
+        vp, i64, i32, dbl = ctypes.c_void_p, ctypes.c_int64, ctypes.c_int32, ctypes.c_double
+        L.gspca_default_options.restype = None
+        L.gspca_default_options.argtypes = [ctypes.POINTER(Options)]
+        L.gspca_workspace_bytes.restype = ctypes.c_size_t
+        L.gspca_workspace_bytes.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options)]
+        L.gspca_fit_ex.restype = ctypes.c_int
+        L.gspca_fit_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                   ctypes.POINTER(Result), vp, ctypes.c_size_t, vp]
+        L.gspca_fit.restype = ctypes.c_int
+        L.gspca_fit.argtypes = [vp, i64, i64, i64, dbl, i32, vp, vp, vp, vp]
+        L.gspca_fit_f32.restype = ctypes.c_int
+        L.gspca_fit_f32.argtypes = [vp, i64, i64, i64, dbl, i32, vp, vp, vp, vp]
+        L.gspca_status_string.restype = ctypes.c_char_p
+        L.gspca_status_string.argtypes = [ctypes.c_int]
+        L.gspca_version.restype = ctypes.c_int
+        L.gspca_version.argtypes = []
+        _lib = L
+        return L
+
+
+def status_string(st: int) -> str:
+    return load().gspca_status_string(int(st)).decode()
+
+
+class GspcaError(RuntimeError):
+    def __init__(self, status: int):
+        super().__init__("gspca: %s (%d)" % (status_string(status), status))
+        self.status = status

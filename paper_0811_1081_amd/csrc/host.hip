@@ -1,0 +1,363 @@
+// host.hip -- C ABI of the iterative-PCA library: validation, workspace plan and
+// the stream-ordered launch sequence of NIPALS-PCA (Sec. 2.2) and GS-PCA
+// (Sec. 2.3) of Andrecut, arXiv:0811.1081.
+//
+// Per component k:  start vector -> iterations (six kernels each, see
+// kernels.hip) -> finish (V[:,k] = t / sigma, P[:,k] = p / |p|) -> explicit
+// deflation R <- R - t p^T fused with the column norms used by the next start.
+// The convergence test runs on the device; the host reads one small status
+// record per batch of iterations and sizes the next batch from the observed
+// geometric decay of the relative change (so the GPU is not idled by a
+// round-trip every iteration, as in the paper's programs, which read the norm
+// back twice per iteration).
+#include <float.h>
+#include <math.h>
+#include <string.h>
+
+#include <algorithm>
+#include <vector>
+
+#include "../../include/gspca.h"
+#include "internal.h"
+
+using namespace gspca;
+
+namespace {
+
+constexpr size_t kAlign = 256;
+inline size_t align_up(size_t x) { return (x + kAlign - 1) / kAlign * kAlign; }
+inline int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Launch geometry and workspace layout of one fit.
+struct Plan {
+    int64_t M, N, K, ldr;
+    int ncolblk, nsplit_t, nsplit_n, nbM, nbN;
+    int64_t rows_per_split, cols_per_split;
+    size_t off_state, off_R, off_t, off_qpart, off_tpart, off_qy, off_ty, off_cpart, off_c,
+        off_sq, off_cn, off_p, off_sig, total;
+};
+
+Plan make_plan(int64_t M, int64_t N, int64_t K, size_t esize)
+{
+    Plan pl{};
+    pl.M = M;
+    pl.N = N;
+    pl.K = K;
+    pl.ldr = cdiv(M, kRowAlign) * kRowAlign;
+    const int64_t vn = 16 / (int64_t)esize;
+    const int64_t row_unit = (int64_t)kBlock * vn;
+    const int64_t nrow_units = cdiv(pl.ldr, row_unit);
+    const int64_t target_wg = 2048; // >> 256 CUs: several resident workgroups per CU
+    // gemv_t: 8 columns per workgroup, rows split so that the grid is large
+    pl.ncolblk = (int)cdiv(N, 8);
+    int64_t ns = std::min<int64_t>(std::max<int64_t>(cdiv(target_wg, pl.ncolblk), 1), nrow_units);
+    pl.rows_per_split = cdiv(nrow_units, ns) * row_unit;
+    pl.nsplit_t = (int)cdiv(pl.ldr, pl.rows_per_split);
+    // gemv_n: 256*vn rows per workgroup, columns split
+    const int64_t nbr = nrow_units;
+    int64_t nsn = std::min<int64_t>(std::max<int64_t>(cdiv(target_wg, nbr), 1), cdiv(N, 8));
+    pl.cols_per_split = std::min<int64_t>(cdiv(N, nsn), 1024);
+    pl.nsplit_n = (int)cdiv(N, pl.cols_per_split);
+    pl.nbM = (int)cdiv(M, kBlock);
+    pl.nbN = (int)cdiv(N, kBlock);
+    const int nbmax = std::max(pl.nbM, pl.nbN);
+
+    size_t o = 0;
+    pl.off_state = o; o = align_up(o + sizeof(LoopState));
+    pl.off_R = o;     o = align_up(o + (size_t)pl.ldr * N * esize);
+    pl.off_t = o;     o = align_up(o + (size_t)pl.ldr * esize);
+    pl.off_qpart = o; o = align_up(o + (size_t)pl.nsplit_t * N * 8);
+    pl.off_tpart = o; o = align_up(o + (size_t)pl.nsplit_n * pl.ldr * 8);
+    pl.off_qy = o;    o = align_up(o + (size_t)N * 8);
+    pl.off_ty = o;    o = align_up(o + (size_t)pl.ldr * 8);
+    pl.off_cpart = o; o = align_up(o + (size_t)nbmax * (K + 1) * 8);
+    pl.off_c = o;     o = align_up(o + (size_t)(K + 1) * 8);
+    pl.off_sq = o;    o = align_up(o + (size_t)nbmax * 8);
+    pl.off_cn = o;    o = align_up(o + (size_t)N * 8);
+    pl.off_p = o;     o = align_up(o + (size_t)N * 8);
+    pl.off_sig = o;   o = align_up(o + (size_t)K * 8);
+    pl.total = o;
+    return pl;
+}
+
+size_t dtype_size(int32_t dt) { return dt == GSPCA_F64 ? 8 : dt == GSPCA_F32 ? 4 : 0; }
+
+gspca_status validate(const gspca_problem *pr, const gspca_options *op)
+{
+    if (!pr || !op)
+        return GSPCA_EINVAL;
+    if (dtype_size(pr->dtype) == 0 || !pr->X)
+        return GSPCA_EINVAL;
+    if (pr->M < 1 || pr->N < 1 || pr->K < 1 || pr->K > pr->M || pr->K > pr->N || pr->ldx < pr->M)
+        return GSPCA_EINVAL;
+    // grid-dimension limits of the launch plan (rows: 2^30, columns: 2^25)
+    if (pr->M > (int64_t(1) << 30) || pr->N > (int64_t(1) << 25))
+        return GSPCA_EINVAL;
+    if (op->algo != GSPCA_GS && op->algo != GSPCA_NIPALS)
+        return GSPCA_EINVAL;
+    if (op->init != GSPCA_INIT_MAXNORM && op->init != GSPCA_INIT_COLUMN_K &&
+        op->init != GSPCA_INIT_GIVEN)
+        return GSPCA_EINVAL;
+    if (op->init == GSPCA_INIT_GIVEN && !op->T0)
+        return GSPCA_EINVAL;
+    if (!(op->tol >= 0.0) || !isfinite(op->tol) || op->max_iter < 1)
+        return GSPCA_EINVAL;
+    return GSPCA_OK;
+}
+
+// Next batch size from the geometric decay of the relative change:
+// delta_j ~ rho^j, so the test delta < tol passes after about
+// log(tol / delta) / log(rho) more iterations.
+int next_batch(const LoopState &h, double tol, int cur)
+{
+    const double d = h.delta, dp = h.delta_prev;
+    if (!(tol > 0.0) || !(d > 0.0) || !(dp > 0.0) || !(d < dp) || h.iter < 3)
+        return std::min(cur * 2, 16);
+    if (d < tol)
+        return 1;
+    const double rho = d / dp;
+    const double rem = log(tol / d) / log(rho);
+    if (!(rem > 0.0) || !isfinite(rem))
+        return 4;
+    return (int)std::min(64.0, std::max(1.0, ceil(rem)));
+}
+
+template <typename E>
+gspca_status fit_typed(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
+                       void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t M = pr->M, N = pr->N, K = pr->K;
+    const Plan pl = make_plan(M, N, K, sizeof(E));
+    if (!ws || ws_bytes < pl.total)
+        return GSPCA_EWORKSPACE;
+    if (((uintptr_t)ws) % kAlign)
+        return GSPCA_EINVAL;
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    LoopState *st = reinterpret_cast<LoopState *>(base + pl.off_state);
+    E *R = reinterpret_cast<E *>(base + pl.off_R);
+    E *t = reinterpret_cast<E *>(base + pl.off_t);
+    double *qpart = reinterpret_cast<double *>(base + pl.off_qpart);
+    double *tpart = reinterpret_cast<double *>(base + pl.off_tpart);
+    double *qy = reinterpret_cast<double *>(base + pl.off_qy);
+    double *ty = reinterpret_cast<double *>(base + pl.off_ty);
+    double *cpart = reinterpret_cast<double *>(base + pl.off_cpart);
+    double *c = reinterpret_cast<double *>(base + pl.off_c);
+    double *sq = reinterpret_cast<double *>(base + pl.off_sq);
+    double *cn = reinterpret_cast<double *>(base + pl.off_cn);
+    double *p = reinterpret_cast<double *>(base + pl.off_p);
+    double *sig = reinterpret_cast<double *>(base + pl.off_sig);
+    E *T = static_cast<E *>(rs->T);
+    E *P = static_cast<E *>(rs->P);
+    const E *X = static_cast<const E *>(pr->X);
+    const E *T0 = static_cast<const E *>(op->T0);
+    const double tiny = sizeof(E) == 8 ? DBL_MIN : (double)FLT_MIN;
+    const int gs = op->algo == GSPCA_GS;
+    const double tol = op->tol;
+    using L = Launch<E>;
+
+    std::vector<int32_t> rit;
+    const bool replay = op->replay_iters != nullptr;
+    if (replay) {
+        rit.resize(K);
+        if (hipMemcpy(rit.data(), op->replay_iters, K * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return GSPCA_EDEVICE;
+        for (int64_t k = 0; k < K; ++k)
+            if (rit[k] < 0)
+                return GSPCA_EINVAL;
+    }
+
+    // optional event timing of the streaming kernels (see gspca_profile)
+    gspca_profile *prof = op->profile;
+    constexpr int kMaxBatch = 64;
+    std::vector<hipEvent_t> ev;
+    struct EventPool {
+        std::vector<hipEvent_t> *v;
+        ~EventPool() { for (hipEvent_t e : *v) (void)hipEventDestroy(e); }
+    } ev_guard{&ev};
+    if (prof) {
+        ev.resize(4 * kMaxBatch);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                return GSPCA_EDEVICE;
+        prof->bytes_per_pass = (int64_t)(M * N * (int64_t)sizeof(E));
+    }
+
+    LoopState h{};
+    auto read_state = [&]() -> bool {
+        if (hipMemcpyAsync(&h, st, sizeof(LoopState), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        return hipStreamSynchronize(s) == hipSuccess;
+    };
+
+    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
+        return GSPCA_EDEVICE;
+    L::copy_pad(X, pr->ldx, R, pl.ldr, M, N, st, s);
+    if (!read_state())
+        return GSPCA_EDEVICE;
+    if (h.nonfinite)
+        return GSPCA_ENONFINITE;
+    L::colnorm(R, pl.ldr, M, N, cn, s);
+
+    for (int64_t k = 0; k < K; ++k) {
+        const int32_t limit = replay ? rit[k] : op->max_iter;
+        StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, op->replay_start_col};
+        L::start(R, pl.ldr, M, N, cn, T0, a, tiny, t, st, s);
+        const int kk = gs ? (int)k : 0;
+        int32_t enq = 0;
+        int batch = 4;
+        bool have = false;
+        int32_t iter_before = 0;
+        while (enq < limit) {
+            const int n = std::min<int32_t>(std::min(batch, kMaxBatch), limit - enq);
+            for (int i = 0; i < n; ++i) {
+                if (prof)
+                    (void)hipEventRecord(ev[4 * i], s);
+                L::gemv_t(R, pl.ldr, N, t, pl.rows_per_split, pl.nsplit_t, pl.ncolblk, qpart, st, s);
+                if (prof)
+                    (void)hipEventRecord(ev[4 * i + 1], s);
+                if (kk > 0)
+                    L::gs_dot(qpart, pl.nsplit_t, N, N, P, N, kk, qy, cpart, c, st, kCntDotN, s);
+                L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, nullptr, sq, st, 0, tol,
+                            limit, replay, tiny, s);
+                if (prof)
+                    (void)hipEventRecord(ev[4 * i + 2], s);
+                L::gemv_n(R, pl.ldr, N, p, pl.cols_per_split, pl.nsplit_n, tpart, st, s);
+                if (prof)
+                    (void)hipEventRecord(ev[4 * i + 3], s);
+                if (kk > 0)
+                    L::gs_dot(tpart, pl.nsplit_n, pl.ldr, M, T, M, kk, ty, cpart, c, st, kCntDotM, s);
+                L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, t, sq, st, 1,
+                            tol, limit, replay, tiny, s);
+            }
+            enq += n;
+            if (!read_state())
+                return GSPCA_EDEVICE;
+            have = true;
+            if (prof) {
+                const int real = std::min(n, h.iter - iter_before);
+                for (int i = 0; i < real; ++i) {
+                    float a = 0.f, b = 0.f;
+                    if (hipEventElapsedTime(&a, ev[4 * i], ev[4 * i + 1]) == hipSuccess &&
+                        hipEventElapsedTime(&b, ev[4 * i + 2], ev[4 * i + 3]) == hipSuccess) {
+                        prof->gemv_t_ms += a;
+                        prof->gemv_n_ms += b;
+                        prof->gemv_t_launches += 1;
+                        prof->gemv_n_launches += 1;
+                    }
+                }
+                prof->iterations += std::max(0, h.iter - iter_before);
+                iter_before = h.iter;
+            }
+            if (h.done)
+                break;
+            batch = next_batch(h, tol, batch);
+        }
+        if (!have && !read_state())
+            return GSPCA_EDEVICE;
+        if (h.degenerate)
+            L::degenerate_p(P, N, (int)k, p, st, s);
+        L::finalize_comp(t, M, N, p, (int)k, gs, T, P, sig, rs->iters, rs->start_col, st, s);
+        if (k + 1 < K && !h.degenerate)
+            L::deflate(R, pl.ldr, M, N, t, P + k * N, cn, s);
+    }
+    L::finalize_all(T, M, (int)K, sig, rs->lambda, rs->sigma, gs, s);
+    if (!read_state())
+        return GSPCA_EDEVICE;
+    if (hipGetLastError() != hipSuccess)
+        return GSPCA_EDEVICE;
+    return h.not_converged ? GSPCA_NOT_CONVERGED : GSPCA_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void gspca_default_options(gspca_options *opt)
+{
+    if (!opt)
+        return;
+    memset(opt, 0, sizeof(*opt));
+    opt->algo = GSPCA_GS;
+    opt->init = GSPCA_INIT_MAXNORM;
+    opt->tol = 1e-7;
+    opt->max_iter = 10000;
+}
+
+size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt)
+{
+    if (validate(prob, opt) != GSPCA_OK)
+        return 0;
+    return make_plan(prob->M, prob->N, prob->K, dtype_size(prob->dtype)).total;
+}
+
+gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
+                          const gspca_result *res, void *ws, size_t ws_bytes, void *stream)
+{
+    gspca_status v = validate(prob, opt);
+    if (v != GSPCA_OK)
+        return v;
+    if (!res || !res->T || !res->P || !res->lambda)
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (prob->dtype == GSPCA_F64)
+        return fit_typed<double>(prob, opt, res, ws, ws_bytes, s);
+    return fit_typed<float>(prob, opt, res, ws, ws_bytes, s);
+}
+
+static gspca_status fit_alloc(int32_t dtype, const void *X, int64_t M, int64_t N, int64_t K,
+                              double tol, int32_t max_iter, void *T, void *P, double *lambda,
+                              void *stream)
+{
+    gspca_problem pr{dtype, X, M, M, N, K};
+    gspca_options op;
+    gspca_default_options(&op);
+    op.tol = tol;
+    op.max_iter = max_iter;
+    gspca_result rs{T, P, lambda, nullptr, nullptr, nullptr};
+    gspca_status v = validate(&pr, &op);
+    if (v != GSPCA_OK)
+        return v;
+    if (!T || !P || !lambda)
+        return GSPCA_EINVAL;
+    const size_t bytes = gspca_workspace_bytes(&pr, &op);
+    void *ws = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess)
+        return GSPCA_ENOMEM;
+    gspca_status r = gspca_fit_ex(&pr, &op, &rs, ws, bytes, stream);
+    if (hipStreamSynchronize(static_cast<hipStream_t>(stream)) != hipSuccess && r >= 0)
+        r = GSPCA_EDEVICE;
+    if (hipFree(ws) != hipSuccess && r >= 0)
+        r = GSPCA_EDEVICE;
+    return r;
+}
+
+gspca_status gspca_fit(const double *X, int64_t M, int64_t N, int64_t K, double tol,
+                       int32_t max_iter, double *T, double *P, double *lambda, void *stream)
+{
+    return fit_alloc(GSPCA_F64, X, M, N, K, tol, max_iter, T, P, lambda, stream);
+}
+
+gspca_status gspca_fit_f32(const float *X, int64_t M, int64_t N, int64_t K, double tol,
+                           int32_t max_iter, float *T, float *P, double *lambda, void *stream)
+{
+    return fit_alloc(GSPCA_F32, X, M, N, K, tol, max_iter, T, P, lambda, stream);
+}
+
+const char *gspca_status_string(int status)
+{
+    switch (status) {
+    case GSPCA_OK: return "ok";
+    case GSPCA_NOT_CONVERGED: return "not converged (max_iter reached)";
+    case GSPCA_EINVAL: return "invalid argument";
+    case GSPCA_EWORKSPACE: return "workspace too small";
+    case GSPCA_EDEVICE: return "HIP runtime error";
+    case GSPCA_ENONFINITE: return "X holds NaN or Inf";
+    case GSPCA_ENOMEM: return "device allocation failed";
+    default: return "unknown status";
+    }
+}
+
+int gspca_version(void) { return 100; }
+
+}  // extern "C"

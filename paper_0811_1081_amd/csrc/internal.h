@@ -1,0 +1,73 @@
+// internal.h -- launch interface between the host orchestration (gspca.cpp)
+// and the gfx950 kernels (kernels.hip).  Not installed; not part of the ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gspca {
+
+// Threads per workgroup of the streaming kernels (4 wave64s).
+constexpr int kBlock = 256;
+// Row padding of the internal residual copy: every column starts 256-byte
+// aligned for FP32 (512 for FP64), so 16-byte vector loads never straddle.
+constexpr int64_t kRowAlign = 64;
+
+// Per-fit loop state, resident in device memory.  Written by the kernels that
+// finish a reduction (the last workgroup to arrive), read back by the host
+// once per batch of iterations.
+struct LoopState {
+    double sigma;      // |t| after the current iteration
+    double mu;         // previous estimate (0 at the start of a component)
+    double pnorm;      // |p| after the Gram-Schmidt pass of this iteration
+    double delta;      // |sigma - mu| / sigma of the last iteration
+    double delta_prev; // the same one iteration earlier
+    int32_t iter;      // iterations done on the current component
+    int32_t done;      // the current component has stopped
+    int32_t converged; // stopped by the relative test
+    int32_t degenerate;
+    int32_t start_col;
+    int32_t nonfinite;     // X held NaN/Inf
+    int32_t not_converged; // some component ran out of iterations
+    int32_t pad;
+    uint32_t counter[8];   // arrival counters of the last-workgroup reductions
+};
+
+enum Counter { kCntDotN = 0, kCntApplyN = 1, kCntDotM = 2, kCntApplyM = 3 };
+
+struct StartArgs {
+    int32_t k;
+    int32_t init;           // gspca_init
+    int32_t force_degenerate;
+    const int32_t *replay_start; // device, nullable
+};
+
+template <typename E>
+struct Launch {
+    static void copy_pad(const E *X, int64_t ldx, E *R, int64_t ldr, int64_t M, int64_t N,
+                         LoopState *st, hipStream_t s);
+    static void colnorm(const E *R, int64_t ldr, int64_t M, int64_t N, double *cn, hipStream_t s);
+    static void start(const E *R, int64_t ldr, int64_t M, int64_t N, const double *cn,
+                      const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s);
+    static void gemv_t(const E *R, int64_t ldr, int64_t N, const E *t, int64_t rows_per_split,
+                       int nsplit, int ncolblk, double *qpart, const LoopState *st, hipStream_t s);
+    static void gemv_n(const E *R, int64_t ldr, int64_t N, const double *p, int64_t cols_per_split,
+                       int nsplit, double *tpart, const LoopState *st, hipStream_t s);
+    static void gs_dot(const double *part, int nsplit, int64_t ldpart, int64_t L, const E *Q,
+                       int64_t ldq, int k, double *y, double *cpart, double *c, LoopState *st,
+                       int counter, hipStream_t s);
+    static void gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
+                         const double *y, const E *Q, int64_t ldq, int k, const double *c,
+                         double *ydst, E *edst, double *sqpart, LoopState *st, int side,
+                         double tol, int32_t limit, int replay, double tiny, hipStream_t s);
+    static void degenerate_p(const E *P, int64_t N, int k, double *p, LoopState *st, hipStream_t s);
+    static void finalize_comp(const E *t, int64_t M, int64_t N, const double *p, int k, int gs,
+                              E *T, E *P, double *sigma, int32_t *iters, int32_t *start_col,
+                              LoopState *st, hipStream_t s);
+    static void deflate(E *R, int64_t ldr, int64_t M, int64_t N, const E *t, const E *pk,
+                        double *cn, hipStream_t s);
+    static void finalize_all(E *T, int64_t M, int K, const double *sigma, double *lambda,
+                             double *sigma_out, int gs, hipStream_t s);
+};
+
+}  // namespace gspca

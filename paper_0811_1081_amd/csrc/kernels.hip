@@ -1,0 +1,693 @@
+// kernels.hip -- gfx950 kernels of the GS-PCA / NIPALS-PCA power iteration.
+//
+// Each iteration of Sec. 2.3 (GS-PCA) maps to six launches:
+//   gemv_t   q = R^T t              streaming R, split-row partial sums
+//   gs_dot   c = P_(k)^T q          (FP64; skipped for k = 0 and for NIPALS)
+//   gs_apply p = q - P_(k) c, |p|   (FP64; last workgroup finishes |p|)
+//   gemv_n   t = R p / |p|          streaming R, split-column partial sums
+//   gs_dot   d = V_(k)^T t          (FP64)
+//   gs_apply t = t - V_(k) d, sigma = |t|, relative test (last workgroup)
+// The score is kept unnormalised during the iteration: the next loading is
+// normalised after the Gram-Schmidt pass, so the scale 1/sigma of Sec. 2.3's
+// V <- V / lambda cancels and is applied once, when the component finishes.
+//
+// Reductions are deterministic: partials are written to workspace and summed
+// in a fixed order; no floating-point atomics.  Every kernel of the loop
+// returns at once when the current component has already stopped, so the
+// host may enqueue iterations ahead of the convergence test.
+#include <float.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace gspca {
+
+// 16-byte native vectors (one global_load_dwordx4 per lane).
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+typedef double f64x2 __attribute__((ext_vector_type(2)));
+
+template <typename E> struct V16;
+template <> struct V16<float> { using T = f32x4; static constexpr int n = 4; };
+template <> struct V16<double> { using T = f64x2; static constexpr int n = 2; };
+
+__device__ inline float vdot(f32x4 a, f32x4 b) { return a[0] * b[0] + a[1] * b[1] + a[2] * b[2] + a[3] * b[3]; }
+__device__ inline double vdot(f64x2 a, f64x2 b) { return a[0] * b[0] + a[1] * b[1]; }
+
+template <typename T>
+__device__ inline T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Sum over a 256-thread workgroup; every thread gets the result.
+template <typename T>
+__device__ inline T block_sum(T v, T *lds4)
+{
+    v = wave_sum(v);
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    __syncthreads();
+    if (lane == 0)
+        lds4[w] = v;
+    __syncthreads();
+    T r = T(0);
+    for (int i = 0; i < kBlock / 64; ++i)
+        r += lds4[i];
+    return r;
+}
+
+// Last-arriving workgroup detection.  Each workgroup has written its partial
+// results before calling; the fence publishes them device-wide (all XCDs),
+// the counter elects the final workgroup, which resets it for the next use.
+__device__ inline bool arrive_last(uint32_t *counter, int *flag_lds)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(counter, 1u);
+        *flag_lds = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+// R <- X (Sec. 2.2/2.3 first step) into the padded layout; flags NaN/Inf.
+
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_copy_pad(const E *__restrict__ X, int64_t ldx,
+                                                     E *__restrict__ R, int64_t ldr, int64_t M,
+                                                     int64_t N, LoopState *st)
+{
+    int bad = 0;
+    for (int64_t n = blockIdx.y; n < N; n += gridDim.y) {
+        const E *x = X + n * ldx;
+        E *r = R + n * ldr;
+        for (int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x; m < ldr;
+             m += (int64_t)gridDim.x * kBlock) {
+            const E v = m < M ? x[m] : E(0);
+            bad |= !isfinite(v);
+            r[m] = v;
+        }
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0)
+        atomicOr(&st->nonfinite, 1);
+}
+
+// Squared column norms in FP64: one wave per column.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_colnorm(const E *__restrict__ R, int64_t ldr,
+                                                    int64_t M, int64_t N, double *cn)
+{
+    using VT = typename V16<E>::T;
+    constexpr int VN = V16<E>::n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int64_t n = (int64_t)blockIdx.x * 4 + w; n < N; n += (int64_t)gridDim.x * 4) {
+        const E *col = R + n * ldr;
+        double s = 0.0;
+        for (int64_t m = (int64_t)lane * VN; m < ldr; m += 64 * VN) {
+            const VT v = *reinterpret_cast<const VT *>(col + m);
+            const E *e = reinterpret_cast<const E *>(&v);
+#pragma unroll
+            for (int i = 0; i < VN; ++i)
+                s += (double)e[i] * (double)e[i];
+        }
+        s = wave_sum(s);
+        if (lane == 0)
+            cn[n] = s;
+    }
+}
+
+// Start vector (the pseudo-code's T^(k) <- R^(k)); one 1024-thread workgroup.
+template <typename E>
+__global__ __launch_bounds__(1024) void k_start(const E *__restrict__ R, int64_t ldr, int64_t M,
+                                                int64_t N, const double *__restrict__ cn,
+                                                const E *__restrict__ T0, StartArgs a,
+                                                double tiny, E *__restrict__ t, LoopState *st)
+{
+    __shared__ double sv[16];
+    __shared__ int64_t si[16];
+    __shared__ int64_t col_sel;
+    __shared__ int use_given, degenerate;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+
+    if (tid == 0) {
+        col_sel = -2; // -2: undecided, -1: given vector
+        use_given = 0;
+        degenerate = a.force_degenerate;
+        if (a.replay_start && a.replay_start[a.k] >= 0 && a.replay_start[a.k] < N) {
+            col_sel = a.replay_start[a.k];
+        } else if (a.init == 1) { // column k
+            if (sqrt(cn[a.k]) >= tiny)
+                col_sel = a.k;
+        } else if (a.init == 2) {
+            use_given = 1;
+        }
+    }
+    __syncthreads();
+    if (use_given) {
+        // norm of the given start; fall back to the max-norm column if tiny or not finite
+        double s = 0.0;
+        const E *g = T0 + (int64_t)a.k * M;
+        for (int64_t m = tid; m < M; m += 1024)
+            s += (double)g[m] * (double)g[m];
+        s = wave_sum(s);
+        if (lane == 0)
+            sv[w] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int i = 0; i < 16; ++i)
+                tot += sv[i];
+            const double nrm = sqrt(tot);
+            if (nrm >= tiny && isfinite(nrm))
+                col_sel = -1;
+        }
+        __syncthreads();
+    }
+    if (col_sel == -2) {
+        // argmax of the column norms, ties to the lowest index
+        double best = -1.0;
+        int64_t bi = 0;
+        for (int64_t n = tid; n < N; n += 1024) {
+            const double v = cn[n];
+            if (v > best) { best = v; bi = n; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(best, o, 64);
+            const int64_t oi = __shfl_xor(bi, o, 64);
+            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if (lane == 0) { sv[w] = best; si[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = sv[0];
+            int64_t i0 = si[0];
+            for (int i = 1; i < 16; ++i)
+                if (sv[i] > b || (sv[i] == b && si[i] < i0)) { b = sv[i]; i0 = si[i]; }
+            col_sel = i0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && col_sel >= 0 && !(sqrt(cn[col_sel]) >= tiny))
+        degenerate = 1;
+    __syncthreads();
+    const int64_t c = col_sel;
+    const E *src = c >= 0 ? R + c * ldr : T0 + (int64_t)a.k * M;
+    for (int64_t m = tid; m < ldr; m += 1024)
+        t[m] = m < M ? src[m] : E(0);
+    if (tid == 0) {
+        st->start_col = (int32_t)c;
+        st->iter = 0;
+        st->mu = 0.0;
+        st->sigma = 0.0;
+        st->pnorm = 1.0;
+        st->delta = 1.0;
+        st->delta_prev = 1.0;
+        st->converged = 0;
+        st->degenerate = degenerate;
+        st->done = degenerate;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// q_part[s][n] = sum over rows of split s of R[m, n] t[m]   (p <- R^T t).
+// Workgroup: CB columns x one row split; 16-byte loads along each column,
+// the t chunk loaded once per row step and reused across the CB columns.
+
+template <typename E, int CB>
+__global__ __launch_bounds__(kBlock) void k_gemv_t(const E *__restrict__ R, int64_t ldr, int64_t N,
+                                                   const E *__restrict__ t, int64_t rows_per_split,
+                                                   double *__restrict__ qpart,
+                                                   const LoopState *__restrict__ st)
+{
+    if (st->done)
+        return;
+    using VT = typename V16<E>::T;
+    constexpr int VN = V16<E>::n;
+    __shared__ E lds[kBlock / 64][CB];
+    const int64_t n0 = (int64_t)blockIdx.x * CB;
+    const int64_t r0 = (int64_t)blockIdx.y * rows_per_split;
+    const int64_t r1 = min(r0 + rows_per_split, ldr);
+    const E *cols[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        cols[c] = R + min(n0 + c, N - 1) * ldr;
+    E acc[CB];
+#pragma unroll
+    for (int c = 0; c < CB; ++c)
+        acc[c] = E(0);
+    for (int64_t m = r0 + (int64_t)threadIdx.x * VN; m < r1; m += kBlock * VN) {
+        const VT tv = *reinterpret_cast<const VT *>(t + m);
+        VT rv[CB];
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            rv[c] = __builtin_nontemporal_load(reinterpret_cast<const VT *>(cols[c] + m));
+#pragma unroll
+        for (int c = 0; c < CB; ++c)
+            acc[c] += vdot(rv[c], tv);
+    }
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+        const E v = wave_sum(acc[c]);
+        if (lane == 0)
+            lds[w][c] = v;
+    }
+    __syncthreads();
+    if (threadIdx.x < CB && n0 + threadIdx.x < N) {
+        double s = 0.0;
+        for (int i = 0; i < kBlock / 64; ++i)
+            s += (double)lds[i][threadIdx.x];
+        qpart[(int64_t)blockIdx.y * N + n0 + threadIdx.x] = s;
+    }
+}
+
+// t_part[s][m] = sum over columns of split s of R[m, n] p[n] / |p|   (t <- R p).
+// Thread: VN consecutive rows; workgroup: 256*VN rows x one column split.
+
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_gemv_n(const E *__restrict__ R, int64_t ldr, int64_t N,
+                                                   const double *__restrict__ p,
+                                                   int64_t cols_per_split,
+                                                   double *__restrict__ tpart,
+                                                   const LoopState *__restrict__ st)
+{
+    if (st->done)
+        return;
+    using VT = typename V16<E>::T;
+    constexpr int VN = V16<E>::n;
+    extern __shared__ unsigned char smem[];
+    E *pl = reinterpret_cast<E *>(smem);
+    const int64_t c0 = (int64_t)blockIdx.y * cols_per_split;
+    const int64_t c1 = min(c0 + cols_per_split, N);
+    const double pn = st->pnorm;
+    for (int64_t c = c0 + threadIdx.x; c < c1; c += kBlock)
+        pl[c - c0] = (E)(p[c] / pn);
+    __syncthreads();
+    const int64_t m = ((int64_t)blockIdx.x * kBlock + threadIdx.x) * VN;
+    if (m >= ldr)
+        return;
+    E acc[VN];
+#pragma unroll
+    for (int i = 0; i < VN; ++i)
+        acc[i] = E(0);
+    const E *base = R + m;
+    int64_t c = c0;
+    for (; c + 8 <= c1; c += 8) {
+        VT rv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            rv[u] = __builtin_nontemporal_load(reinterpret_cast<const VT *>(base + (c + u) * ldr));
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const E pv = pl[c + u - c0];
+            const E *e = reinterpret_cast<const E *>(&rv[u]);
+#pragma unroll
+            for (int i = 0; i < VN; ++i)
+                acc[i] += e[i] * pv;
+        }
+    }
+    for (; c < c1; ++c) {
+        const VT rv = *reinterpret_cast<const VT *>(base + c * ldr);
+        const E pv = pl[c - c0];
+        const E *e = reinterpret_cast<const E *>(&rv);
+#pragma unroll
+        for (int i = 0; i < VN; ++i)
+            acc[i] += e[i] * pv;
+    }
+    double *dst = tpart + (int64_t)blockIdx.y * ldr + m;
+#pragma unroll
+    for (int i = 0; i < VN; ++i)
+        dst[i] = (double)acc[i];
+}
+
+// ---------------------------------------------------------------------------
+// Gram-Schmidt, FP64.  y = sum_s part[s] (the matvec result), c = Q^T y over
+// the first k columns of Q (Sec. 2.3: A <- U_(k)^T U, B <- V_(k)^T V).
+// Workgroup b covers rows [256 b, 256 b + 256); its per-column partial dot
+// products go to cpart[b][i]; the last workgroup sums them in block order.
+
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ part, int nsplit,
+                                                   int64_t ldpart, int64_t L,
+                                                   const E *__restrict__ Q, int64_t ldq, int k,
+                                                   double *__restrict__ y,
+                                                   double *__restrict__ cpart,
+                                                   double *__restrict__ c, LoopState *st,
+                                                   int counter)
+{
+    if (st->done)
+        return;
+    __shared__ double ys[kBlock];
+    __shared__ int last;
+    const int64_t r0 = (int64_t)blockIdx.x * kBlock;
+    const int64_t r = r0 + threadIdx.x;
+    double v = 0.0;
+    if (r < L) {
+        for (int s = 0; s < nsplit; ++s)
+            v += part[(int64_t)s * ldpart + r];
+        y[r] = v;
+    }
+    ys[threadIdx.x] = v;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = w; i < k; i += kBlock / 64) {
+        const E *q = Q + (int64_t)i * ldq;
+        double s = 0.0;
+        for (int j = lane; j < kBlock; j += 64)
+            if (r0 + j < L)
+                s += (double)q[r0 + j] * ys[j];
+        s = wave_sum(s);
+        if (lane == 0)
+            cpart[(int64_t)blockIdx.x * k + i] = s;
+    }
+    if (!arrive_last(&st->counter[counter], &last))
+        return;
+    for (int i = threadIdx.x; i < k; i += kBlock) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b)
+            s += cpart[(int64_t)b * k + i];
+        c[i] = s;
+    }
+    if (threadIdx.x == 0)
+        st->counter[counter] = 0;
+}
+
+// x = y - Q c (one classical Gram-Schmidt pass), squared norm; the last
+// workgroup finishes the norm.  side 0 (loading): x kept in FP64 (ydst) and
+// |p| stored.  side 1 (score): x stored in the element type (edst), sigma,
+// the relative convergence test of the host programs (Appendices 1, 3) or
+// the replay count, and the loop state update.
+
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ part, int nsplit,
+                                                     int64_t ldpart, int64_t L,
+                                                     const double *__restrict__ y,
+                                                     const E *__restrict__ Q, int64_t ldq, int k,
+                                                     const double *__restrict__ c,
+                                                     double *__restrict__ ydst,
+                                                     E *__restrict__ edst,
+                                                     double *__restrict__ sqpart, LoopState *st,
+                                                     int side, double tol, int32_t limit,
+                                                     int replay, double tiny)
+{
+    if (st->done)
+        return;
+    __shared__ double cs[1024];
+    __shared__ double red[kBlock / 64];
+    __shared__ int last;
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double v = 0.0;
+    if (r < L) {
+        if (k > 0) {
+            v = y[r];
+        } else {
+            for (int s = 0; s < nsplit; ++s)
+                v += part[(int64_t)s * ldpart + r];
+        }
+    }
+    double proj = 0.0;
+    for (int i0 = 0; i0 < k; i0 += 1024) {
+        const int n = min(1024, k - i0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kBlock)
+            cs[i] = c[i0 + i];
+        __syncthreads();
+        if (r < L)
+            for (int i = 0; i < n; ++i)
+                proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
+    }
+    v -= proj;
+    if (r < L) {
+        if (side == 0)
+            ydst[r] = v;
+        else
+            edst[r] = (E)v;
+    }
+    const double sq = block_sum(r < L ? v * v : 0.0, red);
+    if (threadIdx.x == 0)
+        sqpart[blockIdx.x] = sq;
+    if (!arrive_last(&st->counter[side == 0 ? kCntApplyN : kCntApplyM], &last))
+        return;
+    double tot = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+        tot += sqpart[b];
+    // fixed-order final sum: per-thread strided partials, then the block tree
+    tot = block_sum(tot, red);
+    if (threadIdx.x != 0)
+        return;
+    st->counter[side == 0 ? kCntApplyN : kCntApplyM] = 0;
+    const double nrm = sqrt(tot);
+    if (side == 0) {
+        st->pnorm = nrm;
+        if (!(nrm >= tiny)) { // counts as the iteration in which it happened
+            st->iter = st->iter + 1;
+            st->degenerate = 1;
+            st->done = 1;
+        }
+        return;
+    }
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->sigma = nrm;
+    if (!(nrm >= tiny)) {
+        st->degenerate = 1;
+        st->done = 1;
+        return;
+    }
+    const double mu = st->mu;
+    st->delta_prev = st->delta;
+    st->delta = fabs(nrm - mu) / nrm;
+    if (replay) {
+        if (it >= limit)
+            st->done = 1;
+        return;
+    }
+    if (fabs(mu - nrm) < tol * nrm) {
+        st->converged = 1;
+        st->done = 1;
+        return;
+    }
+    st->mu = nrm;
+    if (it >= limit) {
+        st->done = 1;
+        st->not_converged = 1;
+    }
+}
+
+// Degenerate component: the first unit vector whose Gram-Schmidt residual
+// against P_(k) has squared norm >= (N-k)/(2N), normalised, into p (FP64).
+// Rare path: one workgroup, candidates tried in ascending order.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_degenerate_p(const E *__restrict__ P, int64_t N, int k,
+                                                         double *__restrict__ p, LoopState *st)
+{
+    __shared__ double red[kBlock / 64];
+    const double thresh = (double)(N - k) / (2.0 * (double)N);
+    for (int64_t i = 0; i < N; ++i) {
+        // r = e_i - P c with c = P^T e_i = P[i, :k]
+        double sq = 0.0;
+        for (int64_t n = threadIdx.x; n < N; n += kBlock) {
+            double s = 0.0;
+            for (int j = 0; j < k; ++j)
+                s += (double)P[n + (int64_t)j * N] * (double)P[i + (int64_t)j * N];
+            const double rv = (n == i ? 1.0 : 0.0) - s;
+            p[n] = rv;
+            sq += rv * rv;
+        }
+        sq = block_sum(sq, red);
+        if (sq >= thresh) {
+            if (threadIdx.x == 0)
+                st->pnorm = sqrt(sq);
+            return;
+        }
+    }
+}
+
+// Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
+// P[:,k] = p / |p|; degenerate components get t = 0, sigma = 0.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_finalize_comp(const E *__restrict__ t, int64_t M,
+                                                          int64_t N, const double *__restrict__ p,
+                                                          int k, int gs, E *__restrict__ T,
+                                                          E *__restrict__ P, double *sigma,
+                                                          int32_t *iters, int32_t *start_col,
+                                                          LoopState *st)
+{
+    const int deg = st->degenerate;
+    const double s = st->sigma, pn = st->pnorm;
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < M)
+        T[i + (int64_t)k * M] = deg ? E(0) : (gs ? (E)((double)t[i] / s) : t[i]);
+    if (i < N)
+        P[i + (int64_t)k * N] = (E)(p[i] / pn);
+    if (i == 0) {
+        sigma[k] = deg ? 0.0 : s;
+        if (iters)
+            iters[k] = st->iter;
+        if (start_col)
+            start_col[k] = st->start_col;
+    }
+}
+
+// Explicit deflation R <- R - t p^T (eq. 3; Sec. 2.3 with t = lambda_k v) and the
+// squared column norms of the new residual.  One wave per column.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_deflate(E *__restrict__ R, int64_t ldr, int64_t M,
+                                                    int64_t N, const E *__restrict__ t,
+                                                    const E *__restrict__ pk, double *cn)
+{
+    using VT = typename V16<E>::T;
+    constexpr int VN = V16<E>::n;
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    const int64_t n = (int64_t)blockIdx.x * 4 + w;
+    if (n >= N)
+        return;
+    const E pn = pk[n];
+    E *col = R + n * ldr;
+    double s = 0.0;
+    for (int64_t m = (int64_t)lane * VN; m < ldr; m += 64 * VN) {
+        VT rv = *reinterpret_cast<const VT *>(col + m);
+        const VT tv = *reinterpret_cast<const VT *>(t + m);
+        E *re = reinterpret_cast<E *>(&rv);
+        const E *te = reinterpret_cast<const E *>(&tv);
+#pragma unroll
+        for (int i = 0; i < VN; ++i) {
+            re[i] = re[i] - te[i] * pn;
+            s += (double)re[i] * (double)re[i];
+        }
+        *reinterpret_cast<VT *>(col + m) = rv;
+    }
+    s = wave_sum(s);
+    if (lane == 0)
+        cn[n] = s;
+}
+
+// T <- V Lambda (GS) and lambda = sigma^2.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_finalize_all(E *__restrict__ T, int64_t M, int K,
+                                                         const double *__restrict__ sigma,
+                                                         double *lambda, double *sigma_out, int gs)
+{
+    for (int k = blockIdx.y; k < K; k += gridDim.y) {
+        const double s = sigma[k];
+        if (gs)
+            for (int64_t m = (int64_t)blockIdx.x * kBlock + threadIdx.x; m < M;
+                 m += (int64_t)gridDim.x * kBlock)
+                T[m + (int64_t)k * M] = (E)((double)T[m + (int64_t)k * M] * s);
+        if (blockIdx.x == 0 && threadIdx.x == 0) {
+            lambda[k] = s * s;
+            if (sigma_out)
+                sigma_out[k] = s;
+        }
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static inline unsigned ceil_div(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+static inline int64_t hmin(int64_t a, int64_t b) { return a < b ? a : b; }
+
+template <typename E>
+void Launch<E>::copy_pad(const E *X, int64_t ldx, E *R, int64_t ldr, int64_t M, int64_t N,
+                         LoopState *st, hipStream_t s)
+{
+    dim3 g(hmin(ceil_div(ldr, kBlock), 64), (unsigned)hmin(N, 4096));
+    hipLaunchKernelGGL(k_copy_pad<E>, g, dim3(kBlock), 0, s, X, ldx, R, ldr, M, N, st);
+}
+
+template <typename E>
+void Launch<E>::colnorm(const E *R, int64_t ldr, int64_t M, int64_t N, double *cn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colnorm<E>, dim3(hmin(ceil_div(N, 4), 65535)), dim3(kBlock), 0, s,
+                       R, ldr, M, N, cn);
+}
+
+template <typename E>
+void Launch<E>::start(const E *R, int64_t ldr, int64_t M, int64_t N, const double *cn,
+                      const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_start<E>, dim3(1), dim3(1024), 0, s, R, ldr, M, N, cn, T0, a, tiny, t, st);
+}
+
+template <typename E>
+void Launch<E>::gemv_t(const E *R, int64_t ldr, int64_t N, const E *t, int64_t rows_per_split,
+                       int nsplit, int ncolblk, double *qpart, const LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL((k_gemv_t<E, 8>), dim3(ncolblk, nsplit), dim3(kBlock), 0, s, R, ldr, N, t,
+                       rows_per_split, qpart, st);
+}
+
+template <typename E>
+void Launch<E>::gemv_n(const E *R, int64_t ldr, int64_t N, const double *p, int64_t cols_per_split,
+                       int nsplit, double *tpart, const LoopState *st, hipStream_t s)
+{
+    constexpr int VN = V16<E>::n;
+    dim3 g(ceil_div(ldr, (int64_t)kBlock * VN), nsplit);
+    hipLaunchKernelGGL(k_gemv_n<E>, g, dim3(kBlock), cols_per_split * sizeof(E), s, R, ldr, N, p,
+                       cols_per_split, tpart, st);
+}
+
+template <typename E>
+void Launch<E>::gs_dot(const double *part, int nsplit, int64_t ldpart, int64_t L, const E *Q,
+                       int64_t ldq, int k, double *y, double *cpart, double *c, LoopState *st,
+                       int counter, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gs_dot<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, part, nsplit,
+                       ldpart, L, Q, ldq, k, y, cpart, c, st, counter);
+}
+
+template <typename E>
+void Launch<E>::gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
+                         const double *y, const E *Q, int64_t ldq, int k, const double *c,
+                         double *ydst, E *edst, double *sqpart, LoopState *st, int side,
+                         double tol, int32_t limit, int replay, double tiny, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gs_apply<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, part, nsplit,
+                       ldpart, L, y, Q, ldq, k, c, ydst, edst, sqpart, st, side, tol, limit,
+                       replay, tiny);
+}
+
+template <typename E>
+void Launch<E>::degenerate_p(const E *P, int64_t N, int k, double *p, LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_degenerate_p<E>, dim3(1), dim3(kBlock), 0, s, P, N, k, p, st);
+}
+
+template <typename E>
+void Launch<E>::finalize_comp(const E *t, int64_t M, int64_t N, const double *p, int k, int gs,
+                              E *T, E *P, double *sigma, int32_t *iters, int32_t *start_col,
+                              LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_finalize_comp<E>, dim3(ceil_div(M > N ? M : N, kBlock)), dim3(kBlock), 0,
+                       s, t, M, N, p, k, gs, T, P, sigma, iters, start_col, st);
+}
+
+template <typename E>
+void Launch<E>::deflate(E *R, int64_t ldr, int64_t M, int64_t N, const E *t, const E *pk,
+                        double *cn, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_deflate<E>, dim3(ceil_div(N, 4)), dim3(kBlock), 0, s, R, ldr, M, N, t, pk,
+                       cn);
+}
+
+template <typename E>
+void Launch<E>::finalize_all(E *T, int64_t M, int K, const double *sigma, double *lambda,
+                             double *sigma_out, int gs, hipStream_t s)
+{
+    dim3 g(hmin(ceil_div(M, kBlock), 256), hmin(K, 65535));
+    hipLaunchKernelGGL(k_finalize_all<E>, g, dim3(kBlock), 0, s, T, M, K, sigma, lambda,
+                       sigma_out, gs);
+}
+
+template struct Launch<float>;
+template struct Launch<double>;
+
+}  // namespace gspca

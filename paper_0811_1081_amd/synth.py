@@ -58,28 +58,29 @@ def lowrank_gaussian(M: int = 512, N: int = 128, rank: int = 32, noise: float = 
 
 
 def haar_spectrum(M: int, N: int, s: np.ndarray, noise: float, seed: tuple,
-                  centre: bool = False, dtype=np.float64, block_rows: int = 4096,
+                  centre: bool = False, dtype=np.float64, block_cols: int = 256,
                   return_factors: bool = False):
     """X = U diag(s) V^T + noise*E with Haar U (M x r), V (N x r), r = len(s).
 
-    Draw order: U, V, then the noise row block by row block (``block_rows`` rows
-    at a time, float32 draws when dtype is float32 so that the large case stays
-    cheap to generate).  The product is formed in float64 and rounded once to
-    ``dtype`` (round-to-nearest-even)."""
+    Draw order: U, V, then the noise column block by column block
+    (``block_cols`` columns at a time, each block drawn as a (cols, M) array so
+    that it fills whole columns; float32 draws when dtype is float32 so that
+    the large case stays cheap to generate).  The product is formed in float64
+    and rounded once to ``dtype`` (round-to-nearest-even)."""
     s = np.asarray(s, dtype=np.float64)
     r = len(s)
     rng = rng_for(*seed)
     U = haar(rng, M, r)
     V = haar(rng, N, r)
     X = np.empty((M, N), dtype=dtype, order="F")
-    Vs = (V * s).T  # r x N
+    Vs = V * s  # N x r
     ndt = np.float32 if dtype == np.float32 else np.float64
-    for r0 in range(0, M, block_rows):
-        r1 = min(M, r0 + block_rows)
-        blk = U[r0:r1] @ Vs
+    for c0 in range(0, N, block_cols):
+        c1 = min(N, c0 + block_cols)
+        blk = Vs[c0:c1] @ U.T  # (cols, M): row j is column c0 + j of X
         if noise > 0:
-            blk += noise * rng.standard_normal((r1 - r0, N), dtype=ndt)
-        X[r0:r1, :] = blk
+            blk += noise * rng.standard_normal((c1 - c0, M), dtype=ndt)
+        X[:, c0:c1] = blk.T
     if centre:
         mu = X.mean(axis=0, dtype=np.float64, keepdims=True)
         X -= mu.astype(dtype)
