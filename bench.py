@@ -67,6 +67,9 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
+                         "counters of a profiler run against a kernel of known traffic)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
@@ -89,6 +92,13 @@ def main():
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
     ws_view = ws[(-ws.data_ptr()) % 256:]
     torch.cuda.synchronize()
+    if args.calib_copy:
+        a = torch.empty(1 << 28, dtype=torch.float32, device="cuda").fill_(1.0)
+        b = torch.empty_like(a)
+        torch.cuda.synchronize()
+        b.copy_(a)  # reads 1 GiB, writes 1 GiB
+        torch.cuda.synchronize()
+        del a, b
 
     def step(profile=None):
         return gp.fit(Xd, K, tol=args.tol, max_iter=args.max_iter, workspace=ws_view,
