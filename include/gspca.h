@@ -72,12 +72,16 @@ typedef enum {
  * bracketed by HIP events on the fit's stream; launches enqueued past a
  * component's stop are not counted.  Adds a few microseconds per launch. */
 typedef struct {
-    double gemv_t_ms;       /* summed duration of p <- R^T t launches          */
-    double gemv_n_ms;       /* summed duration of t <- R p launches            */
+    double pass_ms;         /* single-pass path: summed duration of the fused  */
+    int64_t pass_launches;  /*   t <- R p, q <- R^T t launches                 */
+    double gemv_t_ms;       /* two-pass path: p <- R^T t launches              */
+    double gemv_n_ms;       /* two-pass path: t <- R p launches                */
     int64_t gemv_t_launches;
     int64_t gemv_n_launches;
     int64_t iterations;     /* iterations run, summed over components          */
-    int64_t bytes_per_pass; /* bytes of R one streaming launch reads           */
+    int64_t bytes_per_pass; /* algorithmic bytes of one read of the data, M*N*size */
+    int32_t single_pass;    /* 1 when the single-pass path ran                 */
+    int32_t reserved;
 } gspca_profile;
 
 /* The data.  X is read, never written. */
@@ -91,6 +95,11 @@ typedef struct {
 typedef struct {
     int32_t algo;       /* gspca_algo                                          */
     int32_t init;       /* gspca_init                                          */
+    /* 0: explicit deflation R <- R - t p^T after each component (Secs. 2.2-2.3).
+     * 1: implicit: R = X - T P^T is never formed; the products use X on
+     *    Gram-Schmidt-projected vectors, for which the T P^T terms vanish in
+     *    exact arithmetic (GS-PCA only, N <= 8192). */
+    int32_t implicit_deflation;
     const void *T0;     /* M x K start scores (GIVEN only), dtype of X         */
     double tol;         /* >= 0; 0 runs exactly max_iter iterations            */
     int32_t max_iter;   /* >= 1: number of (R^T t, R p) product pairs          */

@@ -57,10 +57,12 @@ def _problem(X, K):
     return _b.Problem(_dtype_code(X), X.data_ptr(), X.stride(1), M, N, int(K))
 
 
-def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start=None):
+def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start=None,
+             implicit=False):
     o = _b.Options()
     o.algo = _ALGOS[algo]
     o.init = _INITS[init]
+    o.implicit_deflation = 1 if implicit else 0
     o.T0 = T0.data_ptr() if T0 is not None else None
     o.tol = float(tol)
     o.max_iter = int(max_iter)
@@ -69,10 +71,11 @@ def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start
     return o
 
 
-def workspace_bytes(X, K, algo="gs", init="maxnorm", tol=1e-7, max_iter=10000) -> int:
+def workspace_bytes(X, K, algo="gs", init="maxnorm", tol=1e-7, max_iter=10000,
+                    implicit=False) -> int:
     L = _b.load()
     pr = _problem(X, K)
-    op = _options(algo, init, tol, max_iter)
+    op = _options(algo, init, tol, max_iter, implicit=implicit)
     return int(L.gspca_workspace_bytes(pr, op))
 
 
@@ -85,14 +88,15 @@ def _workspace(nbytes, device):
 
 def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         replay_iters=None, replay_start=None, workspace=None, stream=None, check=True,
-        profile=None):
+        profile=None, implicit=False):
     """Fit K components of the column-major device matrix X (M x N).
 
     Returns a dict of device tensors: T (M x K), P (N x K) (column-major, dtype
     of X), lambda and sigma (float64, K), iters and start_col (int32, K), and
     the integer ``status``.  ``replay_iters`` / ``replay_start`` (int32 device
     tensors of length K) force each component's iteration count and start
-    column.  Raises GspcaError on a negative status when ``check``."""
+    column.  ``implicit`` selects implicit deflation (X is never modified,
+    GS-PCA only).  Raises GspcaError on a negative status when ``check``."""
     import torch
     L = _b.load()
     if not X.is_cuda:
@@ -108,7 +112,7 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
                               or not a.is_contiguous()):
             raise ValueError(name + " must be a contiguous int32 device tensor of length K")
     pr = _problem(X, K)
-    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start)
+    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start, implicit)
     if profile is not None:
         op.profile = ctypes.addressof(profile)
     T = torch.empty_strided((M, K), (1, M), dtype=X.dtype, device=dev)

@@ -32,16 +32,19 @@ class Problem(ctypes.Structure):
 
 
 class Options(ctypes.Structure):
-    _fields_ = [("algo", ctypes.c_int32), ("init", ctypes.c_int32), ("T0", ctypes.c_void_p),
+    _fields_ = [("algo", ctypes.c_int32), ("init", ctypes.c_int32),
+                ("implicit_deflation", ctypes.c_int32), ("T0", ctypes.c_void_p),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
                 ("profile", ctypes.c_void_p)]
 
 
 class Profile(ctypes.Structure):
-    _fields_ = [("gemv_t_ms", ctypes.c_double), ("gemv_n_ms", ctypes.c_double),
+    _fields_ = [("pass_ms", ctypes.c_double), ("pass_launches", ctypes.c_int64),
+                ("gemv_t_ms", ctypes.c_double), ("gemv_n_ms", ctypes.c_double),
                 ("gemv_t_launches", ctypes.c_int64), ("gemv_n_launches", ctypes.c_int64),
-                ("iterations", ctypes.c_int64), ("bytes_per_pass", ctypes.c_int64)]
+                ("iterations", ctypes.c_int64), ("bytes_per_pass", ctypes.c_int64),
+                ("single_pass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):

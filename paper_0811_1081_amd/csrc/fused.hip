@@ -1,0 +1,608 @@
+// fused.hip -- single-pass form of the power iteration (one read of the data
+// matrix per iteration) for GS-PCA / NIPALS-PCA (Andrecut, arXiv:0811.1081,
+// Secs. 2.2-2.3).
+//
+// The data matrix A (the residual R for explicit deflation, or X itself for
+// implicit deflation) is re-tiled once into row panels: panel b holds rows
+// [b*PR, b*PR + PR) with the PR values of each column contiguous (16 bytes),
+// so a wave reading 64 consecutive columns of a panel reads 1 KiB of
+// contiguous memory.  One persistent workgroup per compute unit walks a
+// contiguous range of panels and, for each panel, computes the PR entries of
+// t = A p (a workgroup reduction), then immediately adds the panel's
+// contribution A_b^T t_b to its private copy of q = A^T t, using the panel
+// values still in registers.  The next panel is loaded while the current one
+// is reduced.  The Gram-Schmidt pass on t (needing all of t) is applied
+// afterwards through W = A^T V_(k):  A^T (t - V d) = q - W d.
+#include <float.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace gspca {
+
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
+typedef double f64x2_t __attribute__((ext_vector_type(2)));
+
+template <typename E> struct Raw16;
+template <> struct Raw16<float> { using T = f32x4_t; };
+template <> struct Raw16<double> { using T = f64x2_t; };
+
+template <typename T>
+__device__ inline T fwave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+__device__ inline bool fused_arrive_last(uint32_t *counter, int *flag_lds)
+{
+    __threadfence();
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t prev = atomicAdd(counter, 1u);
+        *flag_lds = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// ---------------------------------------------------------------------------
+// Re-tile X (column-major, ldx) into row panels; rows >= M are zero.  Flags
+// NaN/Inf.  Thread: one 16-byte panel segment (PR rows of one column).
+
+template <typename E>
+__global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t ldx, int64_t M,
+                                                int64_t N, int64_t NP, E *__restrict__ A,
+                                                LoopState *st)
+{
+    constexpr int PR = 16 / sizeof(E);
+    using RT = typename Raw16<E>::T;
+    int bad = 0;
+    const int64_t total = NP * N;
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < total;
+         s += (int64_t)gridDim.x * 256) {
+        const int64_t b = s / N, j = s - b * N;
+        RT v;
+#pragma unroll
+        for (int r = 0; r < PR; ++r) {
+            const int64_t m = b * PR + r;
+            const E x = m < M ? X[m + j * ldx] : E(0);
+            bad |= !isfinite(x);
+            v[r] = x;
+        }
+        *reinterpret_cast<RT *>(A + s * PR) = v;
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0)
+        atomicOr(&st->nonfinite, 1);
+}
+
+// Squared column norms of the panel matrix, optionally after the explicit
+// deflation A <- A - t p^T (eq. 3; Sec. 2.3 with t = lambda_k v).  Grid:
+// (column blocks of 64) x (panel splits); each split writes its partial
+// norms to cnpart[split][j].
+template <typename E>
+__global__ __launch_bounds__(256) void k_deflate_panel(E *__restrict__ A, int64_t N, int64_t NP,
+                                                       const E *__restrict__ t,
+                                                       const E *__restrict__ pk, int update,
+                                                       double *__restrict__ cnpart)
+{
+    constexpr int PR = 16 / sizeof(E);
+    using RT = typename Raw16<E>::T;
+    __shared__ double red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t nsplit = gridDim.y;
+    const int64_t b0 = NP * blockIdx.y / nsplit, b1 = NP * (blockIdx.y + 1) / nsplit;
+    double s = 0.0;
+    if (j < N) {
+        const E pj = update ? pk[j] : E(0);
+        for (int64_t b = b0 + w; b < b1; b += 4) {
+            RT *ptr = reinterpret_cast<RT *>(A + (b * N + j) * PR);
+            RT v = *ptr;
+            if (update) {
+                const RT tv = *reinterpret_cast<const RT *>(t + b * PR);
+#pragma unroll
+                for (int r = 0; r < PR; ++r)
+                    v[r] = v[r] - tv[r] * pj;
+                *ptr = v;
+            }
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                s += (double)v[r] * (double)v[r];
+        }
+    }
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N)
+        cnpart[(int64_t)blockIdx.y * N + j] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// cn[j] = sum over splits of cnpart (fixed order); implicit mode: the norm of
+// the residual column X_j - T P[j,:]^T from |X_j|^2 and the finished
+// components, |X_j|^2 - 2 sum_i sigma_i P_ji (X^T v_i)_j + sum_i sigma_i^2 P_ji^2
+// (scores mutually orthogonal, X^T v_i stored in W).
+template <typename E>
+__global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict__ cnpart,
+                                                        int nsplit, int64_t N,
+                                                        double *__restrict__ cn0,
+                                                        double *__restrict__ cn, int implicit,
+                                                        int k, const E *__restrict__ P,
+                                                        const double *__restrict__ W,
+                                                        const double *__restrict__ sig)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N)
+        return;
+    double s;
+    if (cnpart) {
+        s = 0.0;
+        for (int i = 0; i < nsplit; ++i)
+            s += cnpart[(int64_t)i * N + j];
+        if (cn0)
+            cn0[j] = s;
+    } else {
+        s = cn0[j];
+    }
+    if (implicit) {
+        for (int i = 0; i < k; ++i) {
+            const double pji = (double)P[j + (int64_t)i * N];
+            s += -2.0 * sig[i] * pji * W[j + (int64_t)i * N] + sig[i] * sig[i] * pji * pji;
+        }
+        if (s < 0.0)
+            s = 0.0;
+    }
+    cn[j] = s;
+}
+
+// Start vector of component k (the pseudo-code's T^(k) <- R^(k)): selection
+// as in k_start, the column taken from the panel copy (explicit) or formed as
+// X_j - sum_i sigma_i v_i P_ji (implicit, X column-major).  Output t (E),
+// zero-padded to NP*PR entries.
+template <typename E>
+__global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, int64_t N,
+                                                      int64_t NP, int64_t M,
+                                                      const E *__restrict__ X, int64_t ldx,
+                                                      int implicit, const E *__restrict__ V,
+                                                      const E *__restrict__ P,
+                                                      const double *__restrict__ sig,
+                                                      const double *__restrict__ cn,
+                                                      const E *__restrict__ T0, StartArgs a,
+                                                      double tiny, E *__restrict__ t,
+                                                      LoopState *st)
+{
+    constexpr int PR = 16 / sizeof(E);
+    __shared__ double sv[16];
+    __shared__ int64_t si[16];
+    __shared__ int64_t col_sel;
+    __shared__ int use_given, degenerate;
+    const int tid = threadIdx.x, w = tid >> 6, lane = tid & 63;
+    if (tid == 0) {
+        col_sel = -2;
+        use_given = 0;
+        degenerate = a.force_degenerate;
+        if (a.replay_start && a.replay_start[a.k] >= 0 && a.replay_start[a.k] < N)
+            col_sel = a.replay_start[a.k];
+        else if (a.init == 1) {
+            if (sqrt(cn[a.k]) >= tiny)
+                col_sel = a.k;
+        } else if (a.init == 2)
+            use_given = 1;
+    }
+    __syncthreads();
+    if (use_given) {
+        double s = 0.0;
+        const E *g = T0 + (int64_t)a.k * M;
+        for (int64_t m = tid; m < M; m += 1024)
+            s += (double)g[m] * (double)g[m];
+        s = fwave_sum(s);
+        if (lane == 0)
+            sv[w] = s;
+        __syncthreads();
+        if (tid == 0) {
+            double tot = 0.0;
+            for (int i = 0; i < 16; ++i)
+                tot += sv[i];
+            const double nrm = sqrt(tot);
+            if (nrm >= tiny && isfinite(nrm))
+                col_sel = -1;
+        }
+        __syncthreads();
+    }
+    if (col_sel == -2) {
+        double best = -1.0;
+        int64_t bi = 0;
+        for (int64_t n = tid; n < N; n += 1024) {
+            const double v = cn[n];
+            if (v > best) { best = v; bi = n; }
+        }
+        for (int o = 32; o > 0; o >>= 1) {
+            const double ov = __shfl_xor(best, o, 64);
+            const int64_t oi = __shfl_xor(bi, o, 64);
+            if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+        }
+        if (lane == 0) { sv[w] = best; si[w] = bi; }
+        __syncthreads();
+        if (tid == 0) {
+            double b = sv[0];
+            int64_t i0 = si[0];
+            for (int i = 1; i < 16; ++i)
+                if (sv[i] > b || (sv[i] == b && si[i] < i0)) { b = sv[i]; i0 = si[i]; }
+            col_sel = i0;
+        }
+        __syncthreads();
+    }
+    if (tid == 0 && col_sel >= 0 && !(sqrt(cn[col_sel]) >= tiny))
+        degenerate = 1;
+    __syncthreads();
+    const int64_t c = col_sel;
+    const int64_t len = NP * PR;
+    for (int64_t m = tid; m < len; m += 1024) {
+        E v = E(0);
+        if (m < M) {
+            if (c < 0) {
+                v = T0[m + (int64_t)a.k * M];
+            } else if (!implicit) {
+                v = A[((m / PR) * N + c) * PR + (m % PR)];
+            } else {
+                double s = (double)X[m + c * ldx];
+                for (int i = 0; i < a.k; ++i)
+                    s -= sig[i] * (double)V[m + (int64_t)i * M] * (double)P[c + (int64_t)i * N];
+                v = (E)s;
+            }
+        }
+        t[m] = v;
+    }
+    if (tid == 0) {
+        st->start_col = (int32_t)c;
+        st->iter = 0;
+        st->mu = 0.0;
+        st->sigma = 0.0;
+        st->pnorm = 1.0;
+        st->delta = 1.0;
+        st->delta_prev = 1.0;
+        st->converged = 0;
+        st->degenerate = degenerate;
+        st->done = degenerate;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// The fused pass.  FIRST: q = A^T t_in only (the start of a component).
+// Otherwise: t = A (p / |p|) (written to t_out in FP64), q = A^T t, and the
+// Gram-Schmidt coefficients d = V_(k)^T t (FP64, finished by the last
+// workgroup).  q is left as per-workgroup partials q_part[g][j].
+
+template <typename E, int CPT, bool FIRST>
+__global__ __launch_bounds__(1024) void k_pass(const E *__restrict__ A, int64_t N, int64_t NP,
+                                               int64_t M, const double *__restrict__ p,
+                                               const E *__restrict__ t_in,
+                                               double *__restrict__ t_out,
+                                               const E *__restrict__ V, int kd,
+                                               E *__restrict__ q_part,
+                                               double *__restrict__ d_part,
+                                               double *__restrict__ d, LoopState *st)
+{
+    if (st->done)
+        return;
+    constexpr int PR = 16 / sizeof(E);
+    using RT = typename Raw16<E>::T;
+    __shared__ E red[2][16][PR];
+    __shared__ int last;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int NT = blockDim.x, nw = NT >> 6;
+    const int64_t G = gridDim.x, g = blockIdx.x;
+    const int64_t b0 = NP * g / G, b1 = NP * (g + 1) / G;
+
+    E preg[CPT];
+    E q[CPT];
+    bool cval[CPT];
+    const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
+#pragma unroll
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t j = tid + (int64_t)c * NT;
+        cval[c] = j < N;
+        preg[c] = (!FIRST && cval[c]) ? (E)(p[j] * inv) : E(0);
+        q[c] = E(0);
+    }
+    RT bufA[CPT], bufB[CPT];
+    auto load = [&](RT *buf, int64_t b) {
+        const E *base = A + b * N * PR;
+#pragma unroll
+        for (int c = 0; c < CPT; ++c) {
+            const int64_t j = tid + (int64_t)c * NT;
+            if (cval[c])
+                buf[c] = __builtin_nontemporal_load(reinterpret_cast<const RT *>(base + j * PR));
+            else
+                buf[c] = RT(0);
+        }
+    };
+    auto process = [&](const RT *buf, int64_t b, int slot) {
+        E tb[PR];
+        if (FIRST) {
+            const RT tv = *reinterpret_cast<const RT *>(t_in + b * PR);
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                tb[r] = tv[r];
+        } else {
+            E tp[PR];
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                tp[r] = E(0);
+#pragma unroll
+            for (int c = 0; c < CPT; ++c)
+#pragma unroll
+                for (int r = 0; r < PR; ++r)
+                    tp[r] += buf[c][r] * preg[c];
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                tp[r] = fwave_sum(tp[r]);
+            if (lane == 0)
+#pragma unroll
+                for (int r = 0; r < PR; ++r)
+                    red[slot][w][r] = tp[r];
+            __syncthreads();
+#pragma unroll
+            for (int r = 0; r < PR; ++r) {
+                E s = E(0);
+                for (int i = 0; i < nw; ++i)
+                    s += red[slot][i][r];
+                tb[r] = s;
+            }
+            if (tid < PR) {
+                const int64_t m = b * PR + tid;
+                t_out[m] = (double)tb[tid];
+            }
+        }
+#pragma unroll
+        for (int c = 0; c < CPT; ++c)
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                q[c] += buf[c][r] * tb[r];
+    };
+
+    int64_t b = b0;
+    if (b < b1)
+        load(bufA, b);
+    while (b < b1) {
+        if (b + 1 < b1)
+            load(bufB, b + 1);
+        process(bufA, b, 0);
+        if (++b >= b1)
+            break;
+        if (b + 1 < b1)
+            load(bufA, b + 1);
+        process(bufB, b, 1);
+        ++b;
+    }
+#pragma unroll
+    for (int c = 0; c < CPT; ++c)
+        if (cval[c])
+            q_part[g * N + tid + (int64_t)c * NT] = q[c];
+    if (FIRST || kd == 0)
+        return;
+    // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows]:
+    // one wave per column of V, coalesced along the rows just written.
+    __threadfence();
+    __syncthreads();
+    const int64_t r0 = b0 * PR, r1 = min(b1 * PR, M);
+    for (int i = w; i < kd; i += nw) {
+        const E *vc = V + (int64_t)i * M;
+        double s = 0.0;
+        for (int64_t m = r0 + lane; m < r1; m += 64)
+            s += (double)vc[m] * t_out[m];
+        s = fwave_sum(s);
+        if (lane == 0)
+            d_part[g * kd + i] = s;
+    }
+    if (!fused_arrive_last(&st->counter[kCntDotM], &last))
+        return;
+    for (int i = tid; i < kd; i += NT) {
+        double s = 0.0;
+        for (int64_t gg = 0; gg < G; ++gg)
+            s += d_part[gg * kd + i];
+        d[i] = s;
+    }
+    if (tid == 0)
+        st->counter[kCntDotM] = 0;
+}
+
+// q = sum_g q_part[g] (FP64, fixed order), q' = q - W d (the Gram-Schmidt
+// correction of t carried to the loading side), then the loading's
+// Gram-Schmidt coefficients c = P_(k)^T q' (Sec. 2.3), finished by the last
+// workgroup.  `it` is the iteration this launch belongs to: when the
+// component stopped in that iteration only q' is formed (it feeds W); when
+// it stopped earlier the launch does nothing.
+template <typename E>
+__global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int64_t G, int64_t N,
+                                               const double *__restrict__ W, int kd,
+                                               const double *__restrict__ d,
+                                               const E *__restrict__ P, int kg,
+                                               double *__restrict__ qy,
+                                               double *__restrict__ cpart,
+                                               double *__restrict__ c, LoopState *st, int it)
+{
+    if (st->degenerate)
+        return;
+    const int done = st->done;
+    if (done && st->iter != it)
+        return;
+    __shared__ double ys[256];
+    __shared__ double ds[1024];
+    __shared__ int last;
+    const int64_t r0 = (int64_t)blockIdx.x * 256;
+    const int64_t j = r0 + threadIdx.x;
+    double v = 0.0;
+    if (j < N)
+        for (int64_t g = 0; g < G; ++g)
+            v += (double)q_part[g * N + j];
+    double proj = 0.0;
+    for (int i0 = 0; i0 < kd; i0 += 1024) {
+        const int n = min(1024, kd - i0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += 256)
+            ds[i] = d[i0 + i];
+        __syncthreads();
+        if (j < N)
+            for (int i = 0; i < n; ++i)
+                proj += W[j + (int64_t)(i0 + i) * N] * ds[i];
+    }
+    v -= proj;
+    if (j < N)
+        qy[j] = v;
+    if (done || kg == 0)
+        return;
+    ys[threadIdx.x] = j < N ? v : 0.0;
+    __syncthreads();
+    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
+    for (int i = w; i < kg; i += 4) {
+        const E *q = P + (int64_t)i * N;
+        double s = 0.0;
+        for (int jj = lane; jj < 256; jj += 64)
+            if (r0 + jj < N)
+                s += (double)q[r0 + jj] * ys[jj];
+        s = fwave_sum(s);
+        if (lane == 0)
+            cpart[(int64_t)blockIdx.x * kg + i] = s;
+    }
+    if (!fused_arrive_last(&st->counter[kCntDotN], &last))
+        return;
+    for (int i = threadIdx.x; i < kg; i += 256) {
+        double s = 0.0;
+        for (int b = 0; b < (int)gridDim.x; ++b)
+            s += cpart[(int64_t)b * kg + i];
+        c[i] = s;
+    }
+    if (threadIdx.x == 0)
+        st->counter[kCntDotN] = 0;
+}
+
+// Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
+// P[:,k] = p / |p|, and the new column of W = A^T V:
+//   A^T v_k = q' / sigma (q' = A^T t of the last pass), minus sigma p_k when A
+//   is the explicitly deflated residual (R <- R - sigma v_k p_k^T).
+template <typename E>
+__global__ __launch_bounds__(256) void k_comp_end(const E *__restrict__ t, int64_t M, int64_t N,
+                                                  const double *__restrict__ p,
+                                                  const double *__restrict__ qy, int k, int gs,
+                                                  int explicit_defl, E *__restrict__ T,
+                                                  E *__restrict__ P, double *__restrict__ W,
+                                                  double *sigma, int32_t *iters,
+                                                  int32_t *start_col, LoopState *st)
+{
+    const int deg = st->degenerate;
+    const double s = st->sigma, pn = st->pnorm;
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < M)
+        T[i + (int64_t)k * M] = deg ? E(0) : (gs ? (E)((double)t[i] / s) : t[i]);
+    if (i < N) {
+        const double pk = p[i] / pn;
+        P[i + (int64_t)k * N] = (E)pk;
+        if (W)
+            W[i + (int64_t)k * N] = deg ? 0.0 : qy[i] / s - (explicit_defl ? s * pk : 0.0);
+    }
+    if (i == 0) {
+        sigma[k] = deg ? 0.0 : s;
+        if (iters)
+            iters[k] = st->iter;
+        if (start_col)
+            start_col[k] = st->start_col;
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Launchers.
+
+static inline unsigned fcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+
+template <typename E>
+void Fused<E>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, E *A,
+                      LoopState *st, hipStream_t s)
+{
+    const int64_t total = NP * N;
+    const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
+    hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, A, st);
+}
+
+template <typename E>
+void Fused<E>::deflate(E *A, int64_t N, int64_t NP, const E *t, const E *pk, int update,
+                       int nsplit, double *cnpart, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_deflate_panel<E>, dim3(fcdiv(N, 64), nsplit), dim3(256), 0, s, A, N, NP,
+                       t, pk, update, cnpart);
+}
+
+template <typename E>
+void Fused<E>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
+                              double *cn, int implicit, int k, const E *P, const double *W,
+                              const double *sig, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colnorm_finish<E>, dim3(fcdiv(N, 256)), dim3(256), 0, s, cnpart, nsplit,
+                       N, cn0, cn, implicit, k, P, W, sig);
+}
+
+template <typename E>
+void Fused<E>::start(const E *A, int64_t N, int64_t NP, int64_t M, const E *X, int64_t ldx,
+                     int implicit, const E *V, const E *P, const double *sig, const double *cn,
+                     const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_start_panel<E>, dim3(1), dim3(1024), 0, s, A, N, NP, M, X, ldx, implicit,
+                       V, P, sig, cn, T0, a, tiny, t, st);
+}
+
+template <typename E, bool FIRST>
+static void launch_pass(int cpt, int G, int NT, const E *A, int64_t N, int64_t NP, int64_t M,
+                        const double *p, const E *t_in, double *t_out, const E *V, int kd,
+                        E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
+{
+#define GSPCA_PASS(C)                                                                          \
+    hipLaunchKernelGGL((k_pass<E, C, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, M, p, t_in, \
+                       t_out, V, kd, q_part, d_part, d, st)
+    switch (cpt) {
+    case 1: GSPCA_PASS(1); break;
+    case 2: GSPCA_PASS(2); break;
+    case 4: GSPCA_PASS(4); break;
+    default: GSPCA_PASS(8); break;
+    }
+#undef GSPCA_PASS
+}
+
+template <typename E>
+void Fused<E>::pass(int first, int cpt, int G, int NT, const E *A, int64_t N, int64_t NP,
+                    int64_t M, const double *p, const E *t_in, double *t_out, const E *V, int kd,
+                    E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
+{
+    if (first)
+        launch_pass<E, true>(cpt, G, NT, A, N, NP, M, p, t_in, t_out, V, 0, q_part, d_part, d, st,
+                             s);
+    else
+        launch_pass<E, false>(cpt, G, NT, A, N, NP, M, p, t_in, t_out, V, kd, q_part, d_part, d,
+                              st, s);
+}
+
+template <typename E>
+void Fused<E>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
+                     const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
+                     LoopState *st, int it, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 256)), dim3(256), 0, s, q_part, G, N, W, kd, d, P,
+                       kg, qy, cpart, c, st, it);
+}
+
+template <typename E>
+void Fused<E>::comp_end(const E *t, int64_t M, int64_t N, const double *p, const double *qy,
+                        int k, int gs, int explicit_defl, E *T, E *P, double *W, double *sigma,
+                        int32_t *iters, int32_t *start_col, LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_comp_end<E>, dim3(fcdiv(M > N ? M : N, 256)), dim3(256), 0, s, t, M, N,
+                       p, qy, k, gs, explicit_defl, T, P, W, sigma, iters, start_col, st);
+}
+
+template struct Fused<float>;
+template struct Fused<double>;
+
+}  // namespace gspca

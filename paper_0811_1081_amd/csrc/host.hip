@@ -102,6 +102,8 @@ gspca_status validate(const gspca_problem *pr, const gspca_options *op)
         return GSPCA_EINVAL;
     if (!(op->tol >= 0.0) || !isfinite(op->tol) || op->max_iter < 1)
         return GSPCA_EINVAL;
+    if (op->implicit_deflation && (op->algo != GSPCA_GS || pr->N > 8192))
+        return GSPCA_EINVAL;
     return GSPCA_OK;
 }
 
@@ -123,7 +125,7 @@ int next_batch(const LoopState &h, double tol, int cur)
 }
 
 template <typename E>
-gspca_status fit_typed(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
+gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
                        void *ws, size_t ws_bytes, hipStream_t s)
 {
     const int64_t M = pr->M, N = pr->N, K = pr->K;
@@ -181,6 +183,7 @@ gspca_status fit_typed(const gspca_problem *pr, const gspca_options *op, const g
             if (hipEventCreate(&e) != hipSuccess)
                 return GSPCA_EDEVICE;
         prof->bytes_per_pass = (int64_t)(M * N * (int64_t)sizeof(E));
+        prof->single_pass = 0;
     }
 
     LoopState h{};
@@ -269,6 +272,234 @@ gspca_status fit_typed(const gspca_problem *pr, const gspca_options *op, const g
     return h.not_converged ? GSPCA_NOT_CONVERGED : GSPCA_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Single-pass path (fused.hip).
+
+constexpr int64_t kFusedMaxN = 8192; // columns held in registers: 1024 threads x 8
+
+struct FusedPlan {
+    int64_t M, N, K, PR, NP;
+    int cpt, NT, G, nsplit_cn, nbM, nbN;
+    size_t off_state, off_A, off_tE, off_td, off_qpart, off_dpart, off_d, off_c, off_qy, off_p,
+        off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
+};
+
+int device_cu_count()
+{
+    int dev = 0, cu = 0;
+    if (hipGetDevice(&dev) != hipSuccess ||
+        hipDeviceGetAttribute(&cu, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cu < 1)
+        cu = 256;
+    return cu;
+}
+
+FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu)
+{
+    FusedPlan f{};
+    f.M = M;
+    f.N = N;
+    f.K = K;
+    f.PR = 16 / (int64_t)esize;
+    f.NP = cdiv(M, f.PR);
+    f.cpt = N <= 1024 ? 1 : N <= 2048 ? 2 : N <= 4096 ? 4 : 8;
+    f.NT = (int)std::min<int64_t>(1024, cdiv(cdiv(N, f.cpt), 64) * 64);
+    const int64_t per_cu = std::max<int64_t>(1, 1024 / f.NT);
+    f.G = (int)std::max<int64_t>(1, std::min<int64_t>(ncu * per_cu, std::max<int64_t>(1, f.NP / 2)));
+    f.nsplit_cn = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cdiv(N, 64)), f.NP));
+    f.nbM = (int)cdiv(M, kBlock);
+    f.nbN = (int)cdiv(N, kBlock);
+    const int nbmax = std::max(f.nbM, f.nbN);
+    const size_t len = (size_t)(f.NP * f.PR);
+    size_t o = 0;
+    f.off_state = o;  o = align_up(o + sizeof(LoopState));
+    f.off_A = o;      o = align_up(o + len * N * esize);
+    f.off_tE = o;     o = align_up(o + len * esize);
+    f.off_td = o;     o = align_up(o + len * 8);
+    f.off_qpart = o;  o = align_up(o + (size_t)f.G * N * esize);
+    f.off_dpart = o;  o = align_up(o + (size_t)f.G * (K + 1) * 8);
+    f.off_d = o;      o = align_up(o + (size_t)(K + 1) * 8);
+    f.off_c = o;      o = align_up(o + (size_t)(K + 1) * 8);
+    f.off_qy = o;     o = align_up(o + (size_t)N * 8);
+    f.off_p = o;      o = align_up(o + (size_t)N * 8);
+    f.off_cpart = o;  o = align_up(o + (size_t)nbmax * (K + 1) * 8);
+    f.off_sq = o;     o = align_up(o + (size_t)nbmax * 8);
+    f.off_cnpart = o; o = align_up(o + (size_t)f.nsplit_cn * N * 8);
+    f.off_cn = o;     o = align_up(o + (size_t)N * 8);
+    f.off_cn0 = o;    o = align_up(o + (size_t)N * 8);
+    f.off_W = o;      o = align_up(o + (size_t)N * K * 8);
+    f.off_sig = o;    o = align_up(o + (size_t)K * 8);
+    f.total = o;
+    return f;
+}
+
+bool use_fused(const gspca_problem *pr) { return pr->N <= kFusedMaxN; }
+
+template <typename E>
+gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
+                       void *ws, size_t ws_bytes, hipStream_t s)
+{
+    const int64_t M = pr->M, N = pr->N, K = pr->K;
+    const FusedPlan f = make_fused_plan(M, N, K, sizeof(E), device_cu_count());
+    if (!ws || ws_bytes < f.total)
+        return GSPCA_EWORKSPACE;
+    if (((uintptr_t)ws) % kAlign)
+        return GSPCA_EINVAL;
+    unsigned char *base = static_cast<unsigned char *>(ws);
+    LoopState *st = reinterpret_cast<LoopState *>(base + f.off_state);
+    E *A = reinterpret_cast<E *>(base + f.off_A);
+    E *tE = reinterpret_cast<E *>(base + f.off_tE);
+    double *td = reinterpret_cast<double *>(base + f.off_td);
+    E *qpart = reinterpret_cast<E *>(base + f.off_qpart);
+    double *dpart = reinterpret_cast<double *>(base + f.off_dpart);
+    double *dvec = reinterpret_cast<double *>(base + f.off_d);
+    double *cvec = reinterpret_cast<double *>(base + f.off_c);
+    double *qy = reinterpret_cast<double *>(base + f.off_qy);
+    double *p = reinterpret_cast<double *>(base + f.off_p);
+    double *cpart = reinterpret_cast<double *>(base + f.off_cpart);
+    double *sq = reinterpret_cast<double *>(base + f.off_sq);
+    double *cnpart = reinterpret_cast<double *>(base + f.off_cnpart);
+    double *cn = reinterpret_cast<double *>(base + f.off_cn);
+    double *cn0 = reinterpret_cast<double *>(base + f.off_cn0);
+    double *W = reinterpret_cast<double *>(base + f.off_W);
+    double *sig = reinterpret_cast<double *>(base + f.off_sig);
+    E *T = static_cast<E *>(rs->T);
+    E *P = static_cast<E *>(rs->P);
+    const E *X = static_cast<const E *>(pr->X);
+    const E *T0 = static_cast<const E *>(op->T0);
+    const double tiny = sizeof(E) == 8 ? DBL_MIN : (double)FLT_MIN;
+    const int gs = op->algo == GSPCA_GS;
+    const int implicit = op->implicit_deflation ? 1 : 0;
+    const double tol = op->tol;
+    const int64_t len = f.NP * f.PR;
+    using L = Launch<E>;
+    using F = Fused<E>;
+
+    std::vector<int32_t> rit;
+    const bool replay = op->replay_iters != nullptr;
+    if (replay) {
+        rit.resize(K);
+        if (hipMemcpy(rit.data(), op->replay_iters, K * sizeof(int32_t), hipMemcpyDeviceToHost) !=
+            hipSuccess)
+            return GSPCA_EDEVICE;
+        for (int64_t k = 0; k < K; ++k)
+            if (rit[k] < 0)
+                return GSPCA_EINVAL;
+    }
+
+    gspca_profile *prof = op->profile;
+    constexpr int kMaxBatch = 64;
+    std::vector<hipEvent_t> ev;
+    struct EventPool {
+        std::vector<hipEvent_t> *v;
+        ~EventPool() { for (hipEvent_t e : *v) (void)hipEventDestroy(e); }
+    } ev_guard{&ev};
+    if (prof) {
+        ev.resize(2 * kMaxBatch);
+        for (auto &e : ev)
+            if (hipEventCreate(&e) != hipSuccess)
+                return GSPCA_EDEVICE;
+        prof->bytes_per_pass = (int64_t)(M * N * (int64_t)sizeof(E));
+        prof->single_pass = 1;
+    }
+
+    LoopState h{};
+    auto read_state = [&]() -> bool {
+        if (hipMemcpyAsync(&h, st, sizeof(LoopState), hipMemcpyDeviceToHost, s) != hipSuccess)
+            return false;
+        return hipStreamSynchronize(s) == hipSuccess;
+    };
+
+    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
+        return GSPCA_EDEVICE;
+    F::retile(X, pr->ldx, M, N, f.NP, A, st, s);
+    if (!read_state())
+        return GSPCA_EDEVICE;
+    if (h.nonfinite)
+        return GSPCA_ENONFINITE;
+    F::deflate(A, N, f.NP, nullptr, nullptr, 0, f.nsplit_cn, cnpart, s);
+    F::colnorm_finish(cnpart, f.nsplit_cn, N, cn0, cn, 0, 0, P, W, sig, s);
+
+    for (int64_t k = 0; k < K; ++k) {
+        const int32_t limit = replay ? rit[k] : op->max_iter;
+        const int kg = gs ? (int)k : 0;
+        StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, op->replay_start_col};
+        F::start(A, N, f.NP, M, X, pr->ldx, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
+        // first loading of the component: p = R^T t0, Gram-Schmidt, norm
+        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, M, p, tE, td, T, 0, qpart, dpart, dvec, st, s);
+        F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
+        L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit, replay,
+                    tiny, s);
+        int32_t enq = 0;
+        int batch = 4;
+        bool have = false;
+        int32_t iter_before = 0;
+        while (enq < limit) {
+            const int n = std::min<int32_t>(std::min(batch, kMaxBatch), limit - enq);
+            for (int i = 0; i < n; ++i) {
+                const int it = enq + i + 1;
+                if (prof)
+                    (void)hipEventRecord(ev[2 * i], s);
+                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, M, p, tE, td, T, kg, qpart, dpart, dvec,
+                        st, s);
+                if (prof)
+                    (void)hipEventRecord(ev[2 * i + 1], s);
+                L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, tE, sq, st, 1, tol, limit,
+                            replay, tiny, s);
+                F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);
+                L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit,
+                            replay, tiny, s);
+            }
+            enq += n;
+            if (!read_state())
+                return GSPCA_EDEVICE;
+            have = true;
+            if (prof) {
+                const int real = std::min(n, h.iter - iter_before);
+                for (int i = 0; i < real; ++i) {
+                    float a_ms = 0.f;
+                    if (hipEventElapsedTime(&a_ms, ev[2 * i], ev[2 * i + 1]) == hipSuccess) {
+                        prof->pass_ms += a_ms;
+                        prof->pass_launches += 1;
+                    }
+                }
+                prof->iterations += std::max(0, h.iter - iter_before);
+                iter_before = h.iter;
+            }
+            if (h.done)
+                break;
+            batch = next_batch(h, tol, batch);
+        }
+        if (!have && !read_state())
+            return GSPCA_EDEVICE;
+        if (h.degenerate)
+            L::degenerate_p(P, N, (int)k, p, st, s);
+        F::comp_end(tE, M, N, p, qy, (int)k, gs, implicit ? 0 : 1, T, P, gs ? W : nullptr, sig,
+                    rs->iters, rs->start_col, st, s);
+        if (k + 1 < K) {
+            if (!implicit) {
+                F::deflate(A, N, f.NP, tE, P + k * N, h.degenerate ? 0 : 1, f.nsplit_cn, cnpart, s);
+                F::colnorm_finish(cnpart, f.nsplit_cn, N, nullptr, cn, 0, 0, P, W, sig, s);
+            } else {
+                F::colnorm_finish(nullptr, 1, N, cn0, cn, 1, (int)k + 1, P, W, sig, s);
+            }
+        }
+    }
+    L::finalize_all(T, M, (int)K, sig, rs->lambda, rs->sigma, gs, s);
+    if (!read_state())
+        return GSPCA_EDEVICE;
+    if (hipGetLastError() != hipSuccess)
+        return GSPCA_EDEVICE;
+    return h.not_converged ? GSPCA_NOT_CONVERGED : GSPCA_OK;
+}
+
+size_t workspace_for(const gspca_problem *pr)
+{
+    const size_t es = dtype_size(pr->dtype);
+    if (use_fused(pr))
+        return make_fused_plan(pr->M, pr->N, pr->K, es, device_cu_count()).total;
+    return make_plan(pr->M, pr->N, pr->K, es).total;
+}
+
 }  // namespace
 
 extern "C" {
@@ -288,7 +519,7 @@ size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt
 {
     if (validate(prob, opt) != GSPCA_OK)
         return 0;
-    return make_plan(prob->M, prob->N, prob->K, dtype_size(prob->dtype)).total;
+    return workspace_for(prob);
 }
 
 gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
@@ -300,9 +531,11 @@ gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
     if (!res || !res->T || !res->P || !res->lambda)
         return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (prob->dtype == GSPCA_F64)
-        return fit_typed<double>(prob, opt, res, ws, ws_bytes, s);
-    return fit_typed<float>(prob, opt, res, ws, ws_bytes, s);
+    if (use_fused(prob))
+        return prob->dtype == GSPCA_F64 ? fit_fused<double>(prob, opt, res, ws, ws_bytes, s)
+                                        : fit_fused<float>(prob, opt, res, ws, ws_bytes, s);
+    return prob->dtype == GSPCA_F64 ? fit_two_pass<double>(prob, opt, res, ws, ws_bytes, s)
+                                    : fit_two_pass<float>(prob, opt, res, ws, ws_bytes, s);
 }
 
 static gspca_status fit_alloc(int32_t dtype, const void *X, int64_t M, int64_t N, int64_t K,

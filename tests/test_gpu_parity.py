@@ -137,6 +137,52 @@ def test_f64_wide_and_tiny_shapes(orc):
 
 
 # --------------------------------------------------------------------------
+# Implicit deflation (X never modified) and the two-pass path for wide X.
+
+@pytest.mark.parametrize("dtype", [np.float64, np.float32])
+@pytest.mark.parametrize("shape", [(3001, 203), (700, 1500)])
+def test_implicit_deflation_parity(orc, dtype, shape):
+    from paper_0811_1081_amd import synth
+    M, N = shape
+    X = synth.haar_spectrum(M, N, 0.85 ** np.arange(40), 1e-4, seed=(10, M + N), dtype=dtype)
+    K = 12
+    tol = 1e-10 if dtype == np.float64 else 1e-6
+    g = _gh().gpu_fit(X, K, tol=tol, max_iter=2000, implicit=True)
+    assert g["status"] == 0
+    tiny = orc.DBL_MIN if dtype == np.float64 else orc.FLT_MIN
+    o = orc.fit(X, K, tol=0.0, max_iter=int(g["iters"].max()), implicit=True,
+                replay_iters=g["iters"], replay_start=g["start_col"], tiny=tiny)
+    ok = _gapped(o.sigma)
+    bound = 1e-10 if dtype == np.float64 else 1e-5
+    assert col_angles(g["P"], o.P)[ok].max() <= bound
+    assert col_angles(g["T"], o.T)[ok].max() <= bound
+    assert np.abs(g["sigma"] / o.sigma - 1).max() <= (1e-12 if dtype == np.float64 else 1e-5)
+    # the same start columns without replay (residual column norms formed implicitly)
+    free = orc.fit(X, K, tol=tol, max_iter=2000, implicit=True, tiny=tiny)
+    assert np.array_equal(free.start_col, g["start_col"])
+
+
+def test_implicit_rejected_for_nipals():
+    import paper_0811_1081_amd as gp
+    X = np.ones((50, 10))
+    with pytest.raises(gp.GspcaError):
+        _gh().gpu_fit(X, 2, algo="nipals", implicit=True)
+
+
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_two_pass_path_wide(orc, algo):
+    """N > 8192 runs the two-pass kernels (p <- R^T t and t <- R p separately)."""
+    from paper_0811_1081_amd import synth
+    M, N = 700, 8200
+    X = synth.haar_spectrum(M, N, 0.8 ** np.arange(30), 1e-4, seed=(11, 0), dtype=np.float32)
+    K = 6
+    g = _gh().gpu_fit(X, K, tol=1e-6, algo=algo)
+    o = _replayed(orc, X, g, K, algo, tiny=orc.FLT_MIN)
+    assert col_angles(g["P"], o.P).max() <= 1e-5
+    assert np.abs(g["sigma"] / o.sigma - 1).max() <= 1e-5
+
+
+# --------------------------------------------------------------------------
 # Start-vector modes, replay, determinism.
 
 def test_init_modes_and_given_start(orc):
