@@ -67,6 +67,7 @@ def main():
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--implicit", action="store_true", help="implicit deflation (X read-only)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
@@ -88,7 +89,7 @@ def main():
     X = synth.case_large_f32(M, N)
     log("generated in %.1f s" % (time.perf_counter() - t0))
     Xd = gp.column_major(torch.from_numpy(X).to("cuda"))
-    ws_bytes = gp.workspace_bytes(Xd, K)
+    ws_bytes = gp.workspace_bytes(Xd, K, implicit=args.implicit)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
     ws_view = ws[(-ws.data_ptr()) % 256:]
     torch.cuda.synchronize()
@@ -102,7 +103,7 @@ def main():
 
     def step(profile=None):
         return gp.fit(Xd, K, tol=args.tol, max_iter=args.max_iter, workspace=ws_view,
-                      profile=profile)
+                      profile=profile, implicit=args.implicit)
 
     for i in range(args.warmup):
         out = step()
@@ -124,15 +125,21 @@ def main():
 
     comps = K * args.steps
     value = comps / elapsed
-    # roofline of the dominant streaming kernel: algorithmic bytes = one read of R
-    dom = "gemv_t" if prof.gemv_t_ms >= prof.gemv_n_ms else "gemv_n"
-    ms = prof.gemv_t_ms if dom == "gemv_t" else prof.gemv_n_ms
-    n_l = prof.gemv_t_launches if dom == "gemv_t" else prof.gemv_n_launches
+    # roofline of the dominant streaming kernel: algorithmic bytes = one read of the data
+    if prof.single_pass:
+        dom, ms, n_l = "k_pass", prof.pass_ms, prof.pass_launches
+        passes_per_iter = 1.0
+    else:
+        dom = "gemv_t" if prof.gemv_t_ms >= prof.gemv_n_ms else "gemv_n"
+        ms = prof.gemv_t_ms if dom == "gemv_t" else prof.gemv_n_ms
+        n_l = prof.gemv_t_launches if dom == "gemv_t" else prof.gemv_n_launches
+        passes_per_iter = 2.0
     avg_s = ms / max(n_l, 1) / 1e3
     bytes_per_launch = float(prof.bytes_per_pass)
     achieved = bytes_per_launch / avg_s / 1e9 if avg_s > 0 else 0.0
     total_iters = int(prof.iterations)
-    fit_gbps = 2.0 * total_iters * bytes_per_launch / elapsed / 1e9
+    fit_gbps = passes_per_iter * total_iters * bytes_per_launch / elapsed / 1e9
+    fit_alg_gbps = total_iters * bytes_per_launch / elapsed / 1e9
 
     P = out["P"].double()
     V = (out["T"].double() / out["sigma"]).double()
@@ -147,7 +154,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": "large_f32_lowrank_%dx%d_K%d" % (M, N, K), "M": M, "N": N,
                    "K": K, "tol": args.tol, "max_iter": args.max_iter, "algo": "gs",
-                   "form": "plain_fp32_explicit_two_pass"},
+                   "form": "plain_fp32_%s_%s" % ("implicit" if args.implicit else "explicit",
+                                                 "single_pass" if prof.single_pass else "two_pass")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
@@ -155,8 +163,7 @@ def main():
         "iters_mean": float(iters.mean()),
         "iterations_timed": total_iters,
         "fit_stream_GBps": fit_gbps,
-        "gemv_t_avg_us": prof.gemv_t_ms / max(prof.gemv_t_launches, 1) * 1e3,
-        "gemv_n_avg_us": prof.gemv_n_ms / max(prof.gemv_n_launches, 1) * 1e3,
+        "fit_algorithmic_GBps": fit_alg_gbps,
         "orth_P": orth_p, "orth_V": orth_v,
         "cpu_baseline": None,
     }

@@ -98,7 +98,7 @@ typedef struct {
     /* 0: explicit deflation R <- R - t p^T after each component (Secs. 2.2-2.3).
      * 1: implicit: R = X - T P^T is never formed; the products use X on
      *    Gram-Schmidt-projected vectors, for which the T P^T terms vanish in
-     *    exact arithmetic (GS-PCA only, N <= 8192). */
+     *    exact arithmetic (GS-PCA only; N <= 8192 for FP32, N <= 4096 for FP64). */
     int32_t implicit_deflation;
     const void *T0;     /* M x K start scores (GIVEN only), dtype of X         */
     double tol;         /* >= 0; 0 runs exactly max_iter iterations            */

@@ -52,26 +52,27 @@ __device__ inline bool fused_arrive_last(uint32_t *counter, int *flag_lds)
 }
 
 // ---------------------------------------------------------------------------
-// Re-tile X (column-major, ldx) into row panels; rows >= M are zero.  Flags
-// NaN/Inf.  Thread: one 16-byte panel segment (PR rows of one column).
+// Re-tile X (column-major, ldx) into row panels of ldp >= N columns; rows >= M
+// and columns >= N are zero.  Flags NaN/Inf.  Thread: one 16-byte panel
+// segment (PR rows of one column).
 
 template <typename E>
 __global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t ldx, int64_t M,
-                                                int64_t N, int64_t NP, E *__restrict__ A,
-                                                LoopState *st)
+                                                int64_t N, int64_t NP, int64_t ldp,
+                                                E *__restrict__ A, LoopState *st)
 {
     constexpr int PR = 16 / sizeof(E);
     using RT = typename Raw16<E>::T;
     int bad = 0;
-    const int64_t total = NP * N;
+    const int64_t total = NP * ldp;
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < total;
          s += (int64_t)gridDim.x * 256) {
-        const int64_t b = s / N, j = s - b * N;
+        const int64_t b = s / ldp, j = s - b * ldp;
         RT v;
 #pragma unroll
         for (int r = 0; r < PR; ++r) {
             const int64_t m = b * PR + r;
-            const E x = m < M ? X[m + j * ldx] : E(0);
+            const E x = (m < M && j < N) ? X[m + j * ldx] : E(0);
             bad |= !isfinite(x);
             v[r] = x;
         }
@@ -87,7 +88,7 @@ __global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t
 // norms to cnpart[split][j].
 template <typename E>
 __global__ __launch_bounds__(256) void k_deflate_panel(E *__restrict__ A, int64_t N, int64_t NP,
-                                                       const E *__restrict__ t,
+                                                       int64_t ldp, const E *__restrict__ t,
                                                        const E *__restrict__ pk, int update,
                                                        double *__restrict__ cnpart)
 {
@@ -102,7 +103,7 @@ __global__ __launch_bounds__(256) void k_deflate_panel(E *__restrict__ A, int64_
     if (j < N) {
         const E pj = update ? pk[j] : E(0);
         for (int64_t b = b0 + w; b < b1; b += 4) {
-            RT *ptr = reinterpret_cast<RT *>(A + (b * N + j) * PR);
+            RT *ptr = reinterpret_cast<RT *>(A + (b * ldp + j) * PR);
             RT v = *ptr;
             if (update) {
                 const RT tv = *reinterpret_cast<const RT *>(t + b * PR);
@@ -165,7 +166,7 @@ __global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict
 // zero-padded to NP*PR entries.
 template <typename E>
 __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, int64_t N,
-                                                      int64_t NP, int64_t M,
+                                                      int64_t NP, int64_t ldp, int64_t M,
                                                       const E *__restrict__ X, int64_t ldx,
                                                       int implicit, const E *__restrict__ V,
                                                       const E *__restrict__ P,
@@ -247,7 +248,7 @@ __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, i
             if (c < 0) {
                 v = T0[m + (int64_t)a.k * M];
             } else if (!implicit) {
-                v = A[((m / PR) * N + c) * PR + (m % PR)];
+                v = A[((m / PR) * ldp + c) * PR + (m % PR)];
             } else {
                 double s = (double)X[m + c * ldx];
                 for (int i = 0; i < a.k; ++i)
@@ -278,8 +279,8 @@ __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, i
 // workgroup).  q is left as per-workgroup partials q_part[g][j].
 
 template <typename E, int CPT, bool FIRST>
-__global__ __launch_bounds__(1024) void k_pass(const E *__restrict__ A, int64_t N, int64_t NP,
-                                               int64_t M, const double *__restrict__ p,
+__global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N, int64_t NP,
+                                              int64_t ldp, int64_t M, const double *__restrict__ p,
                                                const E *__restrict__ t_in,
                                                double *__restrict__ t_out,
                                                const E *__restrict__ V, int kd,
@@ -291,7 +292,7 @@ __global__ __launch_bounds__(1024) void k_pass(const E *__restrict__ A, int64_t 
         return;
     constexpr int PR = 16 / sizeof(E);
     using RT = typename Raw16<E>::T;
-    __shared__ E red[2][16][PR];
+    __shared__ E red[2][8][PR];
     __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int NT = blockDim.x, nw = NT >> 6;
@@ -309,17 +310,19 @@ __global__ __launch_bounds__(1024) void k_pass(const E *__restrict__ A, int64_t 
         preg[c] = (!FIRST && cval[c]) ? (E)(p[j] * inv) : E(0);
         q[c] = E(0);
     }
+    // The panel width ldp = NT * CPT covers every lane's columns (columns >= N
+    // are zero), so every lane always loads: no divergent branch around the
+    // loads, and the wait for one panel does not also wait for the prefetched
+    // next one.  Lanes past N carry p = 0 and never store q.
     RT bufA[CPT], bufB[CPT];
+    const uint32_t lane_off = (uint32_t)tid * 16u;
+    const uint32_t col_step = (uint32_t)NT * 16u;
     auto load = [&](RT *buf, int64_t b) {
-        const E *base = A + b * N * PR;
+        const char *base = reinterpret_cast<const char *>(A + b * ldp * PR) + lane_off;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const int64_t j = tid + (int64_t)c * NT;
-            if (cval[c])
-                buf[c] = __builtin_nontemporal_load(reinterpret_cast<const RT *>(base + j * PR));
-            else
-                buf[c] = RT(0);
-        }
+        for (int c = 0; c < CPT; ++c)
+            buf[c] = __builtin_nontemporal_load(
+                reinterpret_cast<const RT *>(base + (uint32_t)c * col_step));
     };
     auto process = [&](const RT *buf, int64_t b, int slot) {
         E tb[PR];
@@ -365,19 +368,25 @@ __global__ __launch_bounds__(1024) void k_pass(const E *__restrict__ A, int64_t 
                 q[c] += buf[c][r] * tb[r];
     };
 
+    // Software pipeline: panel b+1 is in flight while panel b is reduced.  The
+    // steady-state loop issues its prefetches unconditionally; the last one or
+    // two panels are peeled.
     int64_t b = b0;
     if (b < b1)
         load(bufA, b);
-    while (b < b1) {
-        if (b + 1 < b1)
-            load(bufB, b + 1);
+    while (b + 2 < b1) {
+        load(bufB, b + 1);
         process(bufA, b, 0);
-        if (++b >= b1)
-            break;
-        if (b + 1 < b1)
-            load(bufA, b + 1);
-        process(bufB, b, 1);
-        ++b;
+        load(bufA, b + 2);
+        process(bufB, b + 1, 1);
+        b += 2;
+    }
+    if (b + 1 < b1) {
+        load(bufB, b + 1);
+        process(bufA, b, 0);
+        process(bufB, b + 1, 1);
+    } else if (b < b1) {
+        process(bufA, b, 0);
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c)
@@ -520,20 +529,20 @@ __global__ __launch_bounds__(256) void k_comp_end(const E *__restrict__ t, int64
 static inline unsigned fcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
 template <typename E>
-void Fused<E>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, E *A,
-                      LoopState *st, hipStream_t s)
+void Fused<E>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
+                      E *A, LoopState *st, hipStream_t s)
 {
-    const int64_t total = NP * N;
+    const int64_t total = NP * ldp;
     const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
-    hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, A, st);
+    hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, ldp, A, st);
 }
 
 template <typename E>
-void Fused<E>::deflate(E *A, int64_t N, int64_t NP, const E *t, const E *pk, int update,
-                       int nsplit, double *cnpart, hipStream_t s)
+void Fused<E>::deflate(E *A, int64_t N, int64_t NP, int64_t ldp, const E *t, const E *pk,
+                       int update, int nsplit, double *cnpart, hipStream_t s)
 {
     hipLaunchKernelGGL(k_deflate_panel<E>, dim3(fcdiv(N, 64), nsplit), dim3(256), 0, s, A, N, NP,
-                       t, pk, update, cnpart);
+                       ldp, t, pk, update, cnpart);
 }
 
 template <typename E>
@@ -546,42 +555,45 @@ void Fused<E>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, doubl
 }
 
 template <typename E>
-void Fused<E>::start(const E *A, int64_t N, int64_t NP, int64_t M, const E *X, int64_t ldx,
-                     int implicit, const E *V, const E *P, const double *sig, const double *cn,
-                     const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s)
+void Fused<E>::start(const E *A, int64_t N, int64_t NP, int64_t ldp, int64_t M, const E *X,
+                     int64_t ldx, int implicit, const E *V, const E *P, const double *sig,
+                     const double *cn, const E *T0, StartArgs a, double tiny, E *t, LoopState *st,
+                     hipStream_t s)
 {
-    hipLaunchKernelGGL(k_start_panel<E>, dim3(1), dim3(1024), 0, s, A, N, NP, M, X, ldx, implicit,
-                       V, P, sig, cn, T0, a, tiny, t, st);
+    hipLaunchKernelGGL(k_start_panel<E>, dim3(1), dim3(1024), 0, s, A, N, NP, ldp, M, X, ldx,
+                       implicit, V, P, sig, cn, T0, a, tiny, t, st);
 }
 
 template <typename E, bool FIRST>
-static void launch_pass(int cpt, int G, int NT, const E *A, int64_t N, int64_t NP, int64_t M,
-                        const double *p, const E *t_in, double *t_out, const E *V, int kd,
-                        E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
+static void launch_pass(int cpt, int G, int NT, const E *A, int64_t N, int64_t NP, int64_t ldp,
+                        int64_t M, const double *p, const E *t_in, double *t_out, const E *V,
+                        int kd, E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
 {
-#define GSPCA_PASS(C)                                                                          \
-    hipLaunchKernelGGL((k_pass<E, C, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, M, p, t_in, \
+#define GSPCA_PASS(C)                                                                             \
+    hipLaunchKernelGGL((k_pass<E, C, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, ldp, M, p, t_in, \
                        t_out, V, kd, q_part, d_part, d, st)
     switch (cpt) {
     case 1: GSPCA_PASS(1); break;
     case 2: GSPCA_PASS(2); break;
     case 4: GSPCA_PASS(4); break;
-    default: GSPCA_PASS(8); break;
+    case 8: GSPCA_PASS(8); break;
+    default: GSPCA_PASS(16); break;
     }
 #undef GSPCA_PASS
 }
 
 template <typename E>
 void Fused<E>::pass(int first, int cpt, int G, int NT, const E *A, int64_t N, int64_t NP,
-                    int64_t M, const double *p, const E *t_in, double *t_out, const E *V, int kd,
-                    E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
+                    int64_t ldp, int64_t M, const double *p, const E *t_in, double *t_out,
+                    const E *V, int kd, E *q_part, double *d_part, double *d, LoopState *st,
+                    hipStream_t s)
 {
     if (first)
-        launch_pass<E, true>(cpt, G, NT, A, N, NP, M, p, t_in, t_out, V, 0, q_part, d_part, d, st,
-                             s);
+        launch_pass<E, true>(cpt, G, NT, A, N, NP, ldp, M, p, t_in, t_out, V, 0, q_part, d_part, d,
+                             st, s);
     else
-        launch_pass<E, false>(cpt, G, NT, A, N, NP, M, p, t_in, t_out, V, kd, q_part, d_part, d,
-                              st, s);
+        launch_pass<E, false>(cpt, G, NT, A, N, NP, ldp, M, p, t_in, t_out, V, kd, q_part, d_part,
+                              d, st, s);
 }
 
 template <typename E>

@@ -102,7 +102,8 @@ gspca_status validate(const gspca_problem *pr, const gspca_options *op)
         return GSPCA_EINVAL;
     if (!(op->tol >= 0.0) || !isfinite(op->tol) || op->max_iter < 1)
         return GSPCA_EINVAL;
-    if (op->implicit_deflation && (op->algo != GSPCA_GS || pr->N > 8192))
+    if (op->implicit_deflation &&
+        (op->algo != GSPCA_GS || pr->N > (pr->dtype == GSPCA_F64 ? 4096 : 8192)))
         return GSPCA_EINVAL;
     return GSPCA_OK;
 }
@@ -278,7 +279,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
 constexpr int64_t kFusedMaxN = 8192; // columns held in registers: 1024 threads x 8
 
 struct FusedPlan {
-    int64_t M, N, K, PR, NP;
+    int64_t M, N, K, PR, NP, ldp;
     int cpt, NT, G, nsplit_cn, nbM, nbN;
     size_t off_state, off_A, off_tE, off_td, off_qpart, off_dpart, off_d, off_c, off_qy, off_p,
         off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
@@ -301,9 +302,12 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
     f.K = K;
     f.PR = 16 / (int64_t)esize;
     f.NP = cdiv(M, f.PR);
-    f.cpt = N <= 1024 ? 1 : N <= 2048 ? 2 : N <= 4096 ? 4 : 8;
-    f.NT = (int)std::min<int64_t>(1024, cdiv(cdiv(N, f.cpt), 64) * 64);
-    const int64_t per_cu = std::max<int64_t>(1, 1024 / f.NT);
+    // columns per thread: the fewest with at most 512 threads; the panel width
+    // ldp = NT * cpt (zero columns beyond N) lets every lane load unconditionally
+    f.cpt = N <= 512 ? 1 : N <= 1024 ? 2 : N <= 2048 ? 4 : N <= 4096 ? 8 : 16;
+    f.NT = (int)std::min<int64_t>(512, cdiv(cdiv(N, f.cpt), 64) * 64);
+    f.ldp = (int64_t)f.NT * f.cpt;
+    const int64_t per_cu = std::max<int64_t>(1, 512 / f.NT);
     f.G = (int)std::max<int64_t>(1, std::min<int64_t>(ncu * per_cu, std::max<int64_t>(1, f.NP / 2)));
     f.nsplit_cn = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cdiv(N, 64)), f.NP));
     f.nbM = (int)cdiv(M, kBlock);
@@ -312,7 +316,7 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
     const size_t len = (size_t)(f.NP * f.PR);
     size_t o = 0;
     f.off_state = o;  o = align_up(o + sizeof(LoopState));
-    f.off_A = o;      o = align_up(o + len * N * esize);
+    f.off_A = o;      o = align_up(o + len * f.ldp * esize);
     f.off_tE = o;     o = align_up(o + len * esize);
     f.off_td = o;     o = align_up(o + len * 8);
     f.off_qpart = o;  o = align_up(o + (size_t)f.G * N * esize);
@@ -332,7 +336,12 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
     return f;
 }
 
-bool use_fused(const gspca_problem *pr) { return pr->N <= kFusedMaxN; }
+// FP64 panels hold 2 rows per 16 bytes, so twice the registers per column:
+// the single-pass path takes N <= 8192 for FP32 and N <= 4096 for FP64.
+bool use_fused(const gspca_problem *pr)
+{
+    return pr->N <= (pr->dtype == GSPCA_F64 ? kFusedMaxN / 2 : kFusedMaxN);
+}
 
 template <typename E>
 gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
@@ -411,21 +420,22 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
 
     if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
         return GSPCA_EDEVICE;
-    F::retile(X, pr->ldx, M, N, f.NP, A, st, s);
+    F::retile(X, pr->ldx, M, N, f.NP, f.ldp, A, st, s);
     if (!read_state())
         return GSPCA_EDEVICE;
     if (h.nonfinite)
         return GSPCA_ENONFINITE;
-    F::deflate(A, N, f.NP, nullptr, nullptr, 0, f.nsplit_cn, cnpart, s);
+    F::deflate(A, N, f.NP, f.ldp, nullptr, nullptr, 0, f.nsplit_cn, cnpart, s);
     F::colnorm_finish(cnpart, f.nsplit_cn, N, cn0, cn, 0, 0, P, W, sig, s);
 
     for (int64_t k = 0; k < K; ++k) {
         const int32_t limit = replay ? rit[k] : op->max_iter;
         const int kg = gs ? (int)k : 0;
         StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, op->replay_start_col};
-        F::start(A, N, f.NP, M, X, pr->ldx, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
+        F::start(A, N, f.NP, f.ldp, M, X, pr->ldx, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, M, p, tE, td, T, 0, qpart, dpart, dvec, st, s);
+        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, p, tE, td, T, 0, qpart, dpart, dvec, st,
+                s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
         L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit, replay,
                     tiny, s);
@@ -439,8 +449,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 const int it = enq + i + 1;
                 if (prof)
                     (void)hipEventRecord(ev[2 * i], s);
-                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, M, p, tE, td, T, kg, qpart, dpart, dvec,
-                        st, s);
+                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, p, tE, td, T, kg, qpart, dpart,
+                        dvec, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
                 L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, tE, sq, st, 1, tol, limit,
@@ -477,7 +487,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                     rs->iters, rs->start_col, st, s);
         if (k + 1 < K) {
             if (!implicit) {
-                F::deflate(A, N, f.NP, tE, P + k * N, h.degenerate ? 0 : 1, f.nsplit_cn, cnpart, s);
+                F::deflate(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, f.nsplit_cn,
+                           cnpart, s);
                 F::colnorm_finish(cnpart, f.nsplit_cn, N, nullptr, cn, 0, 0, P, W, sig, s);
             } else {
                 F::colnorm_finish(nullptr, 1, N, cn0, cn, 1, (int)k + 1, P, W, sig, s);

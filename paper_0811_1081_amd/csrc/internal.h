@@ -75,19 +75,21 @@ struct Launch {
 // Single-pass path (fused.hip): the data matrix in 16-byte row panels.
 template <typename E>
 struct Fused {
-    static void retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, E *A,
-                       LoopState *st, hipStream_t s);
-    static void deflate(E *A, int64_t N, int64_t NP, const E *t, const E *pk, int update,
-                        int nsplit, double *cnpart, hipStream_t s);
+    static void retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
+                       E *A, LoopState *st, hipStream_t s);
+    static void deflate(E *A, int64_t N, int64_t NP, int64_t ldp, const E *t, const E *pk,
+                        int update, int nsplit, double *cnpart, hipStream_t s);
     static void colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
                                double *cn, int implicit, int k, const E *P, const double *W,
                                const double *sig, hipStream_t s);
-    static void start(const E *A, int64_t N, int64_t NP, int64_t M, const E *X, int64_t ldx,
-                      int implicit, const E *V, const E *P, const double *sig, const double *cn,
-                      const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s);
+    static void start(const E *A, int64_t N, int64_t NP, int64_t ldp, int64_t M, const E *X,
+                      int64_t ldx, int implicit, const E *V, const E *P, const double *sig,
+                      const double *cn, const E *T0, StartArgs a, double tiny, E *t,
+                      LoopState *st, hipStream_t s);
     static void pass(int first, int cpt, int G, int NT, const E *A, int64_t N, int64_t NP,
-                     int64_t M, const double *p, const E *t_in, double *t_out, const E *V, int kd,
-                     E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s);
+                     int64_t ldp, int64_t M, const double *p, const E *t_in, double *t_out,
+                     const E *V, int kd, E *q_part, double *d_part, double *d, LoopState *st,
+                     hipStream_t s);
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);
