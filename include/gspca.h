@@ -55,9 +55,21 @@ typedef enum {
 } gspca_status;
 
 typedef enum {
-    GSPCA_F64 = 0, /* X, T, P, T0 double                                       */
-    GSPCA_F32 = 1  /* X, T, P, T0 float; Gram-Schmidt and norms in FP64        */
+    GSPCA_F64 = 0,      /* X, T, P, T0 double                                  */
+    GSPCA_F32 = 1,      /* X, T, P, T0 float; Gram-Schmidt and norms in FP64   */
+    GSPCA_BF16 = 2,     /* X = bfloat16 codes from gspca_quantize; T, P, T0 float */
+    GSPCA_FP8_E4M3 = 3  /* X = OCP FP8 E4M3 codes from gspca_quantize; T, P, T0 float */
 } gspca_dtype;
+
+/* Stop rule of each component's iteration. */
+typedef enum {
+    GSPCA_STOP_SIGMA_REL = 0, /* |sigma_j - sigma_(j-1)| < tol * sigma_j: the
+                                 relative test of the paper's programs          */
+    GSPCA_STOP_LOADING = 1    /* |p_j - s p_(j-1)| < tol (s = +-1 aligning the
+                                 signs): the unit loading moved less than tol;
+                                 evaluated from FP64 dot products, meaningful
+                                 for tol >= 1e-7                                */
+} gspca_stop;
 
 typedef enum { GSPCA_GS = 0, GSPCA_NIPALS = 1 } gspca_algo;
 
@@ -79,17 +91,23 @@ typedef struct {
     int64_t gemv_t_launches;
     int64_t gemv_n_launches;
     int64_t iterations;     /* iterations run, summed over components          */
-    int64_t bytes_per_pass; /* algorithmic bytes of one read of the data, M*N*size */
+    int64_t bytes_per_pass; /* algorithmic bytes of one read of the data:
+                               M*N*(bytes per element of the stored X)         */
     int32_t single_pass;    /* 1 when the single-pass path ran                 */
     int32_t reserved;
 } gspca_profile;
 
-/* The data.  X is read, never written. */
+/* The data.  X is read, never written.  For F64/F32, X is column-major with
+ * leading dimension ldx >= M.  For BF16/FP8_E4M3, X is the code buffer
+ * written by gspca_quantize for the same M and N (ldx ignored) and col_scale
+ * its N per-column scales; the represented matrix is
+ * X~[m, n] = decode(code[m, n]) * col_scale[n]. */
 typedef struct {
     int32_t dtype;   /* gspca_dtype                                         */
-    const void *X;   /* M x N, leading dimension ldx >= M                   */
+    const void *X;
     int64_t ldx;
     int64_t M, N, K; /* 1 <= K <= min(M, N)                                 */
+    const float *col_scale; /* BF16/FP8 only (device, N floats)             */
 } gspca_problem;
 
 typedef struct {
@@ -98,8 +116,10 @@ typedef struct {
     /* 0: explicit deflation R <- R - t p^T after each component (Secs. 2.2-2.3).
      * 1: implicit: R = X - T P^T is never formed; the products use X on
      *    Gram-Schmidt-projected vectors, for which the T P^T terms vanish in
-     *    exact arithmetic (GS-PCA only; N <= 8192 for FP32, N <= 4096 for FP64). */
+     *    exact arithmetic (GS-PCA only; N <= 8192 for FP32, BF16 and FP8,
+     *    N <= 4096 for FP64).  Required for BF16/FP8 data. */
     int32_t implicit_deflation;
+    int32_t stop;       /* gspca_stop                                          */
     const void *T0;     /* M x K start scores (GIVEN only), dtype of X         */
     double tol;         /* >= 0; 0 runs exactly max_iter iterations            */
     int32_t max_iter;   /* >= 1: number of (R^T t, R p) product pairs          */
@@ -122,8 +142,9 @@ typedef struct {
     int32_t *start_col; /* K: start column, -1 for a given start (nullable)     */
 } gspca_result;
 
-/* Default options: GS-PCA, max-norm start, tol 1e-7 and max_iter 10000 (the
- * constants of the paper's programs), no replay. */
+/* Default options: GS-PCA, explicit deflation, max-norm start, the relative
+ * sigma stop with tol 1e-7 and max_iter 10000 (the constants of the paper's
+ * programs), no replay, no profile. */
 void gspca_default_options(gspca_options *opt);
 
 /* Bytes of device workspace gspca_fit_ex needs for this problem and options
@@ -140,6 +161,24 @@ size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt
  * GPU (the stream is synchronised).  Returns OK, NOT_CONVERGED or an error. */
 gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
                           const gspca_result *res, void *ws, size_t ws_bytes, void *stream);
+
+/* Reduced-precision storage (not in the paper, whose Sec. 3 only notes the
+ * programs convert to single precision): per-column scale
+ * s_n = max_m |X[m,n]| / Qmax (binary32; Qmax = 1 for BF16, 448 for E4M3;
+ * an all-zero column has s_n = 1) and codes encode(X[m,n] / s_n) (binary32
+ * division, round to nearest even; E4M3 saturates to +-448).
+ * Code layout: row panels of PR = 8 (BF16) or 16 (FP8) rows, panel b holding
+ * rows [b*PR, b*PR + PR) of `ldp` columns, the PR codes of one column in 16
+ * contiguous bytes, column n of panel b at byte offset (b*ldp + n)*16; ldp >= N
+ * is fixed by N (columns >= N and rows >= M are zero codes).
+ * gspca_quantized_bytes: size of Q for M x N (0 if dtype is not BF16/FP8, or
+ * N > 8192).  gspca_quantize: X is FP32 column-major (ldx >= M); Q and
+ * col_scale (N floats) are written on `stream`; `ws` is a device scratch of
+ * at least 256 bytes (256-byte aligned).  Synchronises the stream; returns
+ * ENONFINITE if X holds NaN/Inf. */
+size_t gspca_quantized_bytes(int64_t M, int64_t N, int32_t dtype);
+gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int32_t dtype,
+                            void *Q, float *col_scale, void *ws, size_t ws_bytes, void *stream);
 
 /* Convenience forms: GS-PCA with the max-norm start and the relative
  * sigma test, FP64 or FP32 data (ldx = M).  They allocate and free their own

@@ -33,6 +33,9 @@
  *     (DBL_MIN or FLT_MIN by the caller's choice), sigma_k = 0, t_k = 0 and
  *     p_k is the first canonical vector e_i (ascending i) whose Gram-Schmidt
  *     residual against P_(k) has squared norm >= (N-k)/(2N), normalised.
+ *   - loading stop (not in the paper; optional): component k stops at the
+ *     first iteration j >= 2 where |p_j - s p_(j-1)| < tol, s = +-1 aligning
+ *     the signs of successive unit loadings.
  *   - implicit deflation (not in the paper): R is never formed; products use
  *     R p = X p - T (P^T p) and R^T t = X^T t - P (T^T t), identical in exact
  *     arithmetic.
@@ -53,6 +56,9 @@
 
 #define OR_ALGO_GS 0
 #define OR_ALGO_NIPALS 1
+
+#define OR_STOP_SIGMA 0
+#define OR_STOP_LOADING 1
 
 #define OR_INIT_MAXNORM 0
 #define OR_INIT_COLUMN_K 1
@@ -214,7 +220,7 @@ int oracle_fit(int algo, int implicit,
                const double *X, int64_t M, int64_t N, int64_t ldx, int64_t K,
                double tol, int32_t max_iter, int init, const double *T0,
                const int32_t *replay_iters, const int32_t *replay_start,
-               double tiny,
+               double tiny, int stop,
                double *T, double *P, double *sigma, int32_t *iters, int32_t *start_col,
                double *R_out)
 {
@@ -223,6 +229,8 @@ int oracle_fit(int algo, int implicit,
     if (M < 1 || N < 1 || K < 1 || K > M || K > N || ldx < M || max_iter < 1 || !(tol >= 0.0))
         return OR_EINVAL;
     if (algo != OR_ALGO_GS && algo != OR_ALGO_NIPALS)
+        return OR_EINVAL;
+    if (stop != OR_STOP_SIGMA && stop != OR_STOP_LOADING)
         return OR_EINVAL;
     if (init == OR_INIT_GIVEN && !T0)
         return OR_EINVAL;
@@ -235,12 +243,13 @@ int oracle_fit(int algo, int implicit,
 
     double *t = malloc((size_t)M * sizeof(double));
     double *p = malloc((size_t)N * sizeof(double));
+    double *pprev = malloc((size_t)N * sizeof(double));
     double *coef = malloc((size_t)(K + 1) * sizeof(double));
     double *tmp = malloc((size_t)(K + 1) * sizeof(double));
     double *Tfin = implicit ? malloc((size_t)M * K * sizeof(double)) : NULL;
     double *R = implicit ? NULL : malloc((size_t)M * N * sizeof(double));
-    if (!t || !p || !coef || !tmp || (implicit && !Tfin) || (!implicit && !R)) {
-        free(t); free(p); free(coef); free(tmp); free(Tfin); free(R);
+    if (!t || !p || !pprev || !coef || !tmp || (implicit && !Tfin) || (!implicit && !R)) {
+        free(t); free(p); free(pprev); free(coef); free(tmp); free(Tfin); free(R);
         return OR_EINVAL;
     }
     /* Sec. 2.2/2.3: R <- X. */
@@ -304,6 +313,17 @@ int oracle_fit(int algo, int implicit,
             if (!(pn >= tiny)) { degenerate = 1; break; }
             for (int64_t n = 0; n < N; ++n)
                 p[n] /= pn;
+            /* loading stop (not in the paper): the change |p_j - s p_(j-1)|
+             * of the unit loading, s = +-1 aligning the signs */
+            double dp = INFINITY;
+            if (j >= 2) {
+                const double sgn = dot(p, pprev, N) >= 0.0 ? 1.0 : -1.0;
+                double ss = 0.0;
+                for (int64_t n = 0; n < N; ++n)
+                    ss += (p[n] - sgn * pprev[n]) * (p[n] - sgn * pprev[n]);
+                dp = sqrt(ss);
+            }
+            memcpy(pprev, p, (size_t)N * sizeof(double));
             /* T^(k) <- R P^(k) */
             resid_mul(&op, p, t);
             /* GS-PCA: B <- V_(k)^T V^(k); V^(k) <- V^(k) - V_(k) B */
@@ -318,8 +338,13 @@ int oracle_fit(int algo, int implicit,
                     t[m] /= s;
             if (replay_iters)
                 continue;
-            /* relative test of the host programs (Appendices 1, 3) */
-            if (fabs(mu - s) < tol * s) { converged = 1; break; }
+            if (stop == OR_STOP_LOADING) {
+                if (dp < tol) { converged = 1; break; }
+            } else if (fabs(mu - s) < tol * s) {
+                /* relative test of the host programs (Appendices 1, 3) */
+                converged = 1;
+                break;
+            }
             mu = s;
         }
         if (degenerate) {
@@ -366,7 +391,7 @@ int oracle_fit(int algo, int implicit,
                 resid_column(&op, n, R_out + n * M);
         }
     }
-    free(t); free(p); free(coef); free(tmp); free(Tfin); free(R);
+    free(t); free(p); free(pprev); free(coef); free(tmp); free(Tfin); free(R);
     return status;
 }
 

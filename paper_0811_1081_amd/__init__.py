@@ -14,15 +14,51 @@ from __future__ import annotations
 import ctypes
 
 from . import _binding as _b
-from ._binding import (Profile, EDEVICE, EINVAL, ENOMEM, ENONFINITE, EWORKSPACE, F32, F64, GS,  # noqa: F401
-                       INIT_COLUMN_K, INIT_GIVEN, INIT_MAXNORM, NIPALS, NOT_CONVERGED, OK,
-                       GspcaError, LibraryMissing, status_string)
+from ._binding import (BF16, EDEVICE, EINVAL, ENOMEM, ENONFINITE, EWORKSPACE, F32, F64,  # noqa: F401
+                       FP8_E4M3, GS, INIT_COLUMN_K, INIT_GIVEN, INIT_MAXNORM, NIPALS,
+                       NOT_CONVERGED, OK, STOP_LOADING, STOP_SIGMA_REL, GspcaError,
+                       LibraryMissing, Profile, status_string)
 
-__all__ = ["fit", "workspace_bytes", "column_major", "status_string", "GspcaError",
-           "LibraryMissing", "load"]
+__all__ = ["fit", "quantize", "Quantized", "workspace_bytes", "column_major", "status_string",
+           "GspcaError", "LibraryMissing", "Profile", "load"]
 
 _ALGOS = {"gs": GS, "nipals": NIPALS}
 _INITS = {"maxnorm": INIT_MAXNORM, "column_k": INIT_COLUMN_K, "given": INIT_GIVEN}
+_STOPS = {"sigma": STOP_SIGMA_REL, "loading": STOP_LOADING}
+_FMTS = {"bf16": BF16, "e4m3": FP8_E4M3}
+
+
+class Quantized:
+    """X stored as BF16 or FP8 (E4M3) codes in the library's row-panel layout
+    with per-column FP32 scales (see gspca_quantize in include/gspca.h)."""
+
+    def __init__(self, codes, scale, M, N, fmt):
+        self.codes, self.scale, self.shape, self.fmt = codes, scale, (M, N), fmt
+        self.device = codes.device
+        self.dtype_code = _FMTS[fmt]
+
+
+def quantize(X, fmt="bf16", stream=None) -> Quantized:
+    """Quantise a column-major FP32 device matrix to BF16 or E4M3 codes."""
+    import torch
+    L = _b.load()
+    if X.dtype != torch.float32 or not X.is_cuda or X.dim() != 2 or X.stride(0) != 1:
+        raise ValueError("X must be a column-major float32 device matrix")
+    M, N = X.shape
+    code = _FMTS[fmt]
+    nbytes = int(L.gspca_quantized_bytes(M, N, code))
+    if nbytes == 0:
+        raise GspcaError(EINVAL)
+    Q = torch.empty(nbytes, dtype=torch.uint8, device=X.device)
+    scale = torch.empty(N, dtype=torch.float32, device=X.device)
+    scratch = torch.empty(256, dtype=torch.uint8, device=X.device)
+    if stream is None:
+        stream = torch.cuda.current_stream(X.device)
+    st = int(L.gspca_quantize(X.data_ptr(), M, N, X.stride(1), code, Q.data_ptr(),
+                              scale.data_ptr(), scratch.data_ptr(), 256, ctypes_stream(stream)))
+    if st != OK:
+        raise GspcaError(st)
+    return Quantized(Q, scale, M, N, fmt)
 
 
 def load():
@@ -49,20 +85,24 @@ def _dtype_code(t):
 
 
 def _problem(X, K):
+    if isinstance(X, Quantized):
+        M, N = X.shape
+        return _b.Problem(X.dtype_code, X.codes.data_ptr(), M, M, N, int(K), X.scale.data_ptr())
     if X.dim() != 2:
         raise ValueError("X must be 2-D")
     M, N = X.shape
     if X.stride(0) != 1 or X.stride(1) < max(M, 1):
         raise ValueError("X must be column-major (stride (1, ldx), ldx >= M); use column_major(X)")
-    return _b.Problem(_dtype_code(X), X.data_ptr(), X.stride(1), M, N, int(K))
+    return _b.Problem(_dtype_code(X), X.data_ptr(), X.stride(1), M, N, int(K), None)
 
 
 def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start=None,
-             implicit=False):
+             implicit=False, stop="sigma"):
     o = _b.Options()
     o.algo = _ALGOS[algo]
     o.init = _INITS[init]
     o.implicit_deflation = 1 if implicit else 0
+    o.stop = _STOPS[stop]
     o.T0 = T0.data_ptr() if T0 is not None else None
     o.tol = float(tol)
     o.max_iter = int(max_iter)
@@ -72,10 +112,11 @@ def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start
 
 
 def workspace_bytes(X, K, algo="gs", init="maxnorm", tol=1e-7, max_iter=10000,
-                    implicit=False) -> int:
+                    implicit=False, stop="sigma") -> int:
     L = _b.load()
     pr = _problem(X, K)
-    op = _options(algo, init, tol, max_iter, implicit=implicit)
+    op = _options(algo, init, tol, max_iter, implicit=implicit or isinstance(X, Quantized),
+                  stop=stop)
     return int(L.gspca_workspace_bytes(pr, op))
 
 
@@ -88,7 +129,7 @@ def _workspace(nbytes, device):
 
 def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         replay_iters=None, replay_start=None, workspace=None, stream=None, check=True,
-        profile=None, implicit=False):
+        profile=None, implicit=False, stop="sigma"):
     """Fit K components of the column-major device matrix X (M x N).
 
     Returns a dict of device tensors: T (M x K), P (N x K) (column-major, dtype
@@ -96,27 +137,33 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
     the integer ``status``.  ``replay_iters`` / ``replay_start`` (int32 device
     tensors of length K) force each component's iteration count and start
     column.  ``implicit`` selects implicit deflation (X is never modified,
-    GS-PCA only).  Raises GspcaError on a negative status when ``check``."""
+    GS-PCA only; always on for a Quantized X, whose outputs are float32).
+    ``stop`` is "sigma" (the paper's relative test) or "loading" (the unit
+    loading moved less than tol).  Raises GspcaError on a negative status when
+    ``check``."""
     import torch
     L = _b.load()
-    if not X.is_cuda:
+    quant = isinstance(X, Quantized)
+    if not quant and not X.is_cuda:
         raise ValueError("X must be a device tensor")
     M, N = X.shape
     K = int(K)
     dev = X.device
-    if T0 is not None and (T0.dtype != X.dtype or T0.device != dev or tuple(T0.shape) != (M, K)
+    out_dtype = torch.float32 if quant else X.dtype
+    implicit = implicit or quant
+    if T0 is not None and (T0.dtype != out_dtype or T0.device != dev or tuple(T0.shape) != (M, K)
                            or T0.stride(0) != 1 or T0.stride(1) != M):
-        raise ValueError("T0 must be a column-major (M, K) tensor of X's dtype and device")
+        raise ValueError("T0 must be a column-major (M, K) tensor of the output dtype and device")
     for name, a in (("replay_iters", replay_iters), ("replay_start", replay_start)):
         if a is not None and (a.dtype != torch.int32 or a.device != dev or a.numel() != K
                               or not a.is_contiguous()):
             raise ValueError(name + " must be a contiguous int32 device tensor of length K")
     pr = _problem(X, K)
-    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start, implicit)
+    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start, implicit, stop)
     if profile is not None:
         op.profile = ctypes.addressof(profile)
-    T = torch.empty_strided((M, K), (1, M), dtype=X.dtype, device=dev)
-    P = torch.empty_strided((N, K), (1, N), dtype=X.dtype, device=dev)
+    T = torch.empty_strided((M, K), (1, M), dtype=out_dtype, device=dev)
+    P = torch.empty_strided((N, K), (1, N), dtype=out_dtype, device=dev)
     lam = torch.empty(K, dtype=torch.float64, device=dev)
     sig = torch.empty(K, dtype=torch.float64, device=dev)
     iters = torch.empty(K, dtype=torch.int32, device=dev)

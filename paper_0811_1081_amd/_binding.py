@@ -15,25 +15,29 @@ LIB_PATH = os.path.join(HERE, "libgspca.so")
 
 # gspca_status
 OK, NOT_CONVERGED, EINVAL, EWORKSPACE, EDEVICE, ENONFINITE, ENOMEM = 0, 1, -1, -2, -3, -4, -5
-# gspca_dtype / gspca_algo / gspca_init
-F64, F32 = 0, 1
+# gspca_dtype / gspca_algo / gspca_init / gspca_stop
+F64, F32, BF16, FP8_E4M3 = 0, 1, 2, 3
+STOP_SIGMA_REL, STOP_LOADING = 0, 1
 GS, NIPALS = 0, 1
 INIT_MAXNORM, INIT_COLUMN_K, INIT_GIVEN = 0, 1, 2
 
 EXPORTS = (
     "gspca_default_options", "gspca_workspace_bytes", "gspca_fit_ex", "gspca_fit",
-    "gspca_fit_f32", "gspca_status_string", "gspca_version",
+    "gspca_fit_f32", "gspca_status_string", "gspca_version", "gspca_quantized_bytes",
+    "gspca_quantize",
 )
 
 
 class Problem(ctypes.Structure):
     _fields_ = [("dtype", ctypes.c_int32), ("X", ctypes.c_void_p), ("ldx", ctypes.c_int64),
-                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64)]
+                ("M", ctypes.c_int64), ("N", ctypes.c_int64), ("K", ctypes.c_int64),
+                ("col_scale", ctypes.c_void_p)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("algo", ctypes.c_int32), ("init", ctypes.c_int32),
-                ("implicit_deflation", ctypes.c_int32), ("T0", ctypes.c_void_p),
+                ("implicit_deflation", ctypes.c_int32), ("stop", ctypes.c_int32),
+                ("T0", ctypes.c_void_p),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
                 ("profile", ctypes.c_void_p)]
@@ -88,6 +92,10 @@ def load() -> ctypes.CDLL:
         L.gspca_status_string.argtypes = [ctypes.c_int]
         L.gspca_version.restype = ctypes.c_int
         L.gspca_version.argtypes = []
+        L.gspca_quantized_bytes.restype = ctypes.c_size_t
+        L.gspca_quantized_bytes.argtypes = [i64, i64, i32]
+        L.gspca_quantize.restype = ctypes.c_int
+        L.gspca_quantize.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
         _lib = L
         return L
 

@@ -1,10 +1,12 @@
 // fused.hip -- single-pass form of the power iteration (one read of the data
 // matrix per iteration) for GS-PCA / NIPALS-PCA (Andrecut, arXiv:0811.1081,
-// Secs. 2.2-2.3).
+// Secs. 2.2-2.3), for FP64, FP32 and the reduced-precision BF16 / FP8 (OCP
+// E4M3) storage of X with per-column FP32 scales.
 //
-// The data matrix A (the residual R for explicit deflation, or X itself for
-// implicit deflation) is re-tiled once into row panels: panel b holds rows
-// [b*PR, b*PR + PR) with the PR values of each column contiguous (16 bytes),
+// The data matrix A (the residual R for explicit deflation, X itself for
+// implicit deflation, or the quantised codes Q) is held in row panels: panel b
+// holds rows [b*PR, b*PR + PR) of ldp >= N columns, the PR values of each
+// column contiguous in 16 bytes (PR = 2, 4, 8, 16 for FP64, FP32, BF16, FP8),
 // so a wave reading 64 consecutive columns of a panel reads 1 KiB of
 // contiguous memory.  One persistent workgroup per compute unit walks a
 // contiguous range of panels and, for each panel, computes the PR entries of
@@ -13,8 +15,14 @@
 // values still in registers.  The next panel is loaded while the current one
 // is reduced.  The Gram-Schmidt pass on t (needing all of t) is applied
 // afterwards through W = A^T V_(k):  A^T (t - V d) = q - W d.
+//
+// Quantised storage: X~_mj = decode(Q_mj) * s_j.  The scale is folded into
+// the vectors: X~ p = Q (s o p) and X~^T t = s o (Q^T t); arithmetic is FP32.
 #include <float.h>
+#include <hip/hip_bf16.h>
 #include <math.h>
+
+#include <type_traits>
 
 #include "internal.h"
 
@@ -22,10 +30,73 @@ namespace gspca {
 
 typedef float f32x4_t __attribute__((ext_vector_type(4)));
 typedef double f64x2_t __attribute__((ext_vector_type(2)));
+typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
+typedef float f32x2_t __attribute__((ext_vector_type(2)));
 
-template <typename E> struct Raw16;
-template <> struct Raw16<float> { using T = f32x4_t; };
-template <> struct Raw16<double> { using T = f64x2_t; };
+// Element codecs of a 16-byte panel segment (PR rows of one column).
+struct CodecF64 {
+    using acc = double;
+    using raw = f64x2_t;
+    static constexpr int PR = 2;
+    static constexpr bool scaled = false;
+    __device__ static inline void decode(const raw &v, acc (&o)[PR]) { o[0] = v[0]; o[1] = v[1]; }
+};
+struct CodecF32 {
+    using acc = float;
+    using raw = f32x4_t;
+    static constexpr int PR = 4;
+    static constexpr bool scaled = false;
+    __device__ static inline void decode(const raw &v, acc (&o)[PR])
+    {
+        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+    }
+};
+// bfloat16: the upper half of a binary32, so decoding is a shift.
+struct CodecBF16 {
+    using acc = float;
+    using raw = u32x4_t;
+    static constexpr int PR = 8;
+    static constexpr bool scaled = true;
+    __device__ static inline void decode(const raw &v, acc (&o)[PR])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            o[2 * i] = __uint_as_float(v[i] << 16);
+            o[2 * i + 1] = __uint_as_float(v[i] & 0xFFFF0000u);
+        }
+    }
+    __device__ static inline float decode_one(const unsigned char *seg, int r)
+    {
+        const unsigned short h = reinterpret_cast<const unsigned short *>(seg)[r];
+        return __uint_as_float((unsigned int)h << 16);
+    }
+};
+// OCP E4M3 (gfx950 converts it in hardware, two codes per instruction).
+struct CodecFP8 {
+    using acc = float;
+    using raw = u32x4_t;
+    static constexpr int PR = 16;
+    static constexpr bool scaled = true;
+    __device__ static inline void decode(const raw &v, acc (&o)[PR])
+    {
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const f32x2_t lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], false);
+            const f32x2_t hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], true);
+            o[4 * i] = lo[0];
+            o[4 * i + 1] = lo[1];
+            o[4 * i + 2] = hi[0];
+            o[4 * i + 3] = hi[1];
+        }
+    }
+    __device__ static inline float decode_one(const unsigned char *seg, int r)
+    {
+        const unsigned int word = reinterpret_cast<const unsigned int *>(seg)[r >> 2];
+        const f32x2_t pr = ((r >> 1) & 1) ? __builtin_amdgcn_cvt_pk_f32_fp8((int)word, true)
+                                          : __builtin_amdgcn_cvt_pk_f32_fp8((int)word, false);
+        return (r & 1) ? pr[1] : pr[0];
+    }
+};
 
 template <typename T>
 __device__ inline T fwave_sum(T v)
@@ -51,6 +122,19 @@ __device__ inline bool fused_arrive_last(uint32_t *counter, int *flag_lds)
     return last;
 }
 
+// Element (m, j) of the panel matrix in the arithmetic type (scaled for codes).
+template <class C>
+__device__ inline typename C::acc panel_elem(const unsigned char *A, int64_t ldp, int64_t m,
+                                             int64_t j, const float *scale)
+{
+    const unsigned char *seg = A + ((m / C::PR) * ldp + j) * 16;
+    const int r = (int)(m % C::PR);
+    if constexpr (C::scaled)
+        return C::decode_one(seg, r) * scale[j];
+    else
+        return reinterpret_cast<const typename C::acc *>(seg)[r];
+}
+
 // ---------------------------------------------------------------------------
 // Re-tile X (column-major, ldx) into row panels of ldp >= N columns; rows >= M
 // and columns >= N are zero.  Flags NaN/Inf.  Thread: one 16-byte panel
@@ -62,13 +146,12 @@ __global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t
                                                 E *__restrict__ A, LoopState *st)
 {
     constexpr int PR = 16 / sizeof(E);
-    using RT = typename Raw16<E>::T;
     int bad = 0;
     const int64_t total = NP * ldp;
     for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < total;
          s += (int64_t)gridDim.x * 256) {
         const int64_t b = s / ldp, j = s - b * ldp;
-        RT v;
+        E v[PR];
 #pragma unroll
         for (int r = 0; r < PR; ++r) {
             const int64_t m = b * PR + r;
@@ -76,24 +159,103 @@ __global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t
             bad |= !isfinite(x);
             v[r] = x;
         }
-        *reinterpret_cast<RT *>(A + s * PR) = v;
+#pragma unroll
+        for (int r = 0; r < PR; ++r)
+            A[s * PR + r] = v[r];
     }
     if (__any(bad) && (threadIdx.x & 63) == 0)
         atomicOr(&st->nonfinite, 1);
 }
 
-// Squared column norms of the panel matrix, optionally after the explicit
-// deflation A <- A - t p^T (eq. 3; Sec. 2.3 with t = lambda_k v).  Grid:
-// (column blocks of 64) x (panel splits); each split writes its partial
-// norms to cnpart[split][j].
-template <typename E>
-__global__ __launch_bounds__(256) void k_deflate_panel(E *__restrict__ A, int64_t N, int64_t NP,
-                                                       int64_t ldp, const E *__restrict__ t,
-                                                       const E *__restrict__ pk, int update,
+// Per-column scale of the quantised storage: s_j = max_m |X_mj| / Qmax
+// (binary32 division; Qmax = 1 for BF16, 448 for E4M3; an all-zero column has
+// s_j = 1).  One workgroup per column; flags NaN/Inf.
+__global__ __launch_bounds__(256) void k_col_scale(const float *__restrict__ X, int64_t ldx,
+                                                   int64_t M, float qmax,
+                                                   float *__restrict__ scale, LoopState *st)
+{
+    __shared__ float red[4];
+    const int64_t j = blockIdx.x;
+    const float *col = X + j * ldx;
+    float a = 0.0f;
+    int bad = 0;
+    for (int64_t m = threadIdx.x; m < M; m += 256) {
+        const float x = col[m];
+        bad |= !isfinite(x);
+        a = fmaxf(a, fabsf(x));
+    }
+    if (__any(bad) && (threadIdx.x & 63) == 0)
+        atomicOr(&st->nonfinite, 1);
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        a = fmaxf(a, __shfl_xor(a, o, 64));
+    if ((threadIdx.x & 63) == 0)
+        red[threadIdx.x >> 6] = a;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const float amax = fmaxf(fmaxf(red[0], red[1]), fmaxf(red[2], red[3]));
+        scale[j] = amax > 0.0f ? amax / qmax : 1.0f;
+    }
+}
+
+// Codes q_mj = encode(X_mj / s_j) (binary32 division, round to nearest even;
+// E4M3 saturates to +-448) written into row panels.  Thread: one segment.
+template <class C>
+__global__ __launch_bounds__(256) void k_quantize(const float *__restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t N, int64_t NP, int64_t ldp,
+                                                  const float *__restrict__ scale,
+                                                  unsigned char *__restrict__ Q)
+{
+    constexpr int PR = C::PR;
+    const int64_t total = NP * ldp;
+    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < total;
+         s += (int64_t)gridDim.x * 256) {
+        const int64_t b = s / ldp, j = s - b * ldp;
+        float v[PR];
+        const float sj = j < N ? scale[j] : 1.0f;
+#pragma unroll
+        for (int r = 0; r < PR; ++r) {
+            const int64_t m = b * PR + r;
+            v[r] = (m < M && j < N) ? X[m + j * ldx] / sj : 0.0f;
+        }
+        u32x4_t out;
+        if constexpr (PR == 8) {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                const unsigned int lo = __bfloat16_as_ushort(__float2bfloat16(v[2 * i]));
+                const unsigned int hi = __bfloat16_as_ushort(__float2bfloat16(v[2 * i + 1]));
+                out[i] = lo | (hi << 16);
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < 4; ++i) {
+                float c[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    c[u] = __builtin_amdgcn_fmed3f(v[4 * i + u], 448.0f, -448.0f);
+                int wd = __builtin_amdgcn_cvt_pk_fp8_f32(c[0], c[1], 0, false);
+                wd = __builtin_amdgcn_cvt_pk_fp8_f32(c[2], c[3], wd, true);
+                out[i] = (unsigned int)wd;
+            }
+        }
+        *reinterpret_cast<u32x4_t *>(Q + s * 16) = out;
+    }
+}
+
+// Squared column norms of the panel matrix (FP64), optionally after the
+// explicit deflation A <- A - t p^T (eq. 3; Sec. 2.3 with t = lambda_k v;
+// plain storage only).  Grid: (column blocks of 64) x (panel splits); each
+// split writes its partial norms to cnpart[split][j].
+template <class C>
+__global__ __launch_bounds__(256) void k_deflate_panel(unsigned char *__restrict__ A, int64_t N,
+                                                       int64_t NP, int64_t ldp,
+                                                       const typename C::acc *__restrict__ t,
+                                                       const typename C::acc *__restrict__ pk,
+                                                       int update, const float *__restrict__ scale,
                                                        double *__restrict__ cnpart)
 {
-    constexpr int PR = 16 / sizeof(E);
-    using RT = typename Raw16<E>::T;
+    using E = typename C::acc;
+    constexpr int PR = C::PR;
     __shared__ double red[4][64];
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t j = (int64_t)blockIdx.x * 64 + lane;
@@ -102,31 +264,40 @@ __global__ __launch_bounds__(256) void k_deflate_panel(E *__restrict__ A, int64_
     double s = 0.0;
     if (j < N) {
         const E pj = update ? pk[j] : E(0);
+        double sj = 1.0;
+        if constexpr (C::scaled)
+            sj = (double)scale[j];
         for (int64_t b = b0 + w; b < b1; b += 4) {
-            RT *ptr = reinterpret_cast<RT *>(A + (b * ldp + j) * PR);
-            RT v = *ptr;
-            if (update) {
-                const RT tv = *reinterpret_cast<const RT *>(t + b * PR);
+            typename C::raw *ptr = reinterpret_cast<typename C::raw *>(A + (b * ldp + j) * 16);
+            typename C::raw v = *ptr;
+            if constexpr (!C::scaled) {
+                if (update) {
 #pragma unroll
-                for (int r = 0; r < PR; ++r)
-                    v[r] = v[r] - tv[r] * pj;
-                *ptr = v;
+                    for (int r = 0; r < PR; ++r)
+                        v[r] = v[r] - t[b * PR + r] * pj;
+                    *ptr = v;
+                }
             }
+            E e[PR];
+            C::decode(v, e);
+            double ss = 0.0;
 #pragma unroll
             for (int r = 0; r < PR; ++r)
-                s += (double)v[r] * (double)v[r];
+                ss += (double)e[r] * (double)e[r];
+            s += ss * sj * sj;
         }
     }
     red[w][lane] = s;
     __syncthreads();
     if (w == 0 && j < N)
-        cnpart[(int64_t)blockIdx.y * N + j] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+        cnpart[(int64_t)blockIdx.y * N + j] =
+            red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
 // cn[j] = sum over splits of cnpart (fixed order); implicit mode: the norm of
-// the residual column X_j - T P[j,:]^T from |X_j|^2 and the finished
-// components, |X_j|^2 - 2 sum_i sigma_i P_ji (X^T v_i)_j + sum_i sigma_i^2 P_ji^2
-// (scores mutually orthogonal, X^T v_i stored in W).
+// the residual column A_j - T P[j,:]^T from |A_j|^2 and the finished
+// components, |A_j|^2 - 2 sum_i sigma_i P_ji (A^T v_i)_j + sum_i sigma_i^2 P_ji^2
+// (scores mutually orthogonal, A^T v_i stored in W).
 template <typename E>
 __global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict__ cnpart,
                                                         int nsplit, int64_t N,
@@ -160,23 +331,27 @@ __global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict
     cn[j] = s;
 }
 
-// Start vector of component k (the pseudo-code's T^(k) <- R^(k)): selection
-// as in k_start, the column taken from the panel copy (explicit) or formed as
-// X_j - sum_i sigma_i v_i P_ji (implicit, X column-major).  Output t (E),
-// zero-padded to NP*PR entries.
-template <typename E>
-__global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, int64_t N,
-                                                      int64_t NP, int64_t ldp, int64_t M,
-                                                      const E *__restrict__ X, int64_t ldx,
-                                                      int implicit, const E *__restrict__ V,
-                                                      const E *__restrict__ P,
+// Start vector of component k (the pseudo-code's T^(k) <- R^(k)): explicit
+// deflation takes the residual column from the panel copy; implicit forms
+// A_j - sum_i sigma_i v_i P_ji.  Selection: replayed column, column k, the
+// given vector, or the largest residual column norm (ties to the lowest
+// index), with the fallbacks of the header.  Output t, zero-padded to NP*PR.
+template <class C>
+__global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__restrict__ A,
+                                                      int64_t N, int64_t NP, int64_t ldp,
+                                                      int64_t M, const float *__restrict__ scale,
+                                                      int implicit,
+                                                      const typename C::acc *__restrict__ V,
+                                                      const typename C::acc *__restrict__ P,
                                                       const double *__restrict__ sig,
                                                       const double *__restrict__ cn,
-                                                      const E *__restrict__ T0, StartArgs a,
-                                                      double tiny, E *__restrict__ t,
+                                                      const typename C::acc *__restrict__ T0,
+                                                      StartArgs a, double tiny,
+                                                      typename C::acc *__restrict__ t,
                                                       LoopState *st)
 {
-    constexpr int PR = 16 / sizeof(E);
+    using E = typename C::acc;
+    constexpr int PR = C::PR;
     __shared__ double sv[16];
     __shared__ int64_t si[16];
     __shared__ int64_t col_sel;
@@ -247,12 +422,11 @@ __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, i
         if (m < M) {
             if (c < 0) {
                 v = T0[m + (int64_t)a.k * M];
-            } else if (!implicit) {
-                v = A[((m / PR) * ldp + c) * PR + (m % PR)];
             } else {
-                double s = (double)X[m + c * ldx];
-                for (int i = 0; i < a.k; ++i)
-                    s -= sig[i] * (double)V[m + (int64_t)i * M] * (double)P[c + (int64_t)i * N];
+                double s = (double)panel_elem<C>(A, ldp, m, c, scale);
+                if (implicit)
+                    for (int i = 0; i < a.k; ++i)
+                        s -= sig[i] * (double)V[m + (int64_t)i * M] * (double)P[c + (int64_t)i * N];
                 v = (E)s;
             }
         }
@@ -266,6 +440,7 @@ __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, i
         st->pnorm = 1.0;
         st->delta = 1.0;
         st->delta_prev = 1.0;
+        st->dp = INFINITY;
         st->converged = 0;
         st->degenerate = degenerate;
         st->done = degenerate;
@@ -278,20 +453,23 @@ __global__ __launch_bounds__(1024) void k_start_panel(const E *__restrict__ A, i
 // Gram-Schmidt coefficients d = V_(k)^T t (FP64, finished by the last
 // workgroup).  q is left as per-workgroup partials q_part[g][j].
 
-template <typename E, int CPT, bool FIRST>
-__global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N, int64_t NP,
-                                              int64_t ldp, int64_t M, const double *__restrict__ p,
-                                               const E *__restrict__ t_in,
-                                               double *__restrict__ t_out,
-                                               const E *__restrict__ V, int kd,
-                                               E *__restrict__ q_part,
-                                               double *__restrict__ d_part,
-                                               double *__restrict__ d, LoopState *st)
+template <class C, int CPT, bool FIRST>
+__global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ A, int64_t N,
+                                              int64_t NP, int64_t ldp, int64_t M,
+                                              const float *__restrict__ scale,
+                                              const double *__restrict__ p,
+                                              const typename C::acc *__restrict__ t_in,
+                                              double *__restrict__ t_out,
+                                              const typename C::acc *__restrict__ V, int kd,
+                                              typename C::acc *__restrict__ q_part,
+                                              double *__restrict__ d_part,
+                                              double *__restrict__ d, LoopState *st)
 {
     if (st->done)
         return;
-    constexpr int PR = 16 / sizeof(E);
-    using RT = typename Raw16<E>::T;
+    using E = typename C::acc;
+    using RT = typename C::raw;
+    constexpr int PR = C::PR;
     __shared__ E red[2][8][PR];
     __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -301,13 +479,17 @@ __global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N
 
     E preg[CPT];
     E q[CPT];
-    bool cval[CPT];
     const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
         const int64_t j = tid + (int64_t)c * NT;
-        cval[c] = j < N;
-        preg[c] = (!FIRST && cval[c]) ? (E)(p[j] * inv) : E(0);
+        double pj = 0.0;
+        if (!FIRST && j < N) {
+            pj = p[j] * inv;
+            if constexpr (C::scaled)
+                pj *= (double)scale[j];
+        }
+        preg[c] = (E)pj;
         q[c] = E(0);
     }
     // The panel width ldp = NT * CPT covers every lane's columns (columns >= N
@@ -318,7 +500,7 @@ __global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N
     const uint32_t lane_off = (uint32_t)tid * 16u;
     const uint32_t col_step = (uint32_t)NT * 16u;
     auto load = [&](RT *buf, int64_t b) {
-        const char *base = reinterpret_cast<const char *>(A + b * ldp * PR) + lane_off;
+        const unsigned char *base = A + b * ldp * 16 + lane_off;
 #pragma unroll
         for (int c = 0; c < CPT; ++c)
             buf[c] = __builtin_nontemporal_load(
@@ -327,20 +509,22 @@ __global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N
     auto process = [&](const RT *buf, int64_t b, int slot) {
         E tb[PR];
         if (FIRST) {
-            const RT tv = *reinterpret_cast<const RT *>(t_in + b * PR);
 #pragma unroll
             for (int r = 0; r < PR; ++r)
-                tb[r] = tv[r];
+                tb[r] = t_in[b * PR + r];
         } else {
             E tp[PR];
 #pragma unroll
             for (int r = 0; r < PR; ++r)
                 tp[r] = E(0);
 #pragma unroll
-            for (int c = 0; c < CPT; ++c)
+            for (int c = 0; c < CPT; ++c) {
+                E e[PR];
+                C::decode(buf[c], e);
 #pragma unroll
                 for (int r = 0; r < PR; ++r)
-                    tp[r] += buf[c][r] * preg[c];
+                    tp[r] += e[r] * preg[c];
+            }
 #pragma unroll
             for (int r = 0; r < PR; ++r)
                 tp[r] = fwave_sum(tp[r]);
@@ -362,10 +546,13 @@ __global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N
             }
         }
 #pragma unroll
-        for (int c = 0; c < CPT; ++c)
+        for (int c = 0; c < CPT; ++c) {
+            E e[PR];
+            C::decode(buf[c], e);
 #pragma unroll
             for (int r = 0; r < PR; ++r)
-                q[c] += buf[c][r] * tb[r];
+                q[c] += e[r] * tb[r];
+        }
     };
 
     // Software pipeline: panel b+1 is in flight while panel b is reduced.  The
@@ -389,9 +576,15 @@ __global__ __launch_bounds__(512) void k_pass(const E *__restrict__ A, int64_t N
         process(bufA, b, 0);
     }
 #pragma unroll
-    for (int c = 0; c < CPT; ++c)
-        if (cval[c])
-            q_part[g * N + tid + (int64_t)c * NT] = q[c];
+    for (int c = 0; c < CPT; ++c) {
+        const int64_t j = tid + (int64_t)c * NT;
+        if (j < N) {
+            E v = q[c];
+            if constexpr (C::scaled)
+                v *= scale[j];
+            q_part[g * N + j] = v;
+        }
+    }
     if (FIRST || kd == 0)
         return;
     // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows]:
@@ -528,25 +721,52 @@ __global__ __launch_bounds__(256) void k_comp_end(const E *__restrict__ t, int64
 
 static inline unsigned fcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 
-template <typename E>
-void Fused<E>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
-                      E *A, LoopState *st, hipStream_t s)
+template <int F> struct CodecOf;
+template <> struct CodecOf<kFmtF64> { using type = CodecF64; };
+template <> struct CodecOf<kFmtF32> { using type = CodecF32; };
+template <> struct CodecOf<kFmtBF16> { using type = CodecBF16; };
+template <> struct CodecOf<kFmtFP8> { using type = CodecFP8; };
+
+template <int F>
+void Fused<F>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
+                      unsigned char *A, LoopState *st, hipStream_t s)
 {
-    const int64_t total = NP * ldp;
-    const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
-    hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, ldp, A, st);
+    if constexpr (F == kFmtF64 || F == kFmtF32) {
+        const int64_t total = NP * ldp;
+        const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
+        hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, ldp,
+                           reinterpret_cast<E *>(A), st);
+    }
 }
 
-template <typename E>
-void Fused<E>::deflate(E *A, int64_t N, int64_t NP, int64_t ldp, const E *t, const E *pk,
-                       int update, int nsplit, double *cnpart, hipStream_t s)
+template <int F>
+void Fused<F>::quantize(const float *X, int64_t ldx, int64_t M, int64_t N, int64_t NP,
+                        int64_t ldp, float *scale, unsigned char *Q, LoopState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_deflate_panel<E>, dim3(fcdiv(N, 64), nsplit), dim3(256), 0, s, A, N, NP,
-                       ldp, t, pk, update, cnpart);
+    using C = typename CodecOf<F>::type;
+    if constexpr (C::scaled) {
+        const float qmax = C::PR == 16 ? 448.0f : 1.0f;
+        hipLaunchKernelGGL(k_col_scale, dim3((unsigned)N), dim3(256), 0, s, X, ldx, M, qmax, scale,
+                           st);
+        const int64_t total = NP * ldp;
+        const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
+        hipLaunchKernelGGL(k_quantize<C>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, ldp, scale,
+                           Q);
+    }
 }
 
-template <typename E>
-void Fused<E>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
+template <int F>
+void Fused<F>::deflate(unsigned char *A, int64_t N, int64_t NP, int64_t ldp, const E *t,
+                       const E *pk, int update, const float *scale, int nsplit, double *cnpart,
+                       hipStream_t s)
+{
+    using C = typename CodecOf<F>::type;
+    hipLaunchKernelGGL(k_deflate_panel<C>, dim3(fcdiv(N, 64), nsplit), dim3(256), 0, s, A, N, NP,
+                       ldp, t, pk, update, scale, cnpart);
+}
+
+template <int F>
+void Fused<F>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
                               double *cn, int implicit, int k, const E *P, const double *W,
                               const double *sig, hipStream_t s)
 {
@@ -554,24 +774,27 @@ void Fused<E>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, doubl
                        N, cn0, cn, implicit, k, P, W, sig);
 }
 
-template <typename E>
-void Fused<E>::start(const E *A, int64_t N, int64_t NP, int64_t ldp, int64_t M, const E *X,
-                     int64_t ldx, int implicit, const E *V, const E *P, const double *sig,
+template <int F>
+void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
+                     const float *scale, int implicit, const E *V, const E *P, const double *sig,
                      const double *cn, const E *T0, StartArgs a, double tiny, E *t, LoopState *st,
                      hipStream_t s)
 {
-    hipLaunchKernelGGL(k_start_panel<E>, dim3(1), dim3(1024), 0, s, A, N, NP, ldp, M, X, ldx,
+    using C = typename CodecOf<F>::type;
+    hipLaunchKernelGGL(k_start_panel<C>, dim3(1), dim3(1024), 0, s, A, N, NP, ldp, M, scale,
                        implicit, V, P, sig, cn, T0, a, tiny, t, st);
 }
 
-template <typename E, bool FIRST>
-static void launch_pass(int cpt, int G, int NT, const E *A, int64_t N, int64_t NP, int64_t ldp,
-                        int64_t M, const double *p, const E *t_in, double *t_out, const E *V,
-                        int kd, E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s)
+template <class C, bool FIRST>
+static void launch_pass(int cpt, int G, int NT, const unsigned char *A, int64_t N, int64_t NP,
+                        int64_t ldp, int64_t M, const float *scale, const double *p,
+                        const typename C::acc *t_in, double *t_out, const typename C::acc *V,
+                        int kd, typename C::acc *q_part, double *d_part, double *d,
+                        LoopState *st, hipStream_t s)
 {
-#define GSPCA_PASS(C)                                                                             \
-    hipLaunchKernelGGL((k_pass<E, C, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, ldp, M, p, t_in, \
-                       t_out, V, kd, q_part, d_part, d, st)
+#define GSPCA_PASS(CP)                                                                           \
+    hipLaunchKernelGGL((k_pass<C, CP, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, ldp, M, scale, \
+                       p, t_in, t_out, V, kd, q_part, d_part, d, st)
     switch (cpt) {
     case 1: GSPCA_PASS(1); break;
     case 2: GSPCA_PASS(2); break;
@@ -582,22 +805,23 @@ static void launch_pass(int cpt, int G, int NT, const E *A, int64_t N, int64_t N
 #undef GSPCA_PASS
 }
 
-template <typename E>
-void Fused<E>::pass(int first, int cpt, int G, int NT, const E *A, int64_t N, int64_t NP,
-                    int64_t ldp, int64_t M, const double *p, const E *t_in, double *t_out,
-                    const E *V, int kd, E *q_part, double *d_part, double *d, LoopState *st,
-                    hipStream_t s)
+template <int F>
+void Fused<F>::pass(int first, int cpt, int G, int NT, const unsigned char *A, int64_t N,
+                    int64_t NP, int64_t ldp, int64_t M, const float *scale, const double *p,
+                    const E *t_in, double *t_out, const E *V, int kd, E *q_part, double *d_part,
+                    double *d, LoopState *st, hipStream_t s)
 {
+    using C = typename CodecOf<F>::type;
     if (first)
-        launch_pass<E, true>(cpt, G, NT, A, N, NP, ldp, M, p, t_in, t_out, V, 0, q_part, d_part, d,
-                             st, s);
+        launch_pass<C, true>(cpt, G, NT, A, N, NP, ldp, M, scale, p, t_in, t_out, V, 0, q_part,
+                             d_part, d, st, s);
     else
-        launch_pass<E, false>(cpt, G, NT, A, N, NP, ldp, M, p, t_in, t_out, V, kd, q_part, d_part,
-                              d, st, s);
+        launch_pass<C, false>(cpt, G, NT, A, N, NP, ldp, M, scale, p, t_in, t_out, V, kd, q_part,
+                              d_part, d, st, s);
 }
 
-template <typename E>
-void Fused<E>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
+template <int F>
+void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                      const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                      LoopState *st, int it, hipStream_t s)
 {
@@ -605,8 +829,8 @@ void Fused<E>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int
                        kg, qy, cpart, c, st, it);
 }
 
-template <typename E>
-void Fused<E>::comp_end(const E *t, int64_t M, int64_t N, const double *p, const double *qy,
+template <int F>
+void Fused<F>::comp_end(const E *t, int64_t M, int64_t N, const double *p, const double *qy,
                         int k, int gs, int explicit_defl, E *T, E *P, double *W, double *sigma,
                         int32_t *iters, int32_t *start_col, LoopState *st, hipStream_t s)
 {
@@ -614,7 +838,9 @@ void Fused<E>::comp_end(const E *t, int64_t M, int64_t N, const double *p, const
                        p, qy, k, gs, explicit_defl, T, P, W, sigma, iters, start_col, st);
 }
 
-template struct Fused<float>;
-template struct Fused<double>;
+template struct Fused<kFmtF64>;
+template struct Fused<kFmtF32>;
+template struct Fused<kFmtBF16>;
+template struct Fused<kFmtFP8>;
 
 }  // namespace gspca

@@ -72,7 +72,7 @@ Plan make_plan(int64_t M, int64_t N, int64_t K, size_t esize)
     pl.off_ty = o;    o = align_up(o + (size_t)pl.ldr * 8);
     pl.off_cpart = o; o = align_up(o + (size_t)nbmax * (K + 1) * 8);
     pl.off_c = o;     o = align_up(o + (size_t)(K + 1) * 8);
-    pl.off_sq = o;    o = align_up(o + (size_t)nbmax * 8);
+    pl.off_sq = o;    o = align_up(o + (size_t)nbmax * 2 * 8);
     pl.off_cn = o;    o = align_up(o + (size_t)N * 8);
     pl.off_p = o;     o = align_up(o + (size_t)N * 8);
     pl.off_sig = o;   o = align_up(o + (size_t)K * 8);
@@ -80,7 +80,11 @@ Plan make_plan(int64_t M, int64_t N, int64_t K, size_t esize)
     return pl;
 }
 
-size_t dtype_size(int32_t dt) { return dt == GSPCA_F64 ? 8 : dt == GSPCA_F32 ? 4 : 0; }
+size_t dtype_size(int32_t dt)
+{
+    return dt == GSPCA_F64 ? 8 : dt == GSPCA_F32 ? 4 : dt == GSPCA_BF16 ? 2 : dt == GSPCA_FP8_E4M3 ? 1 : 0;
+}
+bool is_quantised(int32_t dt) { return dt == GSPCA_BF16 || dt == GSPCA_FP8_E4M3; }
 
 gspca_status validate(const gspca_problem *pr, const gspca_options *op)
 {
@@ -88,7 +92,14 @@ gspca_status validate(const gspca_problem *pr, const gspca_options *op)
         return GSPCA_EINVAL;
     if (dtype_size(pr->dtype) == 0 || !pr->X)
         return GSPCA_EINVAL;
-    if (pr->M < 1 || pr->N < 1 || pr->K < 1 || pr->K > pr->M || pr->K > pr->N || pr->ldx < pr->M)
+    if (pr->M < 1 || pr->N < 1 || pr->K < 1 || pr->K > pr->M || pr->K > pr->N)
+        return GSPCA_EINVAL;
+    if (!is_quantised(pr->dtype) && pr->ldx < pr->M)
+        return GSPCA_EINVAL;
+    // quantised data: codes from gspca_quantize, their scales, implicit
+    // deflation (the codes are read-only), GS-PCA, N within the single-pass path
+    if (is_quantised(pr->dtype) &&
+        (!pr->col_scale || !op->implicit_deflation || op->algo != GSPCA_GS || pr->N > 8192))
         return GSPCA_EINVAL;
     // grid-dimension limits of the launch plan (rows: 2^30, columns: 2^25)
     if (pr->M > (int64_t(1) << 30) || pr->N > (int64_t(1) << 25))
@@ -101,6 +112,8 @@ gspca_status validate(const gspca_problem *pr, const gspca_options *op)
     if (op->init == GSPCA_INIT_GIVEN && !op->T0)
         return GSPCA_EINVAL;
     if (!(op->tol >= 0.0) || !isfinite(op->tol) || op->max_iter < 1)
+        return GSPCA_EINVAL;
+    if (op->stop != GSPCA_STOP_SIGMA_REL && op->stop != GSPCA_STOP_LOADING)
         return GSPCA_EINVAL;
     if (op->implicit_deflation &&
         (op->algo != GSPCA_GS || pr->N > (pr->dtype == GSPCA_F64 ? 4096 : 8192)))
@@ -223,7 +236,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
                 if (kk > 0)
                     L::gs_dot(qpart, pl.nsplit_t, N, N, P, N, kk, qy, cpart, c, st, kCntDotN, s);
                 L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, nullptr, sq, st, 0, tol,
-                            limit, replay, tiny, s);
+                            limit, replay, tiny, op->stop, s);
                 if (prof)
                     (void)hipEventRecord(ev[4 * i + 2], s);
                 L::gemv_n(R, pl.ldr, N, p, pl.cols_per_split, pl.nsplit_n, tpart, st, s);
@@ -232,7 +245,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
                 if (kk > 0)
                     L::gs_dot(tpart, pl.nsplit_n, pl.ldr, M, T, M, kk, ty, cpart, c, st, kCntDotM, s);
                 L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, t, sq, st, 1,
-                            tol, limit, replay, tiny, s);
+                            tol, limit, replay, tiny, op->stop, s);
             }
             enq += n;
             if (!read_state())
@@ -276,7 +289,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
 // ---------------------------------------------------------------------------
 // Single-pass path (fused.hip).
 
-constexpr int64_t kFusedMaxN = 8192; // columns held in registers: 1024 threads x 8
+constexpr int64_t kFusedMaxN = 8192; // columns held in registers: 512 threads x 16
 
 struct FusedPlan {
     int64_t M, N, K, PR, NP, ldp;
@@ -294,19 +307,36 @@ int device_cu_count()
     return cu;
 }
 
-FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu)
+int fmt_of(int32_t dtype)
+{
+    switch (dtype) {
+    case GSPCA_F64: return kFmtF64;
+    case GSPCA_F32: return kFmtF32;
+    case GSPCA_BF16: return kFmtBF16;
+    default: return kFmtFP8;
+    }
+}
+
+// Panel width: ldp = NT * cpt columns (zero beyond N), the fewest columns per
+// thread with at most 512 threads.  Depends on N only, so a quantised matrix
+// and the fit that reads it agree on it.
+void panel_width(int64_t N, int *cpt, int *NT, int64_t *ldp)
+{
+    *cpt = N <= 512 ? 1 : N <= 1024 ? 2 : N <= 2048 ? 4 : N <= 4096 ? 8 : 16;
+    *NT = (int)std::min<int64_t>(512, cdiv(cdiv(N, *cpt), 64) * 64);
+    *ldp = (int64_t)(*NT) * (*cpt);
+}
+
+FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
 {
     FusedPlan f{};
     f.M = M;
     f.N = N;
     f.K = K;
-    f.PR = 16 / (int64_t)esize;
+    f.PR = fmt_rows(fmt);
+    const size_t esize = fmt == kFmtF64 ? 8 : 4; // arithmetic / output element
     f.NP = cdiv(M, f.PR);
-    // columns per thread: the fewest with at most 512 threads; the panel width
-    // ldp = NT * cpt (zero columns beyond N) lets every lane load unconditionally
-    f.cpt = N <= 512 ? 1 : N <= 1024 ? 2 : N <= 2048 ? 4 : N <= 4096 ? 8 : 16;
-    f.NT = (int)std::min<int64_t>(512, cdiv(cdiv(N, f.cpt), 64) * 64);
-    f.ldp = (int64_t)f.NT * f.cpt;
+    panel_width(N, &f.cpt, &f.NT, &f.ldp);
     const int64_t per_cu = std::max<int64_t>(1, 512 / f.NT);
     f.G = (int)std::max<int64_t>(1, std::min<int64_t>(ncu * per_cu, std::max<int64_t>(1, f.NP / 2)));
     f.nsplit_cn = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cdiv(N, 64)), f.NP));
@@ -314,9 +344,10 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
     f.nbN = (int)cdiv(N, kBlock);
     const int nbmax = std::max(f.nbM, f.nbN);
     const size_t len = (size_t)(f.NP * f.PR);
+    const bool quantised = fmt == kFmtBF16 || fmt == kFmtFP8; // Q is the caller's
     size_t o = 0;
     f.off_state = o;  o = align_up(o + sizeof(LoopState));
-    f.off_A = o;      o = align_up(o + len * f.ldp * esize);
+    f.off_A = o;      o = align_up(o + (quantised ? 0 : (size_t)f.NP * f.ldp * 16));
     f.off_tE = o;     o = align_up(o + len * esize);
     f.off_td = o;     o = align_up(o + len * 8);
     f.off_qpart = o;  o = align_up(o + (size_t)f.G * N * esize);
@@ -326,7 +357,7 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
     f.off_qy = o;     o = align_up(o + (size_t)N * 8);
     f.off_p = o;      o = align_up(o + (size_t)N * 8);
     f.off_cpart = o;  o = align_up(o + (size_t)nbmax * (K + 1) * 8);
-    f.off_sq = o;     o = align_up(o + (size_t)nbmax * 8);
+    f.off_sq = o;     o = align_up(o + (size_t)nbmax * 2 * 8);
     f.off_cnpart = o; o = align_up(o + (size_t)f.nsplit_cn * N * 8);
     f.off_cn = o;     o = align_up(o + (size_t)N * 8);
     f.off_cn0 = o;    o = align_up(o + (size_t)N * 8);
@@ -337,25 +368,31 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, size_t esize, int ncu
 }
 
 // FP64 panels hold 2 rows per 16 bytes, so twice the registers per column:
-// the single-pass path takes N <= 8192 for FP32 and N <= 4096 for FP64.
+// the single-pass path takes N <= 8192 (N <= 4096 for FP64).  Quantised data
+// always runs it.
 bool use_fused(const gspca_problem *pr)
 {
     return pr->N <= (pr->dtype == GSPCA_F64 ? kFusedMaxN / 2 : kFusedMaxN);
 }
 
-template <typename E>
+template <int FM>
 gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const gspca_result *rs,
                        void *ws, size_t ws_bytes, hipStream_t s)
 {
+    using E = typename FmtElem<FM>::type;
+    using L = Launch<E>;
+    using F = Fused<FM>;
+    constexpr bool quantised = FM == kFmtBF16 || FM == kFmtFP8;
     const int64_t M = pr->M, N = pr->N, K = pr->K;
-    const FusedPlan f = make_fused_plan(M, N, K, sizeof(E), device_cu_count());
+    const FusedPlan f = make_fused_plan(M, N, K, FM, device_cu_count());
     if (!ws || ws_bytes < f.total)
         return GSPCA_EWORKSPACE;
     if (((uintptr_t)ws) % kAlign)
         return GSPCA_EINVAL;
     unsigned char *base = static_cast<unsigned char *>(ws);
     LoopState *st = reinterpret_cast<LoopState *>(base + f.off_state);
-    E *A = reinterpret_cast<E *>(base + f.off_A);
+    unsigned char *A = quantised ? const_cast<unsigned char *>(static_cast<const unsigned char *>(pr->X))
+                                 : base + f.off_A;
     E *tE = reinterpret_cast<E *>(base + f.off_tE);
     double *td = reinterpret_cast<double *>(base + f.off_td);
     E *qpart = reinterpret_cast<E *>(base + f.off_qpart);
@@ -373,15 +410,14 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     double *sig = reinterpret_cast<double *>(base + f.off_sig);
     E *T = static_cast<E *>(rs->T);
     E *P = static_cast<E *>(rs->P);
-    const E *X = static_cast<const E *>(pr->X);
     const E *T0 = static_cast<const E *>(op->T0);
-    const double tiny = sizeof(E) == 8 ? DBL_MIN : (double)FLT_MIN;
+    const float *scale = pr->col_scale;
+    const double tiny = FM == kFmtF64 ? DBL_MIN : (double)FLT_MIN;
     const int gs = op->algo == GSPCA_GS;
-    const int implicit = op->implicit_deflation ? 1 : 0;
+    const int implicit = (op->implicit_deflation || quantised) ? 1 : 0;
     const double tol = op->tol;
+    const int stop = op->stop;
     const int64_t len = f.NP * f.PR;
-    using L = Launch<E>;
-    using F = Fused<E>;
 
     std::vector<int32_t> rit;
     const bool replay = op->replay_iters != nullptr;
@@ -407,7 +443,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         for (auto &e : ev)
             if (hipEventCreate(&e) != hipSuccess)
                 return GSPCA_EDEVICE;
-        prof->bytes_per_pass = (int64_t)(M * N * (int64_t)sizeof(E));
+        prof->bytes_per_pass = (int64_t)(M * N * (int64_t)(16 / f.PR));
         prof->single_pass = 1;
     }
 
@@ -420,25 +456,27 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
 
     if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
         return GSPCA_EDEVICE;
-    F::retile(X, pr->ldx, M, N, f.NP, f.ldp, A, st, s);
-    if (!read_state())
-        return GSPCA_EDEVICE;
-    if (h.nonfinite)
-        return GSPCA_ENONFINITE;
-    F::deflate(A, N, f.NP, f.ldp, nullptr, nullptr, 0, f.nsplit_cn, cnpart, s);
+    if constexpr (!quantised) {
+        F::retile(static_cast<const E *>(pr->X), pr->ldx, M, N, f.NP, f.ldp, A, st, s);
+        if (!read_state())
+            return GSPCA_EDEVICE;
+        if (h.nonfinite)
+            return GSPCA_ENONFINITE;
+    }
+    F::deflate(A, N, f.NP, f.ldp, nullptr, nullptr, 0, scale, f.nsplit_cn, cnpart, s);
     F::colnorm_finish(cnpart, f.nsplit_cn, N, cn0, cn, 0, 0, P, W, sig, s);
 
     for (int64_t k = 0; k < K; ++k) {
         const int32_t limit = replay ? rit[k] : op->max_iter;
         const int kg = gs ? (int)k : 0;
         StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, op->replay_start_col};
-        F::start(A, N, f.NP, f.ldp, M, X, pr->ldx, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
+        F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, p, tE, td, T, 0, qpart, dpart, dvec, st,
-                s);
+        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, 0, qpart, dpart,
+                dvec, st, s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
         L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit, replay,
-                    tiny, s);
+                    tiny, stop, s);
         int32_t enq = 0;
         int batch = 4;
         bool have = false;
@@ -449,15 +487,15 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 const int it = enq + i + 1;
                 if (prof)
                     (void)hipEventRecord(ev[2 * i], s);
-                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, p, tE, td, T, kg, qpart, dpart,
-                        dvec, st, s);
+                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, kg, qpart,
+                        dpart, dvec, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
                 L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, tE, sq, st, 1, tol, limit,
-                            replay, tiny, s);
+                            replay, tiny, stop, s);
                 F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);
                 L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit,
-                            replay, tiny, s);
+                            replay, tiny, stop, s);
             }
             enq += n;
             if (!read_state())
@@ -487,8 +525,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                     rs->iters, rs->start_col, st, s);
         if (k + 1 < K) {
             if (!implicit) {
-                F::deflate(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, f.nsplit_cn,
-                           cnpart, s);
+                F::deflate(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, scale,
+                           f.nsplit_cn, cnpart, s);
                 F::colnorm_finish(cnpart, f.nsplit_cn, N, nullptr, cn, 0, 0, P, W, sig, s);
             } else {
                 F::colnorm_finish(nullptr, 1, N, cn0, cn, 1, (int)k + 1, P, W, sig, s);
@@ -505,10 +543,9 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
 
 size_t workspace_for(const gspca_problem *pr)
 {
-    const size_t es = dtype_size(pr->dtype);
     if (use_fused(pr))
-        return make_fused_plan(pr->M, pr->N, pr->K, es, device_cu_count()).total;
-    return make_plan(pr->M, pr->N, pr->K, es).total;
+        return make_fused_plan(pr->M, pr->N, pr->K, fmt_of(pr->dtype), device_cu_count()).total;
+    return make_plan(pr->M, pr->N, pr->K, dtype_size(pr->dtype)).total;
 }
 
 }  // namespace
@@ -542,9 +579,14 @@ gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
     if (!res || !res->T || !res->P || !res->lambda)
         return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (use_fused(prob))
-        return prob->dtype == GSPCA_F64 ? fit_fused<double>(prob, opt, res, ws, ws_bytes, s)
-                                        : fit_fused<float>(prob, opt, res, ws, ws_bytes, s);
+    if (use_fused(prob)) {
+        switch (prob->dtype) {
+        case GSPCA_F64: return fit_fused<kFmtF64>(prob, opt, res, ws, ws_bytes, s);
+        case GSPCA_F32: return fit_fused<kFmtF32>(prob, opt, res, ws, ws_bytes, s);
+        case GSPCA_BF16: return fit_fused<kFmtBF16>(prob, opt, res, ws, ws_bytes, s);
+        default: return fit_fused<kFmtFP8>(prob, opt, res, ws, ws_bytes, s);
+        }
+    }
     return prob->dtype == GSPCA_F64 ? fit_two_pass<double>(prob, opt, res, ws, ws_bytes, s)
                                     : fit_two_pass<float>(prob, opt, res, ws, ws_bytes, s);
 }
@@ -553,7 +595,7 @@ static gspca_status fit_alloc(int32_t dtype, const void *X, int64_t M, int64_t N
                               double tol, int32_t max_iter, void *T, void *P, double *lambda,
                               void *stream)
 {
-    gspca_problem pr{dtype, X, M, M, N, K};
+    gspca_problem pr{dtype, X, M, M, N, K, nullptr};
     gspca_options op;
     gspca_default_options(&op);
     op.tol = tol;
@@ -586,6 +628,45 @@ gspca_status gspca_fit_f32(const float *X, int64_t M, int64_t N, int64_t K, doub
                            int32_t max_iter, float *T, float *P, double *lambda, void *stream)
 {
     return fit_alloc(GSPCA_F32, X, M, N, K, tol, max_iter, T, P, lambda, stream);
+}
+
+size_t gspca_quantized_bytes(int64_t M, int64_t N, int32_t dtype)
+{
+    if (!is_quantised(dtype) || M < 1 || N < 1 || N > 8192 || M > (int64_t(1) << 30))
+        return 0;
+    int cpt = 0, NT = 0;
+    int64_t ldp = 0;
+    panel_width(N, &cpt, &NT, &ldp);
+    return (size_t)cdiv(M, fmt_rows(fmt_of(dtype))) * (size_t)ldp * 16;
+}
+
+gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int32_t dtype,
+                            void *Q, float *col_scale, void *ws, size_t ws_bytes, void *stream)
+{
+    if (!X || !Q || !col_scale || ldx < M || gspca_quantized_bytes(M, N, dtype) == 0)
+        return GSPCA_EINVAL;
+    if (!ws || ws_bytes < sizeof(LoopState))
+        return GSPCA_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    LoopState *st = static_cast<LoopState *>(ws);
+    int cpt = 0, NT = 0;
+    int64_t ldp = 0;
+    panel_width(N, &cpt, &NT, &ldp);
+    const int fmt = fmt_of(dtype);
+    const int64_t NP = cdiv(M, fmt_rows(fmt));
+    unsigned char *q = static_cast<unsigned char *>(Q);
+    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
+        return GSPCA_EDEVICE;
+    if (fmt == kFmtBF16)
+        Fused<kFmtBF16>::quantize(X, ldx, M, N, NP, ldp, col_scale, q, st, s);
+    else
+        Fused<kFmtFP8>::quantize(X, ldx, M, N, NP, ldp, col_scale, q, st, s);
+    int32_t bad = 0;
+    if (hipMemcpyAsync(&bad, &st->nonfinite, sizeof(int32_t), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return GSPCA_EDEVICE;
+    return bad ? GSPCA_ENONFINITE : GSPCA_OK;
 }
 
 const char *gspca_status_string(int status)

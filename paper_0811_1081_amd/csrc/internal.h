@@ -24,6 +24,7 @@ struct LoopState {
     double pnorm;      // |p| after the Gram-Schmidt pass of this iteration
     double delta;      // |sigma - mu| / sigma of the last iteration
     double delta_prev; // the same one iteration earlier
+    double dp;         // |p_j - s p_(j-1)| of the loading in use (inf for j = 1)
     int32_t iter;      // iterations done on the current component
     int32_t done;      // the current component has stopped
     int32_t converged; // stopped by the relative test
@@ -61,7 +62,8 @@ struct Launch {
     static void gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
                          const double *y, const E *Q, int64_t ldq, int k, const double *c,
                          double *ydst, E *edst, double *sqpart, LoopState *st, int side,
-                         double tol, int32_t limit, int replay, double tiny, hipStream_t s);
+                         double tol, int32_t limit, int replay, double tiny, int stop,
+                         hipStream_t s);
     static void degenerate_p(const E *P, int64_t N, int k, double *p, LoopState *st, hipStream_t s);
     static void finalize_comp(const E *t, int64_t M, int64_t N, const double *p, int k, int gs,
                               E *T, E *P, double *sigma, int32_t *iters, int32_t *start_col,
@@ -72,24 +74,35 @@ struct Launch {
                              double *sigma_out, int gs, hipStream_t s);
 };
 
-// Single-pass path (fused.hip): the data matrix in 16-byte row panels.
-template <typename E>
+// Single-pass path (fused.hip): the data matrix in 16-byte row panels, in one
+// of four storage formats.  E is the arithmetic/output element type.
+enum Fmt { kFmtF64 = 0, kFmtF32 = 1, kFmtBF16 = 2, kFmtFP8 = 3 };
+template <int F> struct FmtElem { using type = float; };
+template <> struct FmtElem<kFmtF64> { using type = double; };
+constexpr int fmt_rows(int f) { return f == kFmtF64 ? 2 : f == kFmtF32 ? 4 : f == kFmtBF16 ? 8 : 16; }
+
+template <int F>
 struct Fused {
+    using E = typename FmtElem<F>::type;
     static void retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
-                       E *A, LoopState *st, hipStream_t s);
-    static void deflate(E *A, int64_t N, int64_t NP, int64_t ldp, const E *t, const E *pk,
-                        int update, int nsplit, double *cnpart, hipStream_t s);
+                       unsigned char *A, LoopState *st, hipStream_t s);
+    static void quantize(const float *X, int64_t ldx, int64_t M, int64_t N, int64_t NP,
+                         int64_t ldp, float *scale, unsigned char *Q, LoopState *st,
+                         hipStream_t s);
+    static void deflate(unsigned char *A, int64_t N, int64_t NP, int64_t ldp, const E *t,
+                        const E *pk, int update, const float *scale, int nsplit, double *cnpart,
+                        hipStream_t s);
     static void colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
                                double *cn, int implicit, int k, const E *P, const double *W,
                                const double *sig, hipStream_t s);
-    static void start(const E *A, int64_t N, int64_t NP, int64_t ldp, int64_t M, const E *X,
-                      int64_t ldx, int implicit, const E *V, const E *P, const double *sig,
+    static void start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
+                      const float *scale, int implicit, const E *V, const E *P, const double *sig,
                       const double *cn, const E *T0, StartArgs a, double tiny, E *t,
                       LoopState *st, hipStream_t s);
-    static void pass(int first, int cpt, int G, int NT, const E *A, int64_t N, int64_t NP,
-                     int64_t ldp, int64_t M, const double *p, const E *t_in, double *t_out,
-                     const E *V, int kd, E *q_part, double *d_part, double *d, LoopState *st,
-                     hipStream_t s);
+    static void pass(int first, int cpt, int G, int NT, const unsigned char *A, int64_t N,
+                     int64_t NP, int64_t ldp, int64_t M, const float *scale, const double *p,
+                     const E *t_in, double *t_out, const E *V, int kd, E *q_part, double *d_part,
+                     double *d, LoopState *st, hipStream_t s);
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);

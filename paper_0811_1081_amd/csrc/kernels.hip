@@ -209,6 +209,7 @@ __global__ __launch_bounds__(1024) void k_start(const E *__restrict__ R, int64_t
         st->pnorm = 1.0;
         st->delta = 1.0;
         st->delta_prev = 1.0;
+        st->dp = INFINITY;
         st->converged = 0;
         st->degenerate = degenerate;
         st->done = degenerate;
@@ -380,10 +381,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ pa
 }
 
 // x = y - Q c (one classical Gram-Schmidt pass), squared norm; the last
-// workgroup finishes the norm.  side 0 (loading): x kept in FP64 (ydst) and
-// |p| stored.  side 1 (score): x stored in the element type (edst), sigma,
-// the relative convergence test of the host programs (Appendices 1, 3) or
-// the replay count, and the loop state update.
+// workgroup finishes the norm.  side 0 (loading): x kept in FP64 (ydst, which
+// holds the previous loading on entry), |p| stored, and the change of the unit
+// loading |p_j - s p_(j-1)| = sqrt(2 - 2 |cos|) (s the sign of the cosine;
+// infinite for the first loading of a component).  side 1 (score): x stored
+// in the element type (edst), sigma, then the stop test -- the relative sigma
+// test of the host programs (Appendices 1, 3) when stop == 0, the loading
+// change below tol when stop == 1, or the replayed count -- and the loop state.
 
 template <typename E>
 __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ part, int nsplit,
@@ -395,7 +399,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
                                                      E *__restrict__ edst,
                                                      double *__restrict__ sqpart, LoopState *st,
                                                      int side, double tol, int32_t limit,
-                                                     int replay, double tiny)
+                                                     int replay, double tiny, int stop)
 {
     if (st->done)
         return;
@@ -424,27 +428,47 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
                 proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
     }
     v -= proj;
+    double dot_old = 0.0;
     if (r < L) {
-        if (side == 0)
+        if (side == 0) {
+            dot_old = v * ydst[r];
             ydst[r] = v;
-        else
+        } else {
             edst[r] = (E)v;
+        }
     }
     const double sq = block_sum(r < L ? v * v : 0.0, red);
     if (threadIdx.x == 0)
         sqpart[blockIdx.x] = sq;
+    if (side == 0) {
+        const double dt = block_sum(dot_old, red);
+        if (threadIdx.x == 0)
+            sqpart[gridDim.x + blockIdx.x] = dt;
+    }
     if (!arrive_last(&st->counter[side == 0 ? kCntApplyN : kCntApplyM], &last))
         return;
-    double tot = 0.0;
-    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock)
+    double tot = 0.0, dtot = 0.0;
+    for (int b = threadIdx.x; b < (int)gridDim.x; b += kBlock) {
         tot += sqpart[b];
-    // fixed-order final sum: per-thread strided partials, then the block tree
+        if (side == 0)
+            dtot += sqpart[gridDim.x + b];
+    }
+    // fixed-order final sums: per-thread strided partials, then the block tree
     tot = block_sum(tot, red);
+    if (side == 0)
+        dtot = block_sum(dtot, red);
     if (threadIdx.x != 0)
         return;
     st->counter[side == 0 ? kCntApplyN : kCntApplyM] = 0;
     const double nrm = sqrt(tot);
     if (side == 0) {
+        const double old = st->pnorm;
+        double dp = INFINITY;
+        if (st->iter > 0 && nrm > 0.0 && old > 0.0) {
+            const double cs1 = fmin(1.0, fabs(dtot) / (nrm * old));
+            dp = sqrt(fmax(0.0, 2.0 - 2.0 * cs1));
+        }
+        st->dp = dp;
         st->pnorm = nrm;
         if (!(nrm >= tiny)) { // counts as the iteration in which it happened
             st->iter = st->iter + 1;
@@ -463,13 +487,14 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
     }
     const double mu = st->mu;
     st->delta_prev = st->delta;
-    st->delta = fabs(nrm - mu) / nrm;
+    st->delta = stop == 1 ? st->dp : fabs(nrm - mu) / nrm;
     if (replay) {
         if (it >= limit)
             st->done = 1;
         return;
     }
-    if (fabs(mu - nrm) < tol * nrm) {
+    const bool pass_test = stop == 1 ? (st->dp < tol) : (fabs(mu - nrm) < tol * nrm);
+    if (pass_test) {
         st->converged = 1;
         st->done = 1;
         return;
@@ -648,11 +673,12 @@ template <typename E>
 void Launch<E>::gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
                          const double *y, const E *Q, int64_t ldq, int k, const double *c,
                          double *ydst, E *edst, double *sqpart, LoopState *st, int side,
-                         double tol, int32_t limit, int replay, double tiny, hipStream_t s)
+                         double tol, int32_t limit, int replay, double tiny, int stop,
+                         hipStream_t s)
 {
     hipLaunchKernelGGL(k_gs_apply<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, part, nsplit,
                        ldpart, L, y, Q, ldq, k, c, ydst, edst, sqpart, st, side, tol, limit,
-                       replay, tiny);
+                       replay, tiny, stop);
 }
 
 template <typename E>

@@ -16,7 +16,7 @@ def gpu_fit(X, K, **kw):
     """Run the library on host array X; returns numpy copies of every output."""
     import torch
     import paper_0811_1081_amd as gp
-    Xd = X if hasattr(X, "is_cuda") else to_device(X)
+    Xd = X if (hasattr(X, "is_cuda") or isinstance(X, gp.Quantized)) else to_device(X)
     out = gp.fit(Xd, K, **kw)
     torch.cuda.synchronize()
     res = {k: (v.cpu().numpy() if hasattr(v, "cpu") else v) for k, v in out.items()}

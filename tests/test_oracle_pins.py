@@ -312,3 +312,25 @@ def test_max_iter_reports_not_converged(orc):
     assert f.status == orc.NOT_CONVERGED
     assert np.all(f.iters == 3)
     assert orth_err(f.P) <= 1e-14
+
+
+def test_loading_stop_accuracy_bound(orc):
+    """Loading stop: once |p_j - p_(j-1)| < tol the error to the exact singular
+    vector is below rho tol / (1 - rho), rho = (s_(k+1)/s_k)^2 the per-iteration
+    contraction of the loading error of power iteration."""
+    M, N, r = 60, 20, 0.8
+    s = r ** np.arange(N)
+    X, U, W = _constructed(M, N, s, seed=6)
+    rho = r ** 2
+    for tol in (1e-5, 1e-7):
+        f = orc.fit(X, 3, tol=tol, max_iter=5000, stop="loading")
+        assert f.status == orc.OK
+        ang = col_angles(f.P, W[:, :3])
+        assert ang.max() <= 1.5 * rho * tol / (1 - rho), (tol, ang)
+        # the stop is the first iteration whose change is below tol: the change
+        # one iteration earlier, |p_(j-1) - p_(j-2)|, was not
+        j = int(f.iters[0])
+        a = orc.fit(X, 1, tol=0.0, max_iter=j - 2)
+        b = orc.fit(X, 1, tol=0.0, max_iter=j - 1)
+        assert angle(a.P[:, 0], b.P[:, 0]) >= tol * 0.999
+        assert angle(b.P[:, 0], f.P[:, 0]) < tol
