@@ -34,7 +34,7 @@ struct Plan {
     int ncolblk, nsplit_t, nsplit_n, nbM, nbN;
     int64_t rows_per_split, cols_per_split;
     size_t off_state, off_R, off_t, off_qpart, off_tpart, off_qy, off_ty, off_cpart, off_c,
-        off_sq, off_cn, off_p, off_sig, total;
+        off_sq, off_cn, off_p, off_pprev, off_sig, total;
 };
 
 Plan make_plan(int64_t M, int64_t N, int64_t K, size_t esize)
@@ -75,6 +75,7 @@ Plan make_plan(int64_t M, int64_t N, int64_t K, size_t esize)
     pl.off_sq = o;    o = align_up(o + (size_t)nbmax * 2 * 8);
     pl.off_cn = o;    o = align_up(o + (size_t)N * 8);
     pl.off_p = o;     o = align_up(o + (size_t)N * 8);
+    pl.off_pprev = o; o = align_up(o + (size_t)N * 8);
     pl.off_sig = o;   o = align_up(o + (size_t)K * 8);
     pl.total = o;
     return pl;
@@ -161,6 +162,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
     double *sq = reinterpret_cast<double *>(base + pl.off_sq);
     double *cn = reinterpret_cast<double *>(base + pl.off_cn);
     double *p = reinterpret_cast<double *>(base + pl.off_p);
+    double *pprev = reinterpret_cast<double *>(base + pl.off_pprev);
     double *sig = reinterpret_cast<double *>(base + pl.off_sig);
     E *T = static_cast<E *>(rs->T);
     E *P = static_cast<E *>(rs->P);
@@ -235,8 +237,8 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
                     (void)hipEventRecord(ev[4 * i + 1], s);
                 if (kk > 0)
                     L::gs_dot(qpart, pl.nsplit_t, N, N, P, N, kk, qy, cpart, c, st, kCntDotN, s);
-                L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, nullptr, sq, st, 0, tol,
-                            limit, replay, tiny, op->stop, s);
+                L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, pprev, nullptr, sq, st, 0,
+                            tol, limit, replay, tiny, op->stop, s);
                 if (prof)
                     (void)hipEventRecord(ev[4 * i + 2], s);
                 L::gemv_n(R, pl.ldr, N, p, pl.cols_per_split, pl.nsplit_n, tpart, st, s);
@@ -244,8 +246,8 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
                     (void)hipEventRecord(ev[4 * i + 3], s);
                 if (kk > 0)
                     L::gs_dot(tpart, pl.nsplit_n, pl.ldr, M, T, M, kk, ty, cpart, c, st, kCntDotM, s);
-                L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, t, sq, st, 1,
-                            tol, limit, replay, tiny, op->stop, s);
+                L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, nullptr, t, sq,
+                            st, 1, tol, limit, replay, tiny, op->stop, s);
             }
             enq += n;
             if (!read_state())
@@ -295,7 +297,7 @@ struct FusedPlan {
     int64_t M, N, K, PR, NP, ldp;
     int cpt, NT, G, nsplit_cn, nbM, nbN;
     size_t off_state, off_A, off_tE, off_td, off_qpart, off_dpart, off_d, off_c, off_qy, off_p,
-        off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
+        off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
 };
 
 int device_cu_count()
@@ -356,6 +358,7 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     f.off_c = o;      o = align_up(o + (size_t)(K + 1) * 8);
     f.off_qy = o;     o = align_up(o + (size_t)N * 8);
     f.off_p = o;      o = align_up(o + (size_t)N * 8);
+    f.off_pprev = o;  o = align_up(o + (size_t)N * 8);
     f.off_cpart = o;  o = align_up(o + (size_t)nbmax * (K + 1) * 8);
     f.off_sq = o;     o = align_up(o + (size_t)nbmax * 2 * 8);
     f.off_cnpart = o; o = align_up(o + (size_t)f.nsplit_cn * N * 8);
@@ -401,6 +404,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     double *cvec = reinterpret_cast<double *>(base + f.off_c);
     double *qy = reinterpret_cast<double *>(base + f.off_qy);
     double *p = reinterpret_cast<double *>(base + f.off_p);
+    double *pprev = reinterpret_cast<double *>(base + f.off_pprev);
     double *cpart = reinterpret_cast<double *>(base + f.off_cpart);
     double *sq = reinterpret_cast<double *>(base + f.off_sq);
     double *cnpart = reinterpret_cast<double *>(base + f.off_cnpart);
@@ -475,8 +479,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, 0, qpart, dpart,
                 dvec, st, s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
-        L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit, replay,
-                    tiny, stop, s);
+        L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol, limit,
+                    replay, tiny, stop, s);
         int32_t enq = 0;
         int batch = 4;
         bool have = false;
@@ -491,11 +495,11 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                         dpart, dvec, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
-                L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, tE, sq, st, 1, tol, limit,
-                            replay, tiny, stop, s);
+                L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, nullptr, tE, sq, st, 1, tol,
+                            limit, replay, tiny, stop, s);
                 F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);
-                L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, nullptr, sq, st, 0, tol, limit,
-                            replay, tiny, stop, s);
+                L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol,
+                            limit, replay, tiny, stop, s);
             }
             enq += n;
             if (!read_state())

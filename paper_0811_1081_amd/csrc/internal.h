@@ -61,8 +61,8 @@ struct Launch {
                        int counter, hipStream_t s);
     static void gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
                          const double *y, const E *Q, int64_t ldq, int k, const double *c,
-                         double *ydst, E *edst, double *sqpart, LoopState *st, int side,
-                         double tol, int32_t limit, int replay, double tiny, int stop,
+                         double *ydst, double *yprev, E *edst, double *sqpart, LoopState *st,
+                         int side, double tol, int32_t limit, int replay, double tiny, int stop,
                          hipStream_t s);
     static void degenerate_p(const E *P, int64_t N, int k, double *p, LoopState *st, hipStream_t s);
     static void finalize_comp(const E *t, int64_t M, int64_t N, const double *p, int k, int gs,

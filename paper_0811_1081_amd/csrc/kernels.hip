@@ -381,10 +381,12 @@ __global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ pa
 }
 
 // x = y - Q c (one classical Gram-Schmidt pass), squared norm; the last
-// workgroup finishes the norm.  side 0 (loading): x kept in FP64 (ydst, which
-// holds the previous loading on entry), |p| stored, and the change of the unit
-// loading |p_j - s p_(j-1)| = sqrt(2 - 2 |cos|) (s the sign of the cosine;
-// infinite for the first loading of a component).  side 1 (score): x stored
+// workgroup finishes the norm.  side 0 (loading): x kept in FP64 (ydst, whose
+// previous content moves to yprev), |p| stored, and -- for the loading stop --
+// the change of the unit loading |p_j - s p_(j-1)| (s = +-1 aligning the signs;
+// infinite for the first loading of a component), summed element by element
+// by the last workgroup so that it resolves changes far below sqrt(eps).
+// side 1 (score): x stored
 // in the element type (edst), sigma, then the stop test -- the relative sigma
 // test of the host programs (Appendices 1, 3) when stop == 0, the loading
 // change below tol when stop == 1, or the replayed count -- and the loop state.
@@ -396,6 +398,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
                                                      const E *__restrict__ Q, int64_t ldq, int k,
                                                      const double *__restrict__ c,
                                                      double *__restrict__ ydst,
+                                                     double *__restrict__ yprev,
                                                      E *__restrict__ edst,
                                                      double *__restrict__ sqpart, LoopState *st,
                                                      int side, double tol, int32_t limit,
@@ -431,7 +434,9 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
     double dot_old = 0.0;
     if (r < L) {
         if (side == 0) {
-            dot_old = v * ydst[r];
+            const double o = ydst[r];
+            dot_old = v * o;
+            yprev[r] = o;
             ydst[r] = v;
         } else {
             edst[r] = (E)v;
@@ -457,17 +462,22 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
     tot = block_sum(tot, red);
     if (side == 0)
         dtot = block_sum(dtot, red);
+    const double nrm = sqrt(tot);
+    double dp = INFINITY;
+    if (side == 0 && stop == 1 && st->iter > 0 && nrm > 0.0 && st->pnorm > 0.0) {
+        // |p/|p| - s q/|q||^2 over the whole vector (fixed order, this workgroup)
+        const double a = 1.0 / nrm, bq = (dtot >= 0.0 ? 1.0 : -1.0) / st->pnorm;
+        double ss = 0.0;
+        for (int64_t i = threadIdx.x; i < L; i += kBlock) {
+            const double dd = ydst[i] * a - yprev[i] * bq;
+            ss += dd * dd;
+        }
+        dp = sqrt(block_sum(ss, red));
+    }
     if (threadIdx.x != 0)
         return;
     st->counter[side == 0 ? kCntApplyN : kCntApplyM] = 0;
-    const double nrm = sqrt(tot);
     if (side == 0) {
-        const double old = st->pnorm;
-        double dp = INFINITY;
-        if (st->iter > 0 && nrm > 0.0 && old > 0.0) {
-            const double cs1 = fmin(1.0, fabs(dtot) / (nrm * old));
-            dp = sqrt(fmax(0.0, 2.0 - 2.0 * cs1));
-        }
         st->dp = dp;
         st->pnorm = nrm;
         if (!(nrm >= tiny)) { // counts as the iteration in which it happened
@@ -672,12 +682,12 @@ void Launch<E>::gs_dot(const double *part, int nsplit, int64_t ldpart, int64_t L
 template <typename E>
 void Launch<E>::gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t L,
                          const double *y, const E *Q, int64_t ldq, int k, const double *c,
-                         double *ydst, E *edst, double *sqpart, LoopState *st, int side,
-                         double tol, int32_t limit, int replay, double tiny, int stop,
+                         double *ydst, double *yprev, E *edst, double *sqpart, LoopState *st,
+                         int side, double tol, int32_t limit, int replay, double tiny, int stop,
                          hipStream_t s)
 {
     hipLaunchKernelGGL(k_gs_apply<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, part, nsplit,
-                       ldpart, L, y, Q, ldq, k, c, ydst, edst, sqpart, st, side, tol, limit,
+                       ldpart, L, y, Q, ldq, k, c, ydst, yprev, edst, sqpart, st, side, tol, limit,
                        replay, tiny, stop);
 }
 

@@ -129,7 +129,7 @@ def test_bf16_then_fp32_refinement_reaches_1e5(orc):
     q = gp.quantize(Xd, "bf16")
     b = gp.fit(q, K, tol=1e-4, max_iter=2000, stop="loading")
     err_b = col_angles(b["P"].cpu().numpy(), Q[:, :K])
-    r = gp.fit(Xd, K, tol=2e-6, max_iter=2000, stop="loading", implicit=True, init="given",
+    r = gp.fit(Xd, K, tol=1e-6, max_iter=2000, stop="loading", implicit=True, init="given",
                T0=b["T"])
     err_r = col_angles(r["P"].cpu().numpy(), Q[:, :K])
     assert err_r.max() <= 1e-5, err_r
