@@ -68,6 +68,9 @@ def main():
     ap.add_argument("--max-iter", type=int, default=1000)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--implicit", action="store_true", help="implicit deflation (X read-only)")
+    ap.add_argument("--form", default="f32", choices=["f32", "bf16", "e4m3"],
+                    help="storage of X streamed by the iteration (bf16/e4m3: quantised codes, "
+                         "implicit deflation)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
@@ -89,7 +92,11 @@ def main():
     X = synth.case_large_f32(M, N)
     log("generated in %.1f s" % (time.perf_counter() - t0))
     Xd = gp.column_major(torch.from_numpy(X).to("cuda"))
-    ws_bytes = gp.workspace_bytes(Xd, K, implicit=args.implicit)
+    Xfit = Xd
+    if args.form != "f32":
+        Xfit = gp.quantize(Xd, args.form)
+        args.implicit = True
+    ws_bytes = gp.workspace_bytes(Xfit, K, implicit=args.implicit)
     ws = torch.empty(ws_bytes + 256, dtype=torch.uint8, device="cuda")
     ws_view = ws[(-ws.data_ptr()) % 256:]
     torch.cuda.synchronize()
@@ -102,7 +109,7 @@ def main():
         del a, b
 
     def step(profile=None):
-        return gp.fit(Xd, K, tol=args.tol, max_iter=args.max_iter, workspace=ws_view,
+        return gp.fit(Xfit, K, tol=args.tol, max_iter=args.max_iter, workspace=ws_view,
                       profile=profile, implicit=args.implicit)
 
     for i in range(args.warmup):
@@ -150,12 +157,15 @@ def main():
     res = {
         "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": {"f32": "f32", "bf16": "bf16", "e4m3": "fp8_e4m3"}[args.form],
         "data": "synthetic",
         "config": {"workload": "large_f32_lowrank_%dx%d_K%d" % (M, N, K), "M": M, "N": N,
                    "K": K, "tol": args.tol, "max_iter": args.max_iter, "algo": "gs",
-                   "form": "plain_fp32_%s_%s" % ("implicit" if args.implicit else "explicit",
-                                                 "single_pass" if prof.single_pass else "two_pass")},
+                   "form": "%s_%s_%s" % ({"f32": "plain_fp32", "bf16": "bf16_codes",
+                                           "e4m3": "fp8_e4m3_codes"}[args.form],
+                                          "implicit" if args.implicit else "explicit",
+                                          "single_pass" if prof.single_pass else "two_pass")},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,

@@ -453,31 +453,38 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
 // Gram-Schmidt coefficients d = V_(k)^T t (FP64, finished by the last
 // workgroup).  q is left as per-workgroup partials q_part[g][j].
 
-template <class C, int CPT, bool FIRST>
-__global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ A, int64_t N,
-                                              int64_t NP, int64_t ldp, int64_t M,
-                                              const float *__restrict__ scale,
-                                              const double *__restrict__ p,
-                                              const typename C::acc *__restrict__ t_in,
-                                              double *__restrict__ t_out,
-                                              const typename C::acc *__restrict__ V, int kd,
-                                              typename C::acc *__restrict__ q_part,
-                                              double *__restrict__ d_part,
-                                              double *__restrict__ d, LoopState *st)
+// Variants: PL = false keeps the loading in registers (at most 512 threads,
+// 8 waves per compute unit); PL = true keeps it in LDS, freeing registers for
+// 1024 threads (16 waves per compute unit).  PIPE = true prefetches the next
+// panel into a second register buffer; PIPE = false holds one panel and is
+// meant for two workgroups per compute unit.  `skew` rotates the order in
+// which a workgroup walks its panels so that workgroups start at different
+// phases.
+template <class C, int CPT, bool FIRST, bool PL, bool PIPE>
+__global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
+    const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
+    const float *__restrict__ scale, const double *__restrict__ p,
+    const typename C::acc *__restrict__ t_in, double *__restrict__ t_out,
+    const typename C::acc *__restrict__ V, int kd, typename C::acc *__restrict__ q_part,
+    double *__restrict__ d_part, double *__restrict__ d, LoopState *st, int skew)
 {
     if (st->done)
         return;
     using E = typename C::acc;
     using RT = typename C::raw;
     constexpr int PR = C::PR;
-    __shared__ E red[2][8][PR];
+    __shared__ E red[2][16][PR];
     __shared__ int last;
+    extern __shared__ unsigned char pass_smem[];
+    E *pl = reinterpret_cast<E *>(pass_smem);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int NT = blockDim.x, nw = NT >> 6;
     const int64_t G = gridDim.x, g = blockIdx.x;
     const int64_t b0 = NP * g / G, b1 = NP * (g + 1) / G;
+    const int64_t cnt = b1 - b0;
+    const int64_t off = (skew && cnt > 0) ? (g * 37) % cnt : 0;
 
-    E preg[CPT];
+    E preg[PL ? 1 : CPT];
     E q[CPT];
     const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
 #pragma unroll
@@ -489,22 +496,35 @@ __global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ 
             if constexpr (C::scaled)
                 pj *= (double)scale[j];
         }
-        preg[c] = (E)pj;
+        if constexpr (PL)
+            pl[tid + c * NT] = (E)pj;
+        else
+            preg[c] = (E)pj;
         q[c] = E(0);
     }
+    if constexpr (PL)
+        __syncthreads();
+    auto pval = [&](int c) -> E {
+        if constexpr (PL)
+            return pl[tid + c * NT];
+        else
+            return preg[c];
+    };
     // The panel width ldp = NT * CPT covers every lane's columns (columns >= N
     // are zero), so every lane always loads: no divergent branch around the
     // loads, and the wait for one panel does not also wait for the prefetched
     // next one.  Lanes past N carry p = 0 and never store q.
-    RT bufA[CPT], bufB[CPT];
+    RT bufA[CPT], bufB[PIPE ? CPT : 1];
     const uint32_t lane_off = (uint32_t)tid * 16u;
-    const uint32_t col_step = (uint32_t)NT * 16u;
+    const int64_t col_step = (int64_t)NT * 16;
+    // uniform (scalar) base per panel and column block + one per-lane offset
     auto load = [&](RT *buf, int64_t b) {
-        const unsigned char *base = A + b * ldp * 16 + lane_off;
+        const unsigned char *pb = A + b * ldp * 16;
 #pragma unroll
-        for (int c = 0; c < CPT; ++c)
-            buf[c] = __builtin_nontemporal_load(
-                reinterpret_cast<const RT *>(base + (uint32_t)c * col_step));
+        for (int c = 0; c < CPT; ++c) {
+            const unsigned char *cb = pb + c * col_step;
+            buf[c] = __builtin_nontemporal_load(reinterpret_cast<const RT *>(cb + lane_off));
+        }
     };
     auto process = [&](const RT *buf, int64_t b, int slot) {
         E tb[PR];
@@ -521,9 +541,10 @@ __global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ 
             for (int c = 0; c < CPT; ++c) {
                 E e[PR];
                 C::decode(buf[c], e);
+                const E pc = pval(c);
 #pragma unroll
                 for (int r = 0; r < PR; ++r)
-                    tp[r] += e[r] * preg[c];
+                    tp[r] += e[r] * pc;
             }
 #pragma unroll
             for (int r = 0; r < PR; ++r)
@@ -547,33 +568,61 @@ __global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ 
         }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
+            // Decode again rather than keep the decoded values of all CPT
+            // segments alive across the reduction (16 floats per segment for
+            // FP8): the empty asm hides the raw value from common-subexpression
+            // elimination.
+            RT raw = buf[c];
+            if constexpr (C::scaled) {
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    unsigned int x = raw[u];
+                    asm volatile("" : "+v"(x));
+                    raw[u] = x;
+                }
+            }
             E e[PR];
-            C::decode(buf[c], e);
+            C::decode(raw, e);
 #pragma unroll
             for (int r = 0; r < PR; ++r)
                 q[c] += e[r] * tb[r];
         }
     };
 
-    // Software pipeline: panel b+1 is in flight while panel b is reduced.  The
+    // Software pipeline: panel i+1 is in flight while panel i is reduced.  The
     // steady-state loop issues its prefetches unconditionally; the last one or
-    // two panels are peeled.
-    int64_t b = b0;
-    if (b < b1)
-        load(bufA, b);
-    while (b + 2 < b1) {
-        load(bufB, b + 1);
-        process(bufA, b, 0);
-        load(bufA, b + 2);
-        process(bufB, b + 1, 1);
-        b += 2;
-    }
-    if (b + 1 < b1) {
-        load(bufB, b + 1);
-        process(bufA, b, 0);
-        process(bufB, b + 1, 1);
-    } else if (b < b1) {
-        process(bufA, b, 0);
+    // two panels are peeled.  Panel i of this workgroup is b0 + (i + off) % cnt.
+    auto pid = [&](int64_t i) -> int64_t {
+        int64_t k = i + off;
+        if (k >= cnt)
+            k -= cnt;
+        return b0 + k;
+    };
+    int64_t i = 0;
+    if constexpr (PIPE) {
+        if (i < cnt)
+            load(bufA, pid(i));
+        while (i + 2 < cnt) {
+            load(bufB, pid(i + 1));
+            process(bufA, pid(i), 0);
+            load(bufA, pid(i + 2));
+            process(bufB, pid(i + 1), 1);
+            i += 2;
+        }
+        if (i + 1 < cnt) {
+            load(bufB, pid(i + 1));
+            process(bufA, pid(i), 0);
+            process(bufB, pid(i + 1), 1);
+        } else if (i < cnt) {
+            process(bufA, pid(i), 0);
+        }
+    } else {
+        // one panel in registers; latency is hidden by a second workgroup on
+        // the same compute unit
+        for (; i < cnt; ++i) {
+            load(bufA, pid(i));
+            process(bufA, pid(i), (int)(i & 1));
+        }
     }
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -618,7 +667,9 @@ __global__ __launch_bounds__(512) void k_pass(const unsigned char *__restrict__ 
 // Gram-Schmidt coefficients c = P_(k)^T q' (Sec. 2.3), finished by the last
 // workgroup.  `it` is the iteration this launch belongs to: when the
 // component stopped in that iteration only q' is formed (it feeds W); when
-// it stopped earlier the launch does nothing.
+// it stopped earlier the launch does nothing.  Workgroup: 64 columns x 4
+// groups of partials (the partial sums are read with 16 loads in flight per
+// thread and combined in a fixed order).
 template <typename E>
 __global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int64_t G, int64_t N,
                                                const double *__restrict__ W, int kd,
@@ -633,51 +684,57 @@ __global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int
     const int done = st->done;
     if (done && st->iter != it)
         return;
-    __shared__ double ys[256];
-    __shared__ double ds[1024];
+    __shared__ double part4[4][64];
+    __shared__ double ys[64];
     __shared__ int last;
-    const int64_t r0 = (int64_t)blockIdx.x * 256;
-    const int64_t j = r0 + threadIdx.x;
-    double v = 0.0;
-    if (j < N)
-        for (int64_t g = 0; g < G; ++g)
-            v += (double)q_part[g * N + j];
-    double proj = 0.0;
-    for (int i0 = 0; i0 < kd; i0 += 1024) {
-        const int n = min(1024, kd - i0);
-        __syncthreads();
-        for (int i = threadIdx.x; i < n; i += 256)
-            ds[i] = d[i0 + i];
-        __syncthreads();
-        if (j < N)
-            for (int i = 0; i < n; ++i)
-                proj += W[j + (int64_t)(i0 + i) * N] * ds[i];
+    const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * 64;
+    const int64_t j = r0 + lane;
+    double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
+    if (j < N) {
+        int64_t g = grp;
+        for (; g + 12 < G; g += 16) {
+            a0 += (double)q_part[g * N + j];
+            a1 += (double)q_part[(g + 4) * N + j];
+            a2 += (double)q_part[(g + 8) * N + j];
+            a3 += (double)q_part[(g + 12) * N + j];
+        }
+        for (; g < G; g += 4)
+            a0 += (double)q_part[g * N + j];
     }
-    v -= proj;
+    part4[grp][lane] = (a0 + a1) + (a2 + a3);
+    // W d, the W columns split over the four groups
+    double pr = 0.0;
     if (j < N)
-        qy[j] = v;
+        for (int i = grp; i < kd; i += 4)
+            pr += W[j + (int64_t)i * N] * d[i];
+    __syncthreads();
+    const double v = part4[0][lane] + part4[1][lane] + part4[2][lane] + part4[3][lane];
+    __syncthreads();
+    part4[grp][lane] = pr;
+    __syncthreads();
+    const double qv = v - (part4[0][lane] + part4[1][lane] + part4[2][lane] + part4[3][lane]);
+    if (grp == 0) {
+        if (j < N)
+            qy[j] = qv;
+        ys[lane] = j < N ? qv : 0.0;
+    }
     if (done || kg == 0)
         return;
-    ys[threadIdx.x] = j < N ? v : 0.0;
     __syncthreads();
-    const int w = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    for (int i = w; i < kg; i += 4) {
-        const E *q = P + (int64_t)i * N;
-        double s = 0.0;
-        for (int jj = lane; jj < 256; jj += 64)
-            if (r0 + jj < N)
-                s += (double)q[r0 + jj] * ys[jj];
-        s = fwave_sum(s);
+    for (int i = grp; i < kg; i += 4) {
+        const double sv = (j < N) ? (double)P[j + (int64_t)i * N] * ys[lane] : 0.0;
+        const double sum = fwave_sum(sv);
         if (lane == 0)
-            cpart[(int64_t)blockIdx.x * kg + i] = s;
+            cpart[(int64_t)blockIdx.x * kg + i] = sum;
     }
     if (!fused_arrive_last(&st->counter[kCntDotN], &last))
         return;
     for (int i = threadIdx.x; i < kg; i += 256) {
-        double s = 0.0;
+        double sum = 0.0;
         for (int b = 0; b < (int)gridDim.x; ++b)
-            s += cpart[(int64_t)b * kg + i];
-        c[i] = s;
+            sum += cpart[(int64_t)b * kg + i];
+        c[i] = sum;
     }
     if (threadIdx.x == 0)
         st->counter[kCntDotN] = 0;
@@ -786,38 +843,48 @@ void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp,
 }
 
 template <class C, bool FIRST>
-static void launch_pass(int cpt, int G, int NT, const unsigned char *A, int64_t N, int64_t NP,
-                        int64_t ldp, int64_t M, const float *scale, const double *p,
-                        const typename C::acc *t_in, double *t_out, const typename C::acc *V,
-                        int kd, typename C::acc *q_part, double *d_part, double *d,
-                        LoopState *st, hipStream_t s)
+static void launch_pass(int cpt, int G, int NT, int plds, int skew, int pipe,
+                        const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
+                        const float *scale, const double *p, const typename C::acc *t_in,
+                        double *t_out, const typename C::acc *V, int kd,
+                        typename C::acc *q_part, double *d_part, double *d, LoopState *st,
+                        hipStream_t s)
 {
-#define GSPCA_PASS(CP)                                                                           \
-    hipLaunchKernelGGL((k_pass<C, CP, FIRST>), dim3(G), dim3(NT), 0, s, A, N, NP, ldp, M, scale, \
-                       p, t_in, t_out, V, kd, q_part, d_part, d, st)
-    switch (cpt) {
-    case 1: GSPCA_PASS(1); break;
-    case 2: GSPCA_PASS(2); break;
-    case 4: GSPCA_PASS(4); break;
-    case 8: GSPCA_PASS(8); break;
-    default: GSPCA_PASS(16); break;
+    const size_t lds = plds ? (size_t)cpt * NT * sizeof(typename C::acc) : 0;
+#define GSPCA_PASS(CP, PLV, PIV)                                                               \
+    hipLaunchKernelGGL((k_pass<C, CP, FIRST, PLV, PIV>), dim3(G), dim3(NT), lds, s, A, N, NP,  \
+                       ldp, M, scale, p, t_in, t_out, V, kd, q_part, d_part, d, st, skew)
+#define GSPCA_PASS_CPT(PLV, PIV)                                                               \
+    switch (cpt) {                                                                             \
+    case 1: GSPCA_PASS(1, PLV, PIV); break;                                                    \
+    case 2: GSPCA_PASS(2, PLV, PIV); break;                                                    \
+    case 4: GSPCA_PASS(4, PLV, PIV); break;                                                    \
+    case 8: GSPCA_PASS(8, PLV, PIV); break;                                                    \
+    default: GSPCA_PASS(16, PLV, PIV); break;                                                  \
     }
+    if (plds) {
+        if (pipe) { GSPCA_PASS_CPT(true, true) } else { GSPCA_PASS_CPT(true, false) }
+    } else {
+        if (pipe) { GSPCA_PASS_CPT(false, true) } else { GSPCA_PASS_CPT(false, false) }
+    }
+#undef GSPCA_PASS_CPT
 #undef GSPCA_PASS
 }
 
 template <int F>
-void Fused<F>::pass(int first, int cpt, int G, int NT, const unsigned char *A, int64_t N,
-                    int64_t NP, int64_t ldp, int64_t M, const float *scale, const double *p,
-                    const E *t_in, double *t_out, const E *V, int kd, E *q_part, double *d_part,
-                    double *d, LoopState *st, hipStream_t s)
+void Fused<F>::pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
+                    const unsigned char *A,
+                    int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
+                    const double *p, const E *t_in, double *t_out, const E *V, int kd, E *q_part,
+                    double *d_part, double *d, LoopState *st, hipStream_t s)
 {
     using C = typename CodecOf<F>::type;
     if (first)
-        launch_pass<C, true>(cpt, G, NT, A, N, NP, ldp, M, scale, p, t_in, t_out, V, 0, q_part,
-                             d_part, d, st, s);
+        launch_pass<C, true>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
+                             t_out, V, 0, q_part, d_part, d, st, s);
     else
-        launch_pass<C, false>(cpt, G, NT, A, N, NP, ldp, M, scale, p, t_in, t_out, V, kd, q_part,
-                              d_part, d, st, s);
+        launch_pass<C, false>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
+                              t_out, V, kd, q_part, d_part, d, st, s);
 }
 
 template <int F>
@@ -825,7 +892,7 @@ void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int
                      const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                      LoopState *st, int it, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 256)), dim3(256), 0, s, q_part, G, N, W, kd, d, P,
+    hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 64)), dim3(256), 0, s, q_part, G, N, W, kd, d, P,
                        kg, qy, cpart, c, st, it);
 }
 

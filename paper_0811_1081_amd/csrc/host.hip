@@ -12,6 +12,7 @@
 // back twice per iteration).
 #include <float.h>
 #include <math.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <algorithm>
@@ -296,6 +297,8 @@ constexpr int64_t kFusedMaxN = 8192; // columns held in registers: 512 threads x
 struct FusedPlan {
     int64_t M, N, K, PR, NP, ldp;
     int cpt, NT, G, nsplit_cn, nbM, nbN;
+    int plds, skew, pipe; // pass-kernel variant: loading in LDS (1024 threads), panel-order
+                          // skew, register double buffering (else two workgroups per CU)
     size_t off_state, off_A, off_tE, off_td, off_qpart, off_dpart, off_d, off_c, off_qy, off_p,
         off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
 };
@@ -339,12 +342,24 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     const size_t esize = fmt == kFmtF64 ? 8 : 4; // arithmetic / output element
     f.NP = cdiv(M, f.PR);
     panel_width(N, &f.cpt, &f.NT, &f.ldp);
-    const int64_t per_cu = std::max<int64_t>(1, 512 / f.NT);
+    // Variant knobs (GSPCA_PASS_LDS=1: loading in LDS with twice the threads;
+    // GSPCA_PASS_SKEW=1: rotated panel order); the panel width is unchanged.
+    const char *e_lds = getenv("GSPCA_PASS_LDS");
+    const char *e_skew = getenv("GSPCA_PASS_SKEW");
+    const char *e_pipe = getenv("GSPCA_PASS_PIPE");
+    f.plds = (e_lds && e_lds[0] == '1' && f.cpt >= 2 && f.NT <= 512) ? 1 : 0;
+    f.skew = (e_skew && e_skew[0] == '1') ? 1 : 0;
+    f.pipe = (e_pipe && e_pipe[0] == '0') ? 0 : 1;
+    if (f.plds) {
+        f.cpt /= 2;
+        f.NT *= 2;
+    }
+    const int64_t per_cu = std::max<int64_t>(1, (f.plds ? 1024 : 512) / f.NT) * (f.pipe ? 1 : 2);
     f.G = (int)std::max<int64_t>(1, std::min<int64_t>(ncu * per_cu, std::max<int64_t>(1, f.NP / 2)));
     f.nsplit_cn = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cdiv(N, 64)), f.NP));
     f.nbM = (int)cdiv(M, kBlock);
     f.nbN = (int)cdiv(N, kBlock);
-    const int nbmax = std::max(f.nbM, f.nbN);
+    const int nbmax = (int)std::max<int64_t>(std::max(f.nbM, f.nbN), cdiv(N, 64));
     const size_t len = (size_t)(f.NP * f.PR);
     const bool quantised = fmt == kFmtBF16 || fmt == kFmtFP8; // Q is the caller's
     size_t o = 0;
@@ -476,8 +491,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, op->replay_start_col};
         F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-        F::pass(1, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, 0, qpart, dpart,
-                dvec, st, s);
+        F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, 0,
+                qpart, dpart, dvec, st, s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
         L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol, limit,
                     replay, tiny, stop, s);
@@ -491,8 +506,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 const int it = enq + i + 1;
                 if (prof)
                     (void)hipEventRecord(ev[2 * i], s);
-                F::pass(0, f.cpt, f.G, f.NT, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, kg, qpart,
-                        dpart, dvec, st, s);
+                F::pass(0, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE, td,
+                        T, kg, qpart, dpart, dvec, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
                 L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, nullptr, tE, sq, st, 1, tol,
