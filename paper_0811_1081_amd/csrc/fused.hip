@@ -457,9 +457,8 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
 // 8 waves per compute unit); PL = true keeps it in LDS, freeing registers for
 // 1024 threads (16 waves per compute unit).  PIPE = true prefetches the next
 // panel into a second register buffer; PIPE = false holds one panel and is
-// meant for two workgroups per compute unit.  `skew` rotates the order in
-// which a workgroup walks its panels so that workgroups start at different
-// phases.
+// meant for two workgroups per compute unit.  `skew` != 0 interleaves the
+// panel assignment (see below; requires kd <= blockDim).
 template <class C, int CPT, bool FIRST, bool PL, bool PIPE>
 __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
@@ -480,9 +479,13 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int NT = blockDim.x, nw = NT >> 6;
     const int64_t G = gridDim.x, g = blockIdx.x;
-    const int64_t b0 = NP * g / G, b1 = NP * (g + 1) / G;
-    const int64_t cnt = b1 - b0;
-    const int64_t off = (skew && cnt > 0) ? (g * 37) % cnt : 0;
+    // order 0: workgroup g owns the contiguous panels [b0, b1); order 1: it
+    // owns panels g, g + G, g + 2G, ... so that at any moment the grid reads
+    // one contiguous stretch of the matrix.
+    const bool inter = skew != 0;
+    const int64_t b0 = inter ? g : NP * g / G, b1 = inter ? NP : NP * (g + 1) / G;
+    const int64_t cnt = inter ? (g < NP ? (NP - 1 - g) / G + 1 : 0) : b1 - b0;
+    double dacc = 0.0;
 
     E preg[PL ? 1 : CPT];
     E q[CPT];
@@ -523,7 +526,11 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
             const unsigned char *cb = pb + c * col_step;
+#ifdef GSPCA_PLAIN_LOADS
+            buf[c] = *reinterpret_cast<const RT *>(cb + lane_off);
+#else
             buf[c] = __builtin_nontemporal_load(reinterpret_cast<const RT *>(cb + lane_off));
+#endif
         }
     };
     auto process = [&](const RT *buf, int64_t b, int slot) {
@@ -565,6 +572,16 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
                 const int64_t m = b * PR + tid;
                 t_out[m] = (double)tb[tid];
             }
+            if (inter && tid < kd) {
+                // Gram-Schmidt coefficient d_tid over this panel's rows
+                const E *vc = V + (int64_t)tid * M;
+#pragma unroll
+                for (int r = 0; r < PR; ++r) {
+                    const int64_t m = b * PR + r;
+                    if (m < M)
+                        dacc += (double)vc[m] * (double)tb[r];
+                }
+            }
         }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -592,12 +609,7 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     // Software pipeline: panel i+1 is in flight while panel i is reduced.  The
     // steady-state loop issues its prefetches unconditionally; the last one or
     // two panels are peeled.  Panel i of this workgroup is b0 + (i + off) % cnt.
-    auto pid = [&](int64_t i) -> int64_t {
-        int64_t k = i + off;
-        if (k >= cnt)
-            k -= cnt;
-        return b0 + k;
-    };
+    auto pid = [&](int64_t i) -> int64_t { return inter ? g + i * G : b0 + i; };
     int64_t i = 0;
     if constexpr (PIPE) {
         if (i < cnt)
@@ -636,19 +648,24 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     }
     if (FIRST || kd == 0)
         return;
-    // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows]:
-    // one wave per column of V, coalesced along the rows just written.
-    __threadfence();
-    __syncthreads();
-    const int64_t r0 = b0 * PR, r1 = min(b1 * PR, M);
-    for (int i = w; i < kd; i += nw) {
-        const E *vc = V + (int64_t)i * M;
-        double s = 0.0;
-        for (int64_t m = r0 + lane; m < r1; m += 64)
-            s += (double)vc[m] * t_out[m];
-        s = fwave_sum(s);
-        if (lane == 0)
-            d_part[g * kd + i] = s;
+    if (inter) {
+        if (tid < kd)
+            d_part[g * kd + tid] = dacc;
+    } else {
+        // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows]:
+        // one wave per column of V, coalesced along the rows just written.
+        __threadfence();
+        __syncthreads();
+        const int64_t r0 = b0 * PR, r1 = min(b1 * PR, M);
+        for (int i = w; i < kd; i += nw) {
+            const E *vc = V + (int64_t)i * M;
+            double s = 0.0;
+            for (int64_t m = r0 + lane; m < r1; m += 64)
+                s += (double)vc[m] * t_out[m];
+            s = fwave_sum(s);
+            if (lane == 0)
+                d_part[g * kd + i] = s;
+        }
     }
     if (!fused_arrive_last(&st->counter[kCntDotM], &last))
         return;
