@@ -180,6 +180,58 @@ size_t gspca_quantized_bytes(int64_t M, int64_t N, int32_t dtype);
 gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int32_t dtype,
                             void *Q, float *col_scale, void *ws, size_t ws_bytes, void *stream);
 
+/* ---- Batched fits: many independent FP32 problems in one persistent launch.
+ * Each problem is an FP32 column-major X (M <= 4096, N <= 1024,
+ * 1 <= K <= min(M, N, 64)) with its own outputs, as in gspca_result, plus an
+ * int32 status word written by the device (0 OK, 1 NOT_CONVERGED,
+ * -4 ENONFINITE).  GS-PCA with implicit deflation (X is never written); the
+ * options' algo must be GS, init MAXNORM or COLUMN_K; replay arrays are taken
+ * per problem.  All pointers are device pointers. */
+typedef struct {
+    const float *X;
+    int64_t ldx;
+    int64_t M, N, K;
+    float *T;            /* M x K, leading dimension M                          */
+    float *P;            /* N x K, leading dimension N                          */
+    double *lambda;      /* K                                                   */
+    double *sigma;       /* K, nullable                                         */
+    int32_t *iters;      /* K, nullable                                         */
+    int32_t *start_col;  /* K, nullable                                         */
+    const int32_t *replay_iters;     /* K, nullable (testing)                   */
+    const int32_t *replay_start_col; /* K, nullable (testing)                   */
+    int32_t *status;     /* one int32, nullable                                 */
+} gspca_batch_problem;
+
+/* Launch plan filled by gspca_batched_prepare (host memory, opaque). */
+typedef struct {
+    unsigned char opaque[256];
+} gspca_batch_plan;
+
+/* Device workspace for a batch (problem table, queue, per-problem X^T V). */
+size_t gspca_batched_workspace_bytes(const gspca_batch_problem *probs, int32_t nprob);
+
+/* Validate the problems (host array of descriptors), write the descriptor
+ * table -- sorted by decreasing M*N so that the queue hands out the largest
+ * problems first -- into `ws`, and fill `plan` with a default launch shape.
+ * Synchronises `stream`.  Not capturable. */
+gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t nprob,
+                                   const gspca_options *opt, void *ws, size_t ws_bytes,
+                                   gspca_batch_plan *plan, void *stream);
+
+/* Enqueue the whole batch: one queue-reset kernel and one persistent kernel.
+ * No host synchronisation and no memset, so the call can be captured in a
+ * hipGraph and replayed (each replay refits every problem).  The status words
+ * are valid once the stream has reached the end of the launch. */
+gspca_status gspca_batched_launch(const gspca_batch_plan *plan, void *stream);
+
+/* Autotuner: time the launch for each candidate shape (threads per
+ * workgroup x workgroups per compute unit, within the LDS the problems need)
+ * and keep the fastest in `plan`.  Runs the batch several times (outputs are
+ * overwritten with the same results).  When the environment variable
+ * GSPCA_TUNE_CACHE names a file, results are looked up there first and
+ * recorded there (one JSON object per line, keyed by the batch signature). */
+gspca_status gspca_batched_tune(gspca_batch_plan *plan, void *stream);
+
 /* Convenience forms: GS-PCA with the max-norm start and the relative
  * sigma test, FP64 or FP32 data (ldx = M).  They allocate and free their own
  * workspace with hipMalloc/hipFree (ENOMEM if that fails) and synchronise

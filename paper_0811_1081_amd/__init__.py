@@ -19,8 +19,8 @@ from ._binding import (BF16, EDEVICE, EINVAL, ENOMEM, ENONFINITE, EWORKSPACE, F3
                        NOT_CONVERGED, OK, STOP_LOADING, STOP_SIGMA_REL, GspcaError,
                        LibraryMissing, Profile, status_string)
 
-__all__ = ["fit", "quantize", "Quantized", "workspace_bytes", "column_major", "status_string",
-           "GspcaError", "LibraryMissing", "Profile", "load"]
+__all__ = ["fit", "quantize", "Quantized", "Batch", "workspace_bytes", "column_major",
+           "status_string", "GspcaError", "LibraryMissing", "Profile", "load"]
 
 _ALGOS = {"gs": GS, "nipals": NIPALS}
 _INITS = {"maxnorm": INIT_MAXNORM, "column_k": INIT_COLUMN_K, "given": INIT_GIVEN}
@@ -191,3 +191,81 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
 def ctypes_stream(stream):
     """Raw hipStream_t handle of a torch stream."""
     return stream.cuda_stream
+
+
+class Batch:
+    """Many independent FP32 GS-PCA problems fitted in one persistent launch.
+
+        b = Batch([X0, X1, ...], K=[8, 8, ...], tol=1e-6)   # column-major cuda float32
+        b.launch(); torch.cuda.synchronize()                # or capture launch() in a graph
+        b.T[i], b.P[i], b.lam[i], b.iters[i], b.status
+
+    Outputs are preallocated device tensors; every launch refits all problems."""
+
+    def __init__(self, Xs, K, tol=1e-6, max_iter=1000, init="maxnorm", stop="sigma",
+                 replay_iters=None, replay_start=None, stream=None):
+        import torch
+        L = _b.load()
+        n = len(Xs)
+        Ks = list(K) if hasattr(K, "__len__") else [int(K)] * n
+        self.Xs = Xs
+        dev = Xs[0].device
+        self.T, self.P, self.lam, self.sigma, self.iters, self.start_col = [], [], [], [], [], []
+        self.status = torch.zeros(n, dtype=torch.int32, device=dev)
+        arr = (_b.BatchProblem * n)()
+        self._keep = [replay_iters, replay_start]
+        for i, X in enumerate(Xs):
+            if X.dtype != torch.float32 or X.stride(0) != 1 or not X.is_cuda:
+                raise ValueError("batched problems must be column-major float32 device matrices")
+            M, N = X.shape
+            k = int(Ks[i])
+            T = torch.empty_strided((M, k), (1, M), dtype=torch.float32, device=dev)
+            P = torch.empty_strided((N, k), (1, N), dtype=torch.float32, device=dev)
+            lam = torch.empty(k, dtype=torch.float64, device=dev)
+            sig = torch.empty(k, dtype=torch.float64, device=dev)
+            it = torch.empty(k, dtype=torch.int32, device=dev)
+            sc = torch.empty(k, dtype=torch.int32, device=dev)
+            self.T.append(T); self.P.append(P); self.lam.append(lam); self.sigma.append(sig)
+            self.iters.append(it); self.start_col.append(sc)
+            ri = replay_iters[i].data_ptr() if replay_iters is not None else None
+            rs = replay_start[i].data_ptr() if replay_start is not None else None
+            arr[i] = _b.BatchProblem(X.data_ptr(), X.stride(1), M, N, k, T.data_ptr(),
+                                     P.data_ptr(), lam.data_ptr(), sig.data_ptr(), it.data_ptr(),
+                                     sc.data_ptr(), ri, rs, self.status.data_ptr() + 4 * i)
+        self._arr = arr
+        nbytes = int(L.gspca_batched_workspace_bytes(arr, n))
+        if nbytes == 0:
+            raise GspcaError(EINVAL)
+        self._ws, wptr = _workspace(nbytes, dev)
+        op = _options("gs", init, tol, max_iter, implicit=True, stop=stop)
+        self.plan = _b.BatchPlan()
+        if stream is None:
+            stream = torch.cuda.current_stream(dev)
+        st = int(L.gspca_batched_prepare(arr, n, op, wptr, nbytes, self.plan,
+                                         ctypes_stream(stream)))
+        if st != OK:
+            raise GspcaError(st)
+
+    def launch(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.Xs[0].device)
+        st = int(_b.load().gspca_batched_launch(self.plan, ctypes_stream(stream)))
+        if st != OK:
+            raise GspcaError(st)
+
+    def tune(self, stream=None):
+        import torch
+        if stream is None:
+            stream = torch.cuda.current_stream(self.Xs[0].device)
+        st = int(_b.load().gspca_batched_tune(self.plan, ctypes_stream(stream)))
+        if st != OK:
+            raise GspcaError(st)
+
+    def shape(self):
+        """(threads per workgroup, workgroups per compute unit) of the current plan."""
+        raw = bytes(self.plan.opaque)
+        import struct
+        # PlanImpl: magic(8) items(8) order(8) queue(8) nprob(4) threads(4) occ(4)
+        nprob, threads, occ = struct.unpack_from("<iii", raw, 32)
+        return threads, occ

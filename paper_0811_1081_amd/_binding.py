@@ -24,7 +24,8 @@ INIT_MAXNORM, INIT_COLUMN_K, INIT_GIVEN = 0, 1, 2
 EXPORTS = (
     "gspca_default_options", "gspca_workspace_bytes", "gspca_fit_ex", "gspca_fit",
     "gspca_fit_f32", "gspca_status_string", "gspca_version", "gspca_quantized_bytes",
-    "gspca_quantize",
+    "gspca_quantize", "gspca_batched_workspace_bytes", "gspca_batched_prepare",
+    "gspca_batched_launch", "gspca_batched_tune",
 )
 
 
@@ -49,6 +50,19 @@ class Profile(ctypes.Structure):
                 ("gemv_t_launches", ctypes.c_int64), ("gemv_n_launches", ctypes.c_int64),
                 ("iterations", ctypes.c_int64), ("bytes_per_pass", ctypes.c_int64),
                 ("single_pass", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class BatchProblem(ctypes.Structure):
+    _fields_ = [("X", ctypes.c_void_p), ("ldx", ctypes.c_int64), ("M", ctypes.c_int64),
+                ("N", ctypes.c_int64), ("K", ctypes.c_int64), ("T", ctypes.c_void_p),
+                ("P", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
+                ("iters", ctypes.c_void_p), ("start_col", ctypes.c_void_p),
+                ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
+                ("status", ctypes.c_void_p)]
+
+
+class BatchPlan(ctypes.Structure):
+    _fields_ = [("opaque", ctypes.c_ubyte * 256)]
 
 
 class Result(ctypes.Structure):
@@ -96,6 +110,16 @@ def load() -> ctypes.CDLL:
         L.gspca_quantized_bytes.argtypes = [i64, i64, i32]
         L.gspca_quantize.restype = ctypes.c_int
         L.gspca_quantize.argtypes = [vp, i64, i64, i64, i32, vp, vp, vp, ctypes.c_size_t, vp]
+        L.gspca_batched_workspace_bytes.restype = ctypes.c_size_t
+        L.gspca_batched_workspace_bytes.argtypes = [ctypes.POINTER(BatchProblem), i32]
+        L.gspca_batched_prepare.restype = ctypes.c_int
+        L.gspca_batched_prepare.argtypes = [ctypes.POINTER(BatchProblem), i32,
+                                            ctypes.POINTER(Options), vp, ctypes.c_size_t,
+                                            ctypes.POINTER(BatchPlan), vp]
+        L.gspca_batched_launch.restype = ctypes.c_int
+        L.gspca_batched_launch.argtypes = [ctypes.POINTER(BatchPlan), vp]
+        L.gspca_batched_tune.restype = ctypes.c_int
+        L.gspca_batched_tune.argtypes = [ctypes.POINTER(BatchPlan), vp]
         _lib = L
         return L
 

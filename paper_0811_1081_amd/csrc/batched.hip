@@ -1,0 +1,369 @@
+// batched.hip -- many independent GS-PCA problems (Andrecut, arXiv:0811.1081,
+// Sec. 2.3) in one persistent launch.
+//
+// One workgroup fits one problem at a time, from its first start vector to its
+// last component, with only workgroup barriers: no grid-wide synchronisation
+// and no host round-trips.  Workgroups take problems from a device-side queue
+// (an atomic counter over a descriptor table the host sorted largest-first)
+// until it is empty, so the launch balances uneven sizes by itself and every
+// workgroup reaches the exit.  The launch contains no host synchronisation and
+// can be captured in a hipGraph and replayed; the queue counter is reset by a
+// one-thread kernel, not a memset.
+//
+// Per iteration (FP32 data, FP64 Gram-Schmidt and norms, implicit deflation
+// R = X - T P^T on Gram-Schmidt-projected vectors):
+//   t = X p                 threads over rows (coalesced columns of X)
+//   d = V_(k)^T t           waves over components, lanes over rows
+//   t <- t - V d, sigma = |t|, stop test (relative sigma, loading, replay)
+//   q = X^T t               waves over columns, lanes over rows
+//   c = P_(k)^T q, p = q - P c, p / |p|
+// t, q, p, the column norms and the coefficient vectors live in LDS.
+#include <float.h>
+#include <math.h>
+
+#include "internal.h"
+
+namespace gspca {
+
+template <typename T>
+__device__ inline T bwave_sum(T v)
+{
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// Workgroup sum; every thread gets the result.  `red` holds one slot per wave.
+__device__ inline double bblock_sum(double v, double *red)
+{
+    v = bwave_sum(v);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0)
+        red[w] = v;
+    __syncthreads();
+    double r = 0.0;
+    for (int i = 0; i < nw; ++i)
+        r += red[i];
+    return r;
+}
+
+__global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
+
+__global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ items, int nprob,
+                                                  const int32_t *__restrict__ order,
+                                                  uint32_t *__restrict__ queue, BatchArgs a)
+{
+    extern __shared__ double lds[];
+    __shared__ double red[16];
+    __shared__ int cur, bad;
+    __shared__ int64_t sel;
+    __shared__ double sred[16];
+    __shared__ int64_t ired[16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int NT = blockDim.x, nw = NT >> 6;
+
+    for (;;) {
+        if (tid == 0) {
+            const uint32_t i = atomicAdd(queue, 1u);
+            cur = i < (uint32_t)nprob ? order[i] : -1;
+        }
+        __syncthreads();
+        const int pi = cur;
+        __syncthreads();
+        if (pi < 0)
+            return;
+        const BatchItem it = items[pi];
+        const int M = it.M, N = it.N, K = it.K;
+        const int64_t ldx = it.ldx;
+        const float *X = it.X;
+        float *T = it.T, *P = it.P;
+        double *W = it.W; // N x K: X^T v_i of finished components
+        // LDS: t[M] | q[N] | p[N] | pprev[N] | cn0[N] | sig[K] | dc[K] | pf[N] (float)
+        double *t = lds;
+        double *q = t + M;
+        double *p = q + N;
+        double *pprev = p + N;
+        double *cn0 = pprev + N;
+        double *sig = cn0 + N;
+        double *dc = sig + K;
+        float *pf = reinterpret_cast<float *>(dc + K);
+
+        // |X_j|^2: waves over columns, lanes over rows; NaN/Inf ends the problem
+        if (tid == 0)
+            bad = 0;
+        __syncthreads();
+        for (int j = w; j < N; j += nw) {
+            const float *col = X + (int64_t)j * ldx;
+            double s = 0.0;
+            for (int m = lane; m < M; m += 64)
+                s += (double)col[m] * (double)col[m];
+            s = bwave_sum(s);
+            if (lane == 0) {
+                cn0[j] = s;
+                if (!isfinite(s))
+                    bad = 1;
+            }
+        }
+        __syncthreads();
+        if (bad) {
+            if (tid == 0 && it.status)
+                *it.status = -4;
+            __syncthreads();
+            continue;
+        }
+        int not_conv = 0;
+
+        for (int k = 0; k < K; ++k) {
+            const int32_t limit = it.replay_iters ? it.replay_iters[k] : a.max_iter;
+            // ---- start column: the largest residual column norm (ties to the
+            //      lowest index), |X_j|^2 - 2 sum_i s_i P_ji (X^T v_i)_j
+            //      + sum_i s_i^2 P_ji^2; replayed column or column k when asked
+            double best = -1.0;
+            int64_t bi = 0;
+            for (int j = tid; j < N; j += NT) {
+                double s = cn0[j];
+                for (int i = 0; i < k; ++i) {
+                    const double pji = (double)P[j + (int64_t)i * N];
+                    s += -2.0 * sig[i] * pji * W[j + (int64_t)i * N] + sig[i] * sig[i] * pji * pji;
+                }
+                s = s < 0.0 ? 0.0 : s;
+                q[j] = s;
+                if (s > best) { best = s; bi = j; }
+            }
+            for (int o = 32; o > 0; o >>= 1) {
+                const double ov = __shfl_xor(best, o, 64);
+                const int64_t oi = __shfl_xor(bi, o, 64);
+                if (ov > best || (ov == best && oi < bi)) { best = ov; bi = oi; }
+            }
+            if (lane == 0) { sred[w] = best; ired[w] = bi; }
+            __syncthreads();
+            if (tid == 0) {
+                double b = sred[0];
+                int64_t i0 = ired[0];
+                for (int i = 1; i < nw; ++i)
+                    if (sred[i] > b || (sred[i] == b && ired[i] < i0)) { b = sred[i]; i0 = ired[i]; }
+                if (it.replay_start && it.replay_start[k] >= 0 && it.replay_start[k] < N)
+                    i0 = it.replay_start[k];
+                else if (a.init == 1 && sqrt(q[k]) >= a.tiny)
+                    i0 = k;
+                sel = i0;
+            }
+            __syncthreads();
+            const int64_t c0 = sel;
+            // t0 = X_c - sum_i s_i v_i P_ci
+            double ss = 0.0;
+            for (int m = tid; m < M; m += NT) {
+                double v = (double)X[m + c0 * ldx];
+                for (int i = 0; i < k; ++i)
+                    v -= sig[i] * (double)T[m + (int64_t)i * M] * (double)P[c0 + (int64_t)i * N];
+                t[m] = v;
+                ss += v * v;
+            }
+            const double t0n = sqrt(bblock_sum(ss, red));
+            int degenerate = !(t0n >= a.tiny) || limit < 1;
+            double s_cur = 0.0, mu = 0.0, pn = 1.0, dp = INFINITY;
+            int iters = 0, conv = 0;
+
+            // loading from t: q = X^T t, one GS pass, norm (Sec. 2.3)
+            auto loading = [&](int first) -> bool {
+                __syncthreads();
+                for (int j = w; j < N; j += nw) {
+                    const float *col = X + (int64_t)j * ldx;
+                    double s = 0.0;
+                    for (int m = lane; m < M; m += 64)
+                        s += (double)col[m] * t[m];
+                    s = bwave_sum(s);
+                    if (lane == 0)
+                        q[j] = s;
+                }
+                __syncthreads();
+                for (int i = w; i < k; i += nw) {
+                    const float *pc = P + (int64_t)i * N;
+                    double s = 0.0;
+                    for (int j = lane; j < N; j += 64)
+                        s += (double)pc[j] * q[j];
+                    s = bwave_sum(s);
+                    if (lane == 0)
+                        dc[i] = s;
+                }
+                __syncthreads();
+                double s2 = 0.0, dt = 0.0;
+                for (int j = tid; j < N; j += NT) {
+                    double v = q[j];
+                    double pr = 0.0;
+                    for (int i = 0; i < k; ++i)
+                        pr += (double)P[j + (int64_t)i * N] * dc[i];
+                    v -= pr;
+                    pprev[j] = p[j];
+                    p[j] = v;
+                    s2 += v * v;
+                    dt += v * pprev[j];
+                }
+                const double nrm = sqrt(bblock_sum(s2, red));
+                const double dot = bblock_sum(dt, red);
+                if (!(nrm >= a.tiny))
+                    return false;
+                dp = INFINITY;
+                if (!first && a.stop == 1) {
+                    const double ia = 1.0 / nrm, ib = (dot >= 0.0 ? 1.0 : -1.0) / pn;
+                    double dd = 0.0;
+                    for (int j = tid; j < N; j += NT) {
+                        const double e = p[j] * ia - pprev[j] * ib;
+                        dd += e * e;
+                    }
+                    dp = sqrt(bblock_sum(dd, red));
+                }
+                pn = nrm;
+                return true;
+            };
+
+            if (!degenerate) {
+                if (!loading(1)) {
+                    degenerate = 1;
+                    iters = 1;
+                }
+            }
+            while (!degenerate && iters < limit) {
+                ++iters;
+                // t = X p / |p|: threads over rows, FP32 products, four partial sums
+                __syncthreads();
+                for (int j = tid; j < N; j += NT)
+                    pf[j] = (float)(p[j] / pn);
+                __syncthreads();
+                for (int m = tid; m < M; m += NT) {
+                    float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
+                    const float *xr = X + m;
+                    int j = 0;
+                    for (; j + 4 <= N; j += 4) {
+                        a0 += xr[(int64_t)j * ldx] * pf[j];
+                        a1 += xr[(int64_t)(j + 1) * ldx] * pf[j + 1];
+                        a2 += xr[(int64_t)(j + 2) * ldx] * pf[j + 2];
+                        a3 += xr[(int64_t)(j + 3) * ldx] * pf[j + 3];
+                    }
+                    for (; j < N; ++j)
+                        a0 += xr[(int64_t)j * ldx] * pf[j];
+                    t[m] = (double)((a0 + a1) + (a2 + a3));
+                }
+                __syncthreads();
+                // d = V^T t, t <- t - V d, sigma
+                for (int i = w; i < k; i += nw) {
+                    const float *vc = T + (int64_t)i * M;
+                    double s = 0.0;
+                    for (int m = lane; m < M; m += 64)
+                        s += (double)vc[m] * t[m];
+                    s = bwave_sum(s);
+                    if (lane == 0)
+                        dc[i] = s;
+                }
+                __syncthreads();
+                double s2 = 0.0;
+                for (int m = tid; m < M; m += NT) {
+                    double v = t[m];
+                    double pr = 0.0;
+                    for (int i = 0; i < k; ++i)
+                        pr += (double)T[m + (int64_t)i * M] * dc[i];
+                    v -= pr;
+                    t[m] = v;
+                    s2 += v * v;
+                }
+                s_cur = sqrt(bblock_sum(s2, red));
+                if (!(s_cur >= a.tiny)) {
+                    degenerate = 1;
+                    break;
+                }
+                if (!it.replay_iters) {
+                    const bool pass_test = a.stop == 1 ? (dp < a.tol)
+                                                       : (fabs(mu - s_cur) < a.tol * s_cur);
+                    if (pass_test) {
+                        conv = 1;
+                        break;
+                    }
+                    mu = s_cur;
+                }
+                if (iters >= limit)
+                    break;
+                if (!loading(0)) {
+                    degenerate = 1;
+                    ++iters;
+                    break;
+                }
+            }
+            if (!degenerate && !conv && !it.replay_iters)
+                not_conv = 1;
+            __syncthreads();
+            if (degenerate) {
+                // first unit vector with Gram-Schmidt residual^2 >= (N-k)/(2N)
+                const double thresh = (double)(N - k) / (2.0 * (double)N);
+                for (int i = 0; i < N; ++i) {
+                    double sq = 0.0;
+                    for (int j = tid; j < N; j += NT) {
+                        double s = 0.0;
+                        for (int l = 0; l < k; ++l)
+                            s += (double)P[j + (int64_t)l * N] * (double)P[i + (int64_t)l * N];
+                        const double rv = (j == i ? 1.0 : 0.0) - s;
+                        p[j] = rv;
+                        sq += rv * rv;
+                    }
+                    sq = bblock_sum(sq, red);
+                    if (sq >= thresh) {
+                        pn = sqrt(sq);
+                        break;
+                    }
+                }
+                s_cur = 0.0;
+            }
+            __syncthreads();
+            // finish component k: V[:,k], P[:,k], then W[:,k] = X^T v_k
+            for (int m = tid; m < M; m += NT) {
+                const double v = degenerate ? 0.0 : t[m] / s_cur;
+                t[m] = v;
+                T[m + (int64_t)k * M] = (float)v;
+            }
+            for (int j = tid; j < N; j += NT)
+                P[j + (int64_t)k * N] = (float)(p[j] / pn);
+            if (tid == 0) {
+                sig[k] = s_cur;
+                if (it.sigma)
+                    it.sigma[k] = s_cur;
+                if (it.iters)
+                    it.iters[k] = iters;
+                if (it.start_col)
+                    it.start_col[k] = (int32_t)c0;
+            }
+            __syncthreads();
+            if (k + 1 < K) {
+                for (int j = w; j < N; j += nw) {
+                    const float *col = X + (int64_t)j * ldx;
+                    double s = 0.0;
+                    for (int m = lane; m < M; m += 64)
+                        s += (double)col[m] * t[m];
+                    s = bwave_sum(s);
+                    if (lane == 0)
+                        W[j + (int64_t)k * N] = degenerate ? 0.0 : s;
+                }
+            }
+            __syncthreads();
+        }
+        // T = V Lambda, lambda = sigma^2, status
+        for (int k = 0; k < K; ++k)
+            for (int m = tid; m < M; m += NT)
+                T[m + (int64_t)k * M] = (float)((double)T[m + (int64_t)k * M] * sig[k]);
+        if (tid < K)
+            it.lambda[tid] = sig[tid] * sig[tid];
+        if (tid == 0 && it.status)
+            *it.status = not_conv ? 1 : 0;
+        __syncthreads();
+    }
+}
+
+void batched_launch(const BatchItem *items, int nprob, const int32_t *order, uint32_t *queue,
+                    BatchArgs a, int grid, int threads, size_t lds_bytes, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, queue);
+    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(threads), lds_bytes, s, items, nprob, order,
+                       queue, a);
+}
+
+}  // namespace gspca

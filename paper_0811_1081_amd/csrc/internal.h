@@ -112,4 +112,27 @@ struct Fused {
                          int32_t *iters, int32_t *start_col, LoopState *st, hipStream_t s);
 };
 
+// Batched path (batched.hip): one workgroup per problem, persistent queue.
+struct BatchItem {
+    const float *X;
+    int64_t ldx;
+    int32_t M, N, K, pad;
+    float *T, *P;
+    double *lambda, *sigma;
+    int32_t *iters, *start_col;
+    const int32_t *replay_iters, *replay_start;
+    int32_t *status;
+    double *W; // N x K workspace
+};
+struct BatchArgs {
+    double tol, tiny;
+    int32_t max_iter, init, stop, pad;
+};
+void batched_launch(const BatchItem *items, int nprob, const int32_t *order, uint32_t *queue,
+                    BatchArgs a, int grid, int threads, size_t lds_bytes, hipStream_t s);
+inline size_t batched_lds_bytes(int64_t M, int64_t N, int64_t K)
+{
+    return (size_t)(M + 4 * N + 2 * K) * 8 + (size_t)N * 4;
+}
+
 }  // namespace gspca

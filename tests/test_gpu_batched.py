@@ -1,0 +1,171 @@
+"""GPU tests of the batched form: many independent GS-PCA problems (Sec. 2.3,
+implicit deflation) in one persistent launch, hipGraph capture, autotuner.
+
+Each sampled problem is checked against the FP64 oracle replaying the GPU's
+iteration counts and start columns (FP32 bound 1e-5 on gapped components).
+"""
+import os
+
+import numpy as np
+import pytest
+
+from metrics import col_angles, orth_err
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1081_amd as gp
+    gp.load()
+
+
+def _gh():
+    import gpu_helpers
+    return gpu_helpers
+
+
+def _gapped(sig, rel=0.02):
+    s = np.asarray(sig, dtype=np.float64)
+    ok = np.ones(len(s), dtype=bool)
+    for k in range(len(s)):
+        if k > 0 and s[k] > (1 - rel) * s[k - 1]:
+            ok[k] = False
+        if k + 1 < len(s) and s[k + 1] > (1 - rel) * s[k]:
+            ok[k] = False
+    return ok
+
+
+def _problems(count, seed, mmax=700, nmax=160):
+    from paper_0811_1081_amd import synth
+    rng = np.random.default_rng(seed)
+    out = []
+    for i in range(count):
+        M = int(rng.integers(16, mmax))
+        N = int(rng.integers(4, nmax))
+        r = min(M, N, 12)
+        X = synth.haar_spectrum(M, N, 0.75 ** np.arange(r), 1e-3, seed=(14, seed * 1000 + i),
+                                dtype=np.float32)
+        out.append((X, min(6, M, N)))
+    return out
+
+
+def _check(orc, X, K, T, P, sig, iters, start):
+    o = orc.fit(X, K, tol=0.0, max_iter=max(1, int(iters.max())), implicit=True,
+                replay_iters=iters, replay_start=start, tiny=orc.FLT_MIN)
+    ok = _gapped(o.sigma)
+    if ok.any():
+        assert col_angles(P, o.P)[ok].max() <= 1e-5
+        assert col_angles(T, o.T)[ok].max() <= 1e-5
+    assert np.abs(sig - o.sigma).max() <= 1e-5 * o.sigma[0]
+    assert orth_err(P) <= 1e-5
+
+
+def test_batched_matches_oracle(orc):
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(40, seed=1)
+    Xs = [_gh().to_device(X) for X, _ in probs]
+    b = gp.Batch(Xs, [k for _, k in probs], tol=1e-6, max_iter=1000)
+    b.launch()
+    torch.cuda.synchronize()
+    st = b.status.cpu().numpy()
+    assert np.all(st == 0)
+    for i, (X, K) in enumerate(probs):
+        _check(orc, X, K, b.T[i].cpu().numpy(), b.P[i].cpu().numpy(), b.sigma[i].cpu().numpy(),
+               b.iters[i].cpu().numpy(), b.start_col[i].cpu().numpy())
+        free = orc.fit(X, K, tol=1e-6, max_iter=1000, implicit=True, tiny=orc.FLT_MIN)
+        assert np.array_equal(free.start_col, b.start_col[i].cpu().numpy())
+        assert np.array_equal(b.lam[i].cpu().numpy(), b.sigma[i].cpu().numpy() ** 2)
+
+
+def test_batched_equals_single_fit_trajectory(orc):
+    """The batched kernel and the single-problem library path run the same
+    method: with the same replayed counts their results agree."""
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(6, seed=2, mmax=2000, nmax=300)
+    Xs = [_gh().to_device(X) for X, _ in probs]
+    b = gp.Batch(Xs, [k for _, k in probs], tol=1e-6)
+    b.launch()
+    torch.cuda.synchronize()
+    for i, (X, K) in enumerate(probs):
+        g = gp.fit(Xs[i], K, implicit=True, tol=0.0, max_iter=int(b.iters[i].max()),
+                   replay_iters=b.iters[i], replay_start=b.start_col[i])
+        ok = _gapped(b.sigma[i].cpu().numpy())
+        assert col_angles(g["P"].cpu().numpy(), b.P[i].cpu().numpy())[ok].max() <= 1e-5
+
+
+def test_batched_replay_and_status():
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(5, seed=3)
+    X_bad = np.ones((50, 10), dtype=np.float32)
+    X_bad[3, 4] = np.nan
+    Xs = [_gh().to_device(X) for X, _ in probs] + [_gh().to_device(X_bad)]
+    Ks = [k for _, k in probs] + [2]
+    its = [torch.full((k,), 3, dtype=torch.int32, device="cuda") for k in Ks]
+    scs = [torch.full((k,), -1, dtype=torch.int32, device="cuda") for k in Ks]
+    b = gp.Batch(Xs, Ks, tol=1e-6, replay_iters=its, replay_start=scs)
+    b.launch()
+    torch.cuda.synchronize()
+    st = b.status.cpu().numpy()
+    assert list(st[:-1]) == [0] * 5 and st[-1] == gp.ENONFINITE
+    for i in range(5):
+        assert np.all(b.iters[i].cpu().numpy() == 3)
+    b2 = gp.Batch(Xs[:5], Ks[:5], tol=1e-12, max_iter=2)
+    b2.launch()
+    torch.cuda.synchronize()
+    assert np.all(b2.status.cpu().numpy() == gp.NOT_CONVERGED)
+
+
+def test_batched_graph_replays_match_eager():
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(24, seed=4)
+    Xs = [_gh().to_device(X) for X, _ in probs]
+    b = gp.Batch(Xs, [k for _, k in probs], tol=1e-6)
+    b.launch()
+    torch.cuda.synchronize()
+    ref = [p.clone() for p in b.P]
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.launch(stream=s)
+    torch.cuda.synchronize()
+    for rep in range(3):
+        for P in b.P:
+            P.zero_()
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for P, R in zip(b.P, ref):
+            assert torch.equal(P, R), rep
+        _ = torch.ones(10, device="cuda").sum().item()  # eager work between replays
+
+
+def test_batched_autotune_and_cache(tmp_path):
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(30, seed=5)
+    Xs = [_gh().to_device(X) for X, _ in probs]
+    cache = tmp_path / "tune.jsonl"
+    os.environ["GSPCA_TUNE_CACHE"] = str(cache)
+    try:
+        b = gp.Batch(Xs, [k for _, k in probs], tol=1e-6)
+        b.tune()
+        shape = b.shape()
+        assert shape[0] in (256, 512, 1024) and 1 <= shape[1] <= 4
+        lines = cache.read_text().strip().splitlines()
+        assert len(lines) == 1 and '"threads":%d' % shape[0] in lines[0]
+        b2 = gp.Batch(Xs, [k for _, k in probs], tol=1e-6)  # picks the cached shape
+        assert b2.shape() == shape
+        b2.launch()
+        torch.cuda.synchronize()
+        assert np.all(b2.status.cpu().numpy() == 0)
+    finally:
+        del os.environ["GSPCA_TUNE_CACHE"]
