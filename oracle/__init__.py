@@ -17,7 +17,7 @@ import threading
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_SOURCES = ("pca_oracle.c", "codec_oracle.c")
+_SOURCES = ("pca_oracle.c", "codec_oracle.c", "mlp_oracle.c")
 LIB_PATH = os.path.join(_HERE, "liboracle.so")
 CFLAGS = ["-O2", "-fno-fast-math", "-ffp-contract=off", "-std=c99", "-fPIC", "-shared",
           "-Wall", "-Wextra", "-Wno-unused-parameter"]
@@ -73,6 +73,17 @@ def lib() -> ctypes.CDLL:
             L.oracle_quantize.argtypes = [vp, i64, i64, i64, ctypes.c_int, vp, vp]
             L.oracle_dequantize.restype = ctypes.c_int
             L.oracle_dequantize.argtypes = [vp, vp, i64, i64, ctypes.c_int, vp]
+            ci = ctypes.c_int
+            L.oracle_mlp_forward.restype = None
+            L.oracle_mlp_forward.argtypes = [vp, i64, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci,
+                                             vp, vp, vp]
+            L.oracle_cos2_loss.restype = dbl
+            L.oracle_cos2_loss.argtypes = [vp, vp, i64, ci, vp]
+            L.oracle_mlp_backward.restype = None
+            L.oracle_mlp_backward.argtypes = [vp, i64, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp,
+                                              vp, vp, vp, vp, vp, vp, vp]
+            L.oracle_adam.restype = None
+            L.oracle_adam.argtypes = [vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, ci]
             _lib = L
     return _lib
 
@@ -199,3 +210,53 @@ def dequantize(codes, scale, fmt):
     sc = np.ascontiguousarray(scale, dtype=np.float32)
     lib().oracle_dequantize(_ptr(codes), _ptr(sc), M, N, fmt_i, _ptr(out))
     return out
+
+
+# ---------------------------------------------------------------------------
+# Warm-start network (see mlp_oracle.c): row-wise MLP d0 -> d1 -> d2 -> d3.
+
+def _c64(a):
+    return np.ascontiguousarray(a, dtype=np.float64)
+
+
+def mlp_forward(Z, params, round_bf16=False):
+    """params = (W1, b1, W2, b2, W3, b3) with W_l of shape (d_in, d_out).
+    Returns (H1, H2, O); rows of Z are samples."""
+    W1, b1, W2, b2, W3, b3 = [_c64(x) for x in params]
+    Z = _c64(Z)
+    M, d0 = Z.shape
+    d1, d2, d3 = W1.shape[1], W2.shape[1], W3.shape[1]
+    H1 = np.zeros((M, d1)); H2 = np.zeros((M, d2)); O = np.zeros((M, d3))
+    lib().oracle_mlp_forward(_ptr(Z), M, d0, d1, d2, d3, _ptr(W1), _ptr(b1), _ptr(W2), _ptr(b2),
+                             _ptr(W3), _ptr(b3), int(bool(round_bf16)), _ptr(H1), _ptr(H2), _ptr(O))
+    return H1, H2, O
+
+
+def cos2_loss(O, V):
+    """Sign-invariant loss sum_k 1 - cos^2(o_k, v_k) over columns; returns (L, dL/dO)."""
+    O = _c64(O); V = _c64(V)
+    M, K = O.shape
+    dO = np.zeros((M, K))
+    L = lib().oracle_cos2_loss(_ptr(O), _ptr(V), M, K, _ptr(dO))
+    return L, dO
+
+
+def mlp_backward(Z, params, H1, H2, dO):
+    """Gradients (dW1, db1, dW2, db2, dW3, db3) of the loss whose dL/dO is dO."""
+    W1, b1, W2, b2, W3, b3 = [_c64(x) for x in params]
+    Z = _c64(Z); H1 = _c64(H1); H2 = _c64(H2); dO = _c64(dO)
+    M, d0 = Z.shape
+    d1, d2, d3 = W1.shape[1], W2.shape[1], W3.shape[1]
+    g = [np.zeros_like(W1), np.zeros(d1), np.zeros_like(W2), np.zeros(d2), np.zeros_like(W3),
+         np.zeros(d3)]
+    G1 = np.zeros((M, d1)); G2 = np.zeros((M, d2))
+    lib().oracle_mlp_backward(_ptr(Z), M, d0, d1, d2, d3, _ptr(W1), _ptr(W2), _ptr(W3), _ptr(H1),
+                              _ptr(H2), _ptr(dO), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(g[3]),
+                              _ptr(g[4]), _ptr(g[5]), _ptr(G1), _ptr(G2))
+    return g
+
+
+def adam_step(w, g, m1, m2, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):
+    """In-place Adam update of float64 arrays w, m1, m2 with gradient g."""
+    lib().oracle_adam(_ptr(w), _ptr(_c64(g)), _ptr(m1), _ptr(m2), w.size, lr, beta1, beta2, eps,
+                      int(t))
