@@ -80,8 +80,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_cos2_loss.restype = dbl
             L.oracle_cos2_loss.argtypes = [vp, vp, i64, ci, vp]
             L.oracle_mlp_backward.restype = None
-            L.oracle_mlp_backward.argtypes = [vp, i64, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, vp,
-                                              vp, vp, vp, vp, vp, vp, vp]
+            L.oracle_mlp_backward.argtypes = [vp, i64, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci,
+                                              vp, vp, vp, vp, vp, vp, vp, vp]
             L.oracle_adam.restype = None
             L.oracle_adam.argtypes = [vp, vp, vp, vp, i64, dbl, dbl, dbl, dbl, ci]
             _lib = L
@@ -170,6 +170,31 @@ def jacobi_eig(A):
     return w, Q
 
 
+def sketch_whiten(X, Omega):
+    """Warm-start input rows (not in the paper): Y = X Omega, then the
+    eigen-decomposition Y^T Y = Q diag(g) Q^T by cyclic Jacobi (g decreasing,
+    each eigenvector's largest-magnitude entry made positive) and
+    Z = sqrt(M) Y Q diag(g)^(-1/2); columns with g <= 0 are zero.  FP64.
+    Returns (Y, Z, g)."""
+    X = np.asarray(X, dtype=np.float64)
+    Y = X @ np.asarray(Omega, dtype=np.float64)
+    return (Y,) + whiten(Y)
+
+
+def whiten(Y):
+    """The whitening half of sketch_whiten on a given sketch Y: (Z, g)."""
+    Y = np.asarray(Y, dtype=np.float64)
+    M = Y.shape[0]
+    g, Q = jacobi_eig(Y.T @ Y)
+    Q = np.array(Q)
+    for c in range(Q.shape[1]):
+        i = int(np.argmax(np.abs(Q[:, c])))
+        if Q[i, c] < 0:
+            Q[:, c] = -Q[:, c]
+    scale = np.where(g > 0, np.sqrt(M) / np.sqrt(np.where(g > 0, g, 1.0)), 0.0)
+    return (Y @ Q) * scale, g
+
+
 def bf16_encode(x: float) -> int:
     return int(lib().oracle_bf16_encode(float(x)))
 
@@ -241,8 +266,10 @@ def cos2_loss(O, V):
     return L, dO
 
 
-def mlp_backward(Z, params, H1, H2, dO):
-    """Gradients (dW1, db1, dW2, db2, dW3, db3) of the loss whose dL/dO is dO."""
+def mlp_backward(Z, params, H1, H2, dO, round_bf16=False, return_hidden=False):
+    """Gradients (dW1, db1, dW2, db2, dW3, db3) of the loss whose dL/dO is dO;
+    round_bf16 rounds the masked hidden gradients to bfloat16 where they are
+    stored.  return_hidden: also return those hidden gradients (G1, G2)."""
     W1, b1, W2, b2, W3, b3 = [_c64(x) for x in params]
     Z = _c64(Z); H1 = _c64(H1); H2 = _c64(H2); dO = _c64(dO)
     M, d0 = Z.shape
@@ -251,9 +278,10 @@ def mlp_backward(Z, params, H1, H2, dO):
          np.zeros(d3)]
     G1 = np.zeros((M, d1)); G2 = np.zeros((M, d2))
     lib().oracle_mlp_backward(_ptr(Z), M, d0, d1, d2, d3, _ptr(W1), _ptr(W2), _ptr(W3), _ptr(H1),
-                              _ptr(H2), _ptr(dO), _ptr(g[0]), _ptr(g[1]), _ptr(g[2]), _ptr(g[3]),
+                              _ptr(H2), _ptr(dO), int(bool(round_bf16)), _ptr(g[0]), _ptr(g[1]),
+                              _ptr(g[2]), _ptr(g[3]),
                               _ptr(g[4]), _ptr(g[5]), _ptr(G1), _ptr(G2))
-    return g
+    return (g, G1, G2) if return_hidden else g
 
 
 def adam_step(w, g, m1, m2, lr, t, beta1=0.9, beta2=0.999, eps=1e-8):

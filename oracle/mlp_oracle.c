@@ -15,9 +15,11 @@
  * normalised score v_k.  relu'(0) = 0.
  *
  * Layout: row-major, samples in rows: Z[m*d0 + i], W1[i*d1 + j], H1[m*d1 + j],
- * O[m*d3 + k], V[m*d3 + k].  If round_bf16 is non-zero, the stored
+ * O[m*d3 + k], V[m*d3 + k].  If round_bf16_act is non-zero, the stored
  * activations H1, H2 are rounded to bfloat16 (round to nearest even) after the
- * ReLU, mirroring where a bf16 implementation stores them.
+ * ReLU; if round_bf16_grad is non-zero, so are the masked hidden gradients G2,
+ * G1 in the backward pass: the points where a bf16 implementation stores them.
+ * Rounding the inputs, weights and dL/dO is left to the caller.
  */
 #include <math.h>
 #include <stdint.h>
@@ -90,9 +92,9 @@ double oracle_cos2_loss(const double *O, const double *V, int64_t M, int K, doub
 /* Backward through the three layers given the stored activations. */
 void oracle_mlp_backward(const double *Z, int64_t M, int d0, int d1, int d2, int d3,
                          const double *W1, const double *W2, const double *W3, const double *H1,
-                         const double *H2, const double *dO, double *dW1, double *db1,
-                         double *dW2, double *db2, double *dW3, double *db3, double *G1,
-                         double *G2)
+                         const double *H2, const double *dO, int round_bf16_grad, double *dW1,
+                         double *db1, double *dW2, double *db2, double *dW3, double *db3,
+                         double *G1, double *G2)
 {
     /* layer 3: O = H2 W3 + b3 */
     for (int i = 0; i < d2; ++i)
@@ -114,7 +116,8 @@ void oracle_mlp_backward(const double *Z, int64_t M, int d0, int d1, int d2, int
             double s = 0.0;
             for (int k = 0; k < d3; ++k)
                 s += dO[m * d3 + k] * W3[(int64_t)i * d3 + k];
-            G2[m * d2 + i] = H2[m * d2 + i] > 0.0 ? s : 0.0;
+            s = H2[m * d2 + i] > 0.0 ? s : 0.0;
+            G2[m * d2 + i] = round_bf16_grad ? round_bf16(s) : s;
         }
     for (int i = 0; i < d1; ++i)
         for (int j = 0; j < d2; ++j) {
@@ -135,7 +138,8 @@ void oracle_mlp_backward(const double *Z, int64_t M, int d0, int d1, int d2, int
             double s = 0.0;
             for (int j = 0; j < d2; ++j)
                 s += G2[m * d2 + j] * W2[(int64_t)i * d2 + j];
-            G1[m * d1 + i] = H1[m * d1 + i] > 0.0 ? s : 0.0;
+            s = H1[m * d1 + i] > 0.0 ? s : 0.0;
+            G1[m * d1 + i] = round_bf16_grad ? round_bf16(s) : s;
         }
     for (int i = 0; i < d0; ++i)
         for (int j = 0; j < d1; ++j) {

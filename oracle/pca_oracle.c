@@ -28,7 +28,11 @@
  *     the test passed (or max_iter).
  *   - start vector: column k of the residual (the pseudo-code's R^(k)), the
  *     column of largest norm (ties to the lowest index), or a given vector;
- *     a zero start column falls back to the largest-norm column.
+ *     a zero start column falls back to the largest-norm column.  A given
+ *     vector (the learned warm start) also falls back to the largest-norm
+ *     column if its norm is below `tiny` or not finite, or, for GS-PCA, if
+ *     one Gram-Schmidt pass against the earlier normalised scores V_(k)
+ *     leaves less than a tenth of its norm.
  *   - degenerate component: if the loading or score norm is below `tiny`
  *     (DBL_MIN or FLT_MIN by the caller's choice), sigma_k = 0, t_k = 0 and
  *     p_k is the first canonical vector e_i (ascending i) whose Gram-Schmidt
@@ -279,7 +283,21 @@ int oracle_fit(int algo, int implicit,
             memcpy(t, T0 + k * M, (size_t)M * sizeof(double));
             snrm = nrm2(t, M);
             sc = -1;
-            if (!(snrm >= tiny) || !isfinite(snrm))
+            int fall = !(snrm >= tiny) || !isfinite(snrm);
+            if (!fall && gs && k > 0) {
+                /* residual of one CGS pass against v_0 .. v_(k-1) */
+                double *r = malloc((size_t)M * sizeof(double));
+                if (!r) { status = OR_EINVAL; break; }
+                memcpy(r, t, (size_t)M * sizeof(double));
+                for (int64_t i = 0; i < k; ++i) {
+                    const double c = dot(T + i * M, t, M);
+                    for (int64_t m = 0; m < M; ++m)
+                        r[m] -= c * T[m + i * M];
+                }
+                fall = nrm2(r, M) < 0.1 * snrm;
+                free(r);
+            }
+            if (fall)
                 sc = resid_maxnorm_column(&op, t, &snrm), resid_column(&op, sc, t);
         } else if (init == OR_INIT_COLUMN_K) {
             sc = k;

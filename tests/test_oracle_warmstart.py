@@ -1,0 +1,103 @@
+"""Pins of the oracle's warm-start pieces (not in the paper): the whitened
+sketch, the fallback rule of a given start, and the bf16 rounding points of
+the network's backward pass."""
+import numpy as np
+
+from metrics import col_angles
+
+
+def test_whitened_sketch_closed_forms(orc):
+    from paper_0811_1081_amd import synth
+    X = synth.warmstart_instance(3, M=300, N=64)[0]
+    Om = synth.sketch_matrix(64, 32)
+    Y, Z, g = orc.sketch_whiten(X, Om)
+    M = X.shape[0]
+    assert np.allclose(Y, X.astype(np.float64) @ Om.astype(np.float64), rtol=0, atol=1e-12)
+    # eigenvalues of Y^T Y by a library routine, decreasing
+    ref = np.sort(np.linalg.eigvalsh(Y.T @ Y))[::-1]
+    assert np.all(np.diff(g) <= 0)
+    assert np.abs(g - ref).max() <= 1e-9 * ref[0]
+    # whitened: Z^T Z = M I, and Z spans the columns of Y
+    assert np.abs(Z.T @ Z / M - np.eye(32)).max() <= 1e-6
+    coef, *_ = np.linalg.lstsq(Y, Z, rcond=None)
+    assert np.linalg.norm(Y @ coef - Z) <= 1e-8 * np.linalg.norm(Z)
+    # column c of Z is Y's left singular vector c (times sqrt(M)), up to sign
+    U = np.linalg.svd(Y, full_matrices=False)[0]
+    good = g[:16] > 1e-6 * g[0]
+    assert col_angles(Z[:, :16] / np.sqrt(M), U[:, :16])[good].max() <= 1e-6
+
+
+def test_whitening_sign_rule_and_zero_direction(orc):
+    rng = np.random.default_rng(5)
+    Y = rng.standard_normal((80, 32))
+    Y[:, 7] = Y[:, 3]  # rank 31: one eigenvalue 0 -> a zero column of Z
+    Z, g = orc.whiten(Y)
+    assert abs(g[-1]) <= 1e-10 * g[0]
+    assert np.all(Z[:, -1] == 0.0) or g[-1] > 0
+    # the sign rule: each eigenvector's largest-magnitude entry is positive, so
+    # the coefficients Z = Y A have A's largest entry per column positive
+    A = np.linalg.lstsq(Y, Z[:, :31], rcond=None)[0]
+    i = np.argmax(np.abs(A), axis=0)
+    assert np.all(A[i, np.arange(31)] > 0)
+
+
+def _two_scores():
+    rng = np.random.default_rng(11)
+    M, N = 60, 12
+    U = np.linalg.qr(rng.standard_normal((M, N)))[0]
+    W = np.linalg.qr(rng.standard_normal((N, N)))[0]
+    s = 0.6 ** np.arange(N)
+    return (U * s) @ W.T, U, rng
+
+
+def test_given_start_falls_back_when_inside_earlier_scores(orc):
+    X, U, rng = _two_scores()
+    M = X.shape[0]
+    ref = orc.fit(X, 3, tol=1e-12, max_iter=500)
+    v0 = ref.V[:, 0]
+    w = rng.standard_normal(M)
+    w -= v0 * (v0 @ w)
+    w /= np.linalg.norm(w)
+    T0 = np.zeros((M, 3), order="F")
+    T0[:, 0] = U[:, 0]
+    T0[:, 1] = v0 + 0.05 * w   # 5% of its norm outside span(v0) -> fallback
+    T0[:, 2] = v0 + 0.25 * w   # 24% outside -> kept
+    f = orc.fit(X, 3, tol=1e-12, max_iter=500, init="given", T0=T0)
+    assert f.start_col[0] == -1
+    assert f.start_col[1] >= 0 and f.start_col[1] == ref.start_col[1]
+    assert f.start_col[2] == -1
+    # the projection test is part of GS-PCA only
+    n = orc.fit(X, 3, tol=1e-12, max_iter=500, init="given", T0=T0, algo="nipals")
+    assert np.all(n.start_col == -1)
+    # a non-finite column falls back as well
+    T0[3, 2] = np.nan
+    f2 = orc.fit(X, 3, tol=1e-12, max_iter=500, init="given", T0=T0)
+    assert f2.start_col[2] >= 0
+
+
+def test_backward_rounding_points(orc):
+    rng = np.random.default_rng(2)
+    dims = (8, 24, 20, 4)
+    M = 40
+    Z = rng.standard_normal((M, dims[0]))
+    params = []
+    for a, b in zip(dims[:-1], dims[1:]):
+        params += [rng.standard_normal((a, b)) / np.sqrt(a), 0.1 * rng.standard_normal(b)]
+    H1, H2, O = orc.mlp_forward(Z, params, round_bf16=True)
+    bf = np.vectorize(lambda x: orc.bf16_decode(orc.bf16_encode(x)))
+    assert np.array_equal(H1, bf(H1)) and np.array_equal(H2, bf(H2))
+    _, dO = orc.cos2_loss(O, rng.standard_normal((M, dims[-1])))
+    g0, G1u, G2u = orc.mlp_backward(Z, params, H1, H2, dO, return_hidden=True)
+    g1, G1r, G2r = orc.mlp_backward(Z, params, H1, H2, dO, round_bf16=True, return_hidden=True)
+    # G2 has identical inputs in both runs: rounded = round(unrounded)
+    assert np.array_equal(G2r, bf(G2u))
+    assert not np.array_equal(G2r, G2u)
+    # G1 is formed from the rounded G2, masked by H1 > 0, then rounded
+    G1ref = np.where(H1 > 0, G2r @ params[2].T, 0.0)
+    assert np.abs(G1r - bf(G1ref)).max() <= 2.0 ** -7 * np.abs(G1ref).max()
+    assert np.all(G1r[H1 <= 0] == 0.0)
+    # dW2 = H1^T G2 uses the rounded G2
+    assert np.allclose(g1[2], H1.T @ G2r, rtol=1e-12, atol=1e-14)
+    # rounding moves each gradient by at most a few bf16 units
+    for a, b in zip(g0, g1):
+        assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(a)
