@@ -22,7 +22,10 @@
  *     lambda_k is the norm of the score, i.e. a singular value of X).
  *   - Start vector: column of the residual with the largest norm (ties to the
  *     lowest index) unless options say otherwise.  A zero start column falls
- *     back to the largest-norm column.
+ *     back to the largest-norm column.  So does a given start (options.T0)
+ *     whose norm is below the degenerate threshold or not finite, or, for
+ *     GS-PCA, one that keeps less than a tenth of its norm after one
+ *     Gram-Schmidt pass against the earlier normalised scores.
  *   - Degenerate component (loading or score norm below DBL_MIN for FP64 data,
  *     FLT_MIN otherwise): sigma_k = 0, T[:,k] = 0 and P[:,k] = the first unit
  *     vector e_i (ascending i) whose Gram-Schmidt residual against P[:, :k]

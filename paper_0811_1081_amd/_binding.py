@@ -26,7 +26,13 @@ EXPORTS = (
     "gspca_fit_f32", "gspca_status_string", "gspca_version", "gspca_quantized_bytes",
     "gspca_quantize", "gspca_batched_workspace_bytes", "gspca_batched_prepare",
     "gspca_batched_launch", "gspca_batched_tune",
+    # gspca_ws.h (learned warm start)
+    "gspca_mlp_param_count", "gspca_mlp_workspace_bytes", "gspca_sketch", "gspca_whiten_sketch",
+    "gspca_mlp_sync", "gspca_mlp_forward", "gspca_mlp_loss_grad", "gspca_mlp_adam",
+    "gspca_ws_predict",
 )
+
+WS_RANK = 32  # GSPCA_WS_RANK
 
 
 class Problem(ctypes.Structure):
@@ -63,6 +69,13 @@ class BatchProblem(ctypes.Structure):
 
 class BatchPlan(ctypes.Structure):
     _fields_ = [("opaque", ctypes.c_ubyte * 256)]
+
+
+class Mlp(ctypes.Structure):
+    _fields_ = [("d0", ctypes.c_int32), ("d1", ctypes.c_int32), ("d2", ctypes.c_int32),
+                ("d3", ctypes.c_int32), ("theta", ctypes.c_void_p), ("theta_bf16", ctypes.c_void_p),
+                ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
+                ("step", ctypes.c_int32), ("pad", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -120,6 +133,20 @@ def load() -> ctypes.CDLL:
         L.gspca_batched_launch.argtypes = [ctypes.POINTER(BatchPlan), vp]
         L.gspca_batched_tune.restype = ctypes.c_int
         L.gspca_batched_tune.argtypes = [ctypes.POINTER(BatchPlan), vp]
+        sz, flt, mlp = ctypes.c_size_t, ctypes.c_float, ctypes.POINTER(Mlp)
+        for name, res, args in (
+                ("gspca_mlp_param_count", i64, [i32, i32, i32, i32]),
+                ("gspca_mlp_workspace_bytes", sz, [mlp, i64, i32]),
+                ("gspca_sketch", ctypes.c_int, [vp, i64, i64, i64, vp, i32, vp, vp]),
+                ("gspca_whiten_sketch", ctypes.c_int, [vp, i64, i32, vp, vp, vp, vp]),
+                ("gspca_mlp_sync", ctypes.c_int, [mlp, vp]),
+                ("gspca_mlp_forward", ctypes.c_int, [mlp, vp, i64, vp, vp, sz, vp]),
+                ("gspca_mlp_loss_grad", ctypes.c_int, [mlp, vp, vp, i32, i64, vp, vp, sz, vp]),
+                ("gspca_mlp_adam", ctypes.c_int, [mlp, flt, flt, flt, flt, vp]),
+                ("gspca_ws_predict", ctypes.c_int, [mlp, vp, i64, i64, i64, vp, vp, vp, sz, vp])):
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
         _lib = L
         return L
 

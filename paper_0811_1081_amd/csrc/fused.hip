@@ -371,20 +371,34 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
     }
     __syncthreads();
     if (use_given) {
-        double s = 0.0;
+        // Norm of the given start and, for GS-PCA, of its part outside the
+        // earlier normalised scores (|g|^2 - sum_i (v_i . g)^2, V orthonormal).
+        // Fall back to the max-norm column if the norm is tiny or not finite,
+        // or if less than a tenth of it lies outside span(V_(k)).
         const E *g = T0 + (int64_t)a.k * M;
-        for (int64_t m = tid; m < M; m += 1024)
-            s += (double)g[m] * (double)g[m];
-        s = fwave_sum(s);
-        if (lane == 0)
-            sv[w] = s;
-        __syncthreads();
+        const int nd = a.gs ? a.k : 0;
+        double tot = 0.0, dd = 0.0;
+        for (int i = -1; i < nd; ++i) {
+            const E *v = i < 0 ? g : V + (int64_t)i * M;
+            double s = 0.0;
+            for (int64_t m = tid; m < M; m += 1024)
+                s += (double)v[m] * (double)g[m];
+            s = fwave_sum(s);
+            if (lane == 0)
+                sv[w] = s;
+            __syncthreads();
+            double r = 0.0;
+            for (int j = 0; j < 16; ++j)
+                r += sv[j];
+            __syncthreads();
+            if (i < 0)
+                tot = r;
+            else
+                dd += r * r;
+        }
         if (tid == 0) {
-            double tot = 0.0;
-            for (int i = 0; i < 16; ++i)
-                tot += sv[i];
             const double nrm = sqrt(tot);
-            if (nrm >= tiny && isfinite(nrm))
+            if (nrm >= tiny && isfinite(nrm) && tot - dd >= 0.01 * tot)
                 col_sel = -1;
         }
         __syncthreads();

@@ -42,6 +42,7 @@ struct StartArgs {
     int32_t k;
     int32_t init;           // gspca_init
     int32_t force_degenerate;
+    int32_t gs;             // GS-PCA: a given start is also tested against V_(k)
     const int32_t *replay_start; // device, nullable
 };
 
@@ -50,7 +51,7 @@ struct Launch {
     static void copy_pad(const E *X, int64_t ldx, E *R, int64_t ldr, int64_t M, int64_t N,
                          LoopState *st, hipStream_t s);
     static void colnorm(const E *R, int64_t ldr, int64_t M, int64_t N, double *cn, hipStream_t s);
-    static void start(const E *R, int64_t ldr, int64_t M, int64_t N, const double *cn,
+    static void start(const E *R, int64_t ldr, int64_t M, int64_t N, const double *cn, const E *V,
                       const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s);
     static void gemv_t(const E *R, int64_t ldr, int64_t N, const E *t, int64_t rows_per_split,
                        int nsplit, int ncolblk, double *qpart, const LoopState *st, hipStream_t s);

@@ -127,6 +127,7 @@ __global__ __launch_bounds__(kBlock) void k_colnorm(const E *__restrict__ R, int
 template <typename E>
 __global__ __launch_bounds__(1024) void k_start(const E *__restrict__ R, int64_t ldr, int64_t M,
                                                 int64_t N, const double *__restrict__ cn,
+                                                const E *__restrict__ V,
                                                 const E *__restrict__ T0, StartArgs a,
                                                 double tiny, E *__restrict__ t, LoopState *st)
 {
@@ -151,21 +152,34 @@ __global__ __launch_bounds__(1024) void k_start(const E *__restrict__ R, int64_t
     }
     __syncthreads();
     if (use_given) {
-        // norm of the given start; fall back to the max-norm column if tiny or not finite
-        double s = 0.0;
+        // Norm of the given start and, for GS-PCA, of its part outside the
+        // earlier normalised scores (|g|^2 - sum_i (v_i . g)^2, V orthonormal).
+        // Fall back to the max-norm column if the norm is tiny or not finite,
+        // or if less than a tenth of it lies outside span(V_(k)).
         const E *g = T0 + (int64_t)a.k * M;
-        for (int64_t m = tid; m < M; m += 1024)
-            s += (double)g[m] * (double)g[m];
-        s = wave_sum(s);
-        if (lane == 0)
-            sv[w] = s;
-        __syncthreads();
+        const int nd = a.gs ? a.k : 0;
+        double tot = 0.0, dd = 0.0;
+        for (int i = -1; i < nd; ++i) {
+            const E *v = i < 0 ? g : V + (int64_t)i * M;
+            double s = 0.0;
+            for (int64_t m = tid; m < M; m += 1024)
+                s += (double)v[m] * (double)g[m];
+            s = wave_sum(s);
+            if (lane == 0)
+                sv[w] = s;
+            __syncthreads();
+            double r = 0.0;
+            for (int j = 0; j < 16; ++j)
+                r += sv[j];
+            __syncthreads();
+            if (i < 0)
+                tot = r;
+            else
+                dd += r * r;
+        }
         if (tid == 0) {
-            double tot = 0.0;
-            for (int i = 0; i < 16; ++i)
-                tot += sv[i];
             const double nrm = sqrt(tot);
-            if (nrm >= tiny && isfinite(nrm))
+            if (nrm >= tiny && isfinite(nrm) && tot - dd >= 0.01 * tot)
                 col_sel = -1;
         }
         __syncthreads();
@@ -647,9 +661,11 @@ void Launch<E>::colnorm(const E *R, int64_t ldr, int64_t M, int64_t N, double *c
 
 template <typename E>
 void Launch<E>::start(const E *R, int64_t ldr, int64_t M, int64_t N, const double *cn,
-                      const E *T0, StartArgs a, double tiny, E *t, LoopState *st, hipStream_t s)
+                      const E *V, const E *T0, StartArgs a, double tiny, E *t, LoopState *st,
+                      hipStream_t s)
 {
-    hipLaunchKernelGGL(k_start<E>, dim3(1), dim3(1024), 0, s, R, ldr, M, N, cn, T0, a, tiny, t, st);
+    hipLaunchKernelGGL(k_start<E>, dim3(1), dim3(1024), 0, s, R, ldr, M, N, cn, V, T0, a, tiny, t,
+                       st);
 }
 
 template <typename E>

@@ -1,0 +1,665 @@
+// mlp.hip -- learned warm start (not in the paper, whose start vector is a
+// residual column, Secs. 2.2-2.3): a whitened random sketch of X and a small
+// row-wise multilayer perceptron that predicts the initial scores, with its
+// training step.  The C ABI is declared in gspca_ws.h.
+//
+// The network's products run on bfloat16 matrix cores
+// (v_mfma_f32_16x16x32_bf16, FP32 accumulation).  bf16 rounding points: the
+// input rows, the weights, the stored hidden activations, the incoming
+// gradient dL/do and the masked hidden gradients.  Biases, outputs and
+// parameter gradients are FP32; weight gradients reduce over the rows with a
+// split-K scheme whose partial sums are added in a fixed order, so a step is
+// deterministic.
+#include <float.h>
+#include <hip/hip_bf16.h>
+#include <math.h>
+
+#include <algorithm>
+
+#include "../../include/gspca_ws.h"
+#include "internal.h"
+
+namespace gspca {
+
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float mf32x4_t __attribute__((ext_vector_type(4)));
+
+__device__ inline __bf16 to_bf16(float x)
+{
+    const __hip_bfloat16 h = __float2bfloat16(x);
+    return *reinterpret_cast<const __bf16 *>(&h);
+}
+__device__ inline __bf16 to_bf16(__bf16 x) { return x; }
+
+// ---------------------------------------------------------------------------
+// C = A B (+ bias, relu, mask) with bf16 operands and FP32 accumulation.
+// A(i, k) = A[i*a_r + k*a_c] (M x Kd), B(k, j) = B[k*b_r + j*b_c] (Kd x N);
+// strides express the transposes of the backward pass.  FP32 operands are
+// rounded to bf16 as they are loaded.  One wave computes a 16 x 16 tile, a
+// workgroup of four waves a 32 x 32 tile.  blockIdx.z splits the k range into
+// chunks of `kchunk` (a multiple of 32):
+//   - split == 0: C(i, j) at Cf[i*c_r + j*c_c] (FP32, + bias, relu, mask,
+//     optionally added to the old value) or Cb (bf16); mask zeroes C(i, j)
+//     where the stored activation mask[i*m_r + j] is not positive;
+//   - split != 0: raw partial sums to part[z*M*N + i*N + j].
+
+template <typename TA, typename TB>
+__global__ __launch_bounds__(256) void k_gemm_bf16(
+    const TA *__restrict__ A, int64_t a_r, int64_t a_c, const TB *__restrict__ B, int64_t b_r,
+    int64_t b_c, int64_t M, int64_t N, int64_t Kd, int64_t kchunk, const float *__restrict__ bias,
+    int relu, const __bf16 *__restrict__ mask, int64_t m_r, float *__restrict__ Cf,
+    __bf16 *__restrict__ Cb, int64_t c_r, int64_t c_c, int accumulate, int split,
+    float *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t i0 = (int64_t)blockIdx.y * 32 + (w >> 1) * 16;
+    const int64_t j0 = (int64_t)blockIdx.x * 32 + (w & 1) * 16;
+    const int64_t ia = i0 + (lane & 15); // row of A this lane feeds
+    const int64_t jb = j0 + (lane & 15); // column of B this lane feeds
+    const int kq = (lane >> 4) * 8;      // its 8 consecutive k within a 32-chunk
+    const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
+    const int64_t kend = std::min<int64_t>(Kd, kbeg + kchunk);
+    const bool rowa = ia < M, colb = jb < N;
+    const TA *ap = A + (rowa ? ia : 0) * a_r;
+    const TB *bp = B + (colb ? jb : 0) * b_c;
+    mf32x4_t acc = {0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
+        bf16x8_t av, bv;
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int64_t k = k0 + kq + e;
+            const bool kin = k < kend;
+            av[e] = (rowa && kin) ? to_bf16(ap[k * a_c]) : (__bf16)0.0f;
+            bv[e] = (colb && kin) ? to_bf16(bp[k * b_r]) : (__bf16)0.0f;
+        }
+        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
+    }
+    // lane holds C(i0 + (lane/16)*4 + e, j0 + lane%16), e = 0..3
+    const int64_t j = j0 + (lane & 15);
+    if (j >= N)
+        return;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+        const int64_t i = i0 + (lane >> 4) * 4 + e;
+        if (i >= M)
+            continue;
+        float v = acc[e];
+        if (split) {
+            part[(int64_t)blockIdx.z * M * N + i * N + j] = v;
+            continue;
+        }
+        if (bias)
+            v += bias[j];
+        if (relu && !(v > 0.0f))
+            v = 0.0f;
+        if (mask && !((float)mask[i * m_r + j] > 0.0f))
+            v = 0.0f;
+        if (Cf) {
+            float *dst = Cf + i * c_r + j * c_c;
+            *dst = accumulate ? *dst + v : v;
+        } else {
+            Cb[i * c_r + j * c_c] = to_bf16(v);
+        }
+    }
+}
+
+// C(i, j) = sum_z part[z][i][j] in increasing z (FP32, row-major M x N out
+// with strides c_r, c_c).
+__global__ __launch_bounds__(256) void k_split_reduce(const float *__restrict__ part, int nz,
+                                                      int64_t M, int64_t N, float *__restrict__ C,
+                                                      int64_t c_r, int64_t c_c)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= M * N)
+        return;
+    float s = 0.0f;
+    for (int z = 0; z < nz; ++z)
+        s += part[(int64_t)z * M * N + e];
+    const int64_t i = e / N, j = e % N;
+    C[i * c_r + j * c_c] = s;
+}
+
+// Column sums of a row-major rows x N matrix: block (x, z) sums columns
+// [64x, 64x + 64) over its row range; partials part[z*N + j].
+template <typename T>
+__global__ __launch_bounds__(256) void k_colsum_part(const T *__restrict__ G, int64_t rows,
+                                                     int64_t N, int64_t rchunk,
+                                                     float *__restrict__ part)
+{
+    __shared__ float red[4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t r0 = (int64_t)blockIdx.z * rchunk;
+    const int64_t r1 = std::min<int64_t>(rows, r0 + rchunk);
+    float s = 0.0f;
+    if (j < N)
+        for (int64_t r = r0 + w; r < r1; r += 4)
+            s += (float)G[r * N + j];
+    red[w][lane] = s;
+    __syncthreads();
+    if (w == 0 && j < N)
+        part[(int64_t)blockIdx.z * N + j] = red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
+}
+
+// Loss and dL/dO for matrix b and column k.  O row-major rows x K (FP32),
+// V column-major per matrix (V[b*Mi*K + m + k*Mi]); dO row-major bf16, scaled
+// by `inv` (1 / number of matrices).
+__global__ __launch_bounds__(256) void k_cos2(const float *__restrict__ O,
+                                              const float *__restrict__ V, int64_t Mi, int K,
+                                              double inv, __bf16 *__restrict__ dO,
+                                              double *__restrict__ loss_part)
+{
+    __shared__ double red[3][4];
+    const int k = blockIdx.x, b = blockIdx.y;
+    const int64_t r0 = (int64_t)b * Mi;
+    const float *v = V + (int64_t)b * Mi * K + (int64_t)k * Mi;
+    double ov = 0.0, oo = 0.0, vv = 0.0;
+    for (int64_t m = threadIdx.x; m < Mi; m += 256) {
+        const double o = O[(r0 + m) * K + k], x = v[m];
+        ov += o * x;
+        oo += o * o;
+        vv += x * x;
+    }
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        ov += __shfl_xor(ov, o, 64);
+        oo += __shfl_xor(oo, o, 64);
+        vv += __shfl_xor(vv, o, 64);
+    }
+    const int w = threadIdx.x >> 6;
+    if ((threadIdx.x & 63) == 0) {
+        red[0][w] = ov;
+        red[1][w] = oo;
+        red[2][w] = vv;
+    }
+    __syncthreads();
+    ov = red[0][0] + red[0][1] + red[0][2] + red[0][3];
+    oo = red[1][0] + red[1][1] + red[1][2] + red[1][3];
+    vv = red[2][0] + red[2][1] + red[2][2] + red[2][3];
+    const bool ok = oo > 0.0 && vv > 0.0 && isfinite(oo) && isfinite(vv);
+    // d/do [-(o.v)^2 / (|o|^2 |v|^2)] = -2 (o.v) v / (|o|^2 |v|^2) + 2 (o.v)^2 o / (|o|^4 |v|^2)
+    const double a = ok ? -2.0 * ov / (oo * vv) * inv : 0.0;
+    const double c = ok ? 2.0 * ov * ov / (oo * oo * vv) * inv : 0.0;
+    for (int64_t m = threadIdx.x; m < Mi; m += 256) {
+        const double g = a * (double)v[m] + c * (double)O[(r0 + m) * K + k];
+        dO[(r0 + m) * K + k] = to_bf16((float)g);
+    }
+    if (threadIdx.x == 0)
+        loss_part[(int64_t)b * K + k] = ok ? 1.0 - ov * ov / (oo * vv) : 1.0;
+}
+
+// loss = (sum of the parts in index order) * inv.  One thread.
+__global__ void k_loss_mean(const double *__restrict__ part, int64_t n, double inv,
+                            double *__restrict__ loss)
+{
+    double s = 0.0;
+    for (int64_t i = 0; i < n; ++i)
+        s += part[i];
+    *loss = s * inv;
+}
+
+// Adam (Kingma & Ba) on FP32 master weights; bf16 copy refreshed.
+__global__ __launch_bounds__(256) void k_adam(float *__restrict__ w, const float *__restrict__ g,
+                                              float *__restrict__ m1, float *__restrict__ m2,
+                                              __bf16 *__restrict__ wb, int64_t n, float lr,
+                                              float beta1, float beta2, float eps, float c1,
+                                              float c2)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i >= n)
+        return;
+    const float gi = g[i];
+    const float a = beta1 * m1[i] + (1.0f - beta1) * gi;
+    const float b = beta2 * m2[i] + (1.0f - beta2) * gi * gi;
+    m1[i] = a;
+    m2[i] = b;
+    const float v = w[i] - lr * (a / c1) / (sqrtf(b / c2) + eps);
+    w[i] = v;
+    wb[i] = to_bf16(v);
+}
+
+__global__ __launch_bounds__(256) void k_to_bf16(const float *__restrict__ x,
+                                                 __bf16 *__restrict__ y, int64_t n)
+{
+    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (i < n)
+        y[i] = to_bf16(x[i]);
+}
+
+// ---------------------------------------------------------------------------
+// Sketch and whitening.
+
+// Y = X Omega: thread per row, R accumulators (X column-major, Omega
+// row-major N x R, read uniformly by the wave).
+template <int R>
+__global__ __launch_bounds__(256) void k_sketch(const float *__restrict__ X, int64_t ldx,
+                                                int64_t M, int64_t N, const float *__restrict__ Om,
+                                                float *__restrict__ Y)
+{
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= M)
+        return;
+    float acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+        acc[c] = 0.0f;
+    for (int64_t j = 0; j < N; ++j) {
+        const float x = X[m + j * ldx];
+#pragma unroll
+        for (int c = 0; c < R; ++c)
+            acc[c] += x * Om[j * R + c];
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+        Y[m * R + c] = acc[c];
+}
+
+// G = Y^T Y in FP64 (thread per entry), parallel cyclic Jacobi (round-robin
+// pairing: R/2 disjoint rotations per round, R-1 rounds per sweep; rotation
+// of Golub & Van Loan's symmetric Schur step) until the off-diagonal mass is
+// below 1e-28 of |G|_F^2, then Z = sqrt(M) Y Q diag(g)^(-1/2) with the
+// eigenpairs by decreasing g and each eigenvector's largest entry positive.
+template <int R>
+__global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, int64_t M,
+                                                 float *__restrict__ Z, double *__restrict__ gout,
+                                                 int32_t *__restrict__ flag)
+{
+    __shared__ double G[R][R + 1];
+    __shared__ double Q[R][R + 1];
+    __shared__ double cs[R / 2], sn[R / 2];
+    __shared__ int pa[R / 2], pb[R / 2];
+    __shared__ double eig[R];
+    __shared__ int perm[R];
+    __shared__ double scale[R];
+    __shared__ double offsum[2];
+    const int a = threadIdx.x / R, b = threadIdx.x % R;
+    double s = 0.0;
+    for (int64_t m = 0; m < M; ++m)
+        s += (double)Y[m * R + a] * (double)Y[m * R + b];
+    G[a][b] = s;
+    Q[a][b] = a == b ? 1.0 : 0.0;
+    __syncthreads();
+    for (int sweep = 0; sweep < 60; ++sweep) {
+        if (threadIdx.x == 0) {
+            double off = 0.0, fro = 0.0;
+            for (int i = 0; i < R; ++i)
+                for (int j = 0; j < R; ++j) {
+                    fro += G[i][j] * G[i][j];
+                    if (i != j)
+                        off += G[i][j] * G[i][j];
+                }
+            offsum[0] = off;
+            offsum[1] = fro;
+        }
+        __syncthreads();
+        if (!(offsum[0] > 1e-28 * offsum[1]))
+            break;
+        for (int round = 0; round < R - 1; ++round) {
+            if (threadIdx.x < R / 2) {
+                // position 0 holds index 0; positions 1..R-1 rotate
+                const int i = threadIdx.x;
+                const int pos_a = i, pos_b = R - 1 - i;
+                int p = pos_a == 0 ? 0 : 1 + (pos_a - 1 + round) % (R - 1);
+                int q = 1 + (pos_b - 1 + round) % (R - 1);
+                if (p > q) {
+                    const int tmp = p;
+                    p = q;
+                    q = tmp;
+                }
+                pa[i] = p;
+                pb[i] = q;
+                const double apq = G[p][q];
+                double c = 1.0, sv = 0.0;
+                if (apq != 0.0) {
+                    const double tau = (G[q][q] - G[p][p]) / (2.0 * apq);
+                    const double t =
+                        (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
+                    c = 1.0 / sqrt(1.0 + t * t);
+                    sv = t * c;
+                }
+                cs[i] = c;
+                sn[i] = sv;
+            }
+            __syncthreads();
+            if (b < R / 2) { // G <- G J, Q <- Q J (thread: row a, pair b)
+                const int p = pa[b], q = pb[b];
+                const double c = cs[b], sv = sn[b];
+                const double gp = G[a][p], gq = G[a][q];
+                G[a][p] = c * gp - sv * gq;
+                G[a][q] = sv * gp + c * gq;
+                const double qp = Q[a][p], qq = Q[a][q];
+                Q[a][p] = c * qp - sv * qq;
+                Q[a][q] = sv * qp + c * qq;
+            }
+            __syncthreads();
+            if (b < R / 2) { // G <- J^T G (thread: column a, pair b)
+                const int p = pa[b], q = pb[b];
+                const double c = cs[b], sv = sn[b];
+                const double gp = G[p][a], gq = G[q][a];
+                G[p][a] = c * gp - sv * gq;
+                G[q][a] = sv * gp + c * gq;
+            }
+            __syncthreads();
+        }
+    }
+    if (threadIdx.x == 0) {
+        for (int i = 0; i < R; ++i) {
+            eig[i] = G[i][i];
+            perm[i] = i;
+        }
+        for (int i = 0; i < R; ++i) // selection sort, decreasing
+            for (int j = i + 1; j < R; ++j)
+                if (eig[perm[j]] > eig[perm[i]]) {
+                    const int t = perm[i];
+                    perm[i] = perm[j];
+                    perm[j] = t;
+                }
+        int bad = 0;
+        const double rm = sqrt((double)M);
+        for (int i = 0; i < R; ++i) {
+            const int c = perm[i];
+            double amax = -1.0, sgn = 1.0;
+            for (int r = 0; r < R; ++r)
+                if (fabs(Q[r][c]) > amax) {
+                    amax = fabs(Q[r][c]);
+                    sgn = Q[r][c] >= 0.0 ? 1.0 : -1.0;
+                }
+            const double g = eig[c];
+            const bool ok = g > 0.0 && isfinite(g);
+            bad |= !ok;
+            scale[i] = ok ? rm / sqrt(g) * sgn : 0.0;
+            if (gout)
+                gout[i] = g;
+        }
+        if (flag)
+            *flag = bad;
+    }
+    __syncthreads();
+    // Z = Y Q[:, perm] diag(scale): thread (row offset a, output column b)
+    const int c = perm[b];
+    for (int64_t m = a; m < M; m += R) {
+        double z = 0.0;
+        for (int r = 0; r < R; ++r)
+            z += (double)Y[m * R + r] * Q[r][c];
+        Z[m * R + b] = (float)(z * scale[b]);
+    }
+}
+
+// ---------------------------------------------------------------------------
+// Host side.
+
+namespace {
+
+inline unsigned ucdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
+inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+struct Offs {
+    int64_t W1, b1, W2, b2, W3, b3, n;
+};
+Offs param_offsets(int d0, int d1, int d2, int d3)
+{
+    Offs o;
+    o.W1 = 0;
+    o.b1 = o.W1 + (int64_t)d0 * d1;
+    o.W2 = o.b1 + d1;
+    o.b2 = o.W2 + (int64_t)d1 * d2;
+    o.W3 = o.b2 + d2;
+    o.b3 = o.W3 + (int64_t)d2 * d3;
+    o.n = o.b3 + d3;
+    return o;
+}
+
+bool valid_net(const gspca_mlp *n)
+{
+    return n && n->d0 == GSPCA_WS_RANK && n->d1 >= 16 && n->d1 <= 1024 && n->d2 >= 16 &&
+           n->d2 <= 1024 && n->d3 >= 1 && n->d3 <= 64 && n->theta && n->theta_bf16;
+}
+
+// Split-K partial buffer: enough for any weight gradient with <= kMaxSplit
+// splits.
+constexpr int kMaxSplit = 64;
+
+struct Layout {
+    size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, total;
+};
+Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst)
+{
+    Layout L{};
+    size_t o = 0;
+    auto put = [&](size_t &slot, size_t bytes) {
+        slot = o;
+        o = align256(o + bytes);
+    };
+    const int64_t dmax = std::max<int64_t>(std::max<int64_t>(n->d0, n->d1),
+                                           std::max<int64_t>(n->d2, n->d3));
+    put(L.H1, (size_t)rows * n->d1 * 2);
+    put(L.H2, (size_t)rows * n->d2 * 2);
+    put(L.O, (size_t)rows * n->d3 * 4);
+    put(L.dO, (size_t)rows * n->d3 * 2);
+    put(L.G2, (size_t)rows * n->d2 * 2);
+    put(L.G1, (size_t)rows * n->d1 * 2);
+    put(L.lossp, (size_t)std::max<int32_t>(ninst, 1) * n->d3 * 8);
+    put(L.part, (size_t)kMaxSplit * dmax * dmax * 4);
+    put(L.Y, (size_t)rows * GSPCA_WS_RANK * 4);
+    put(L.Z, (size_t)rows * GSPCA_WS_RANK * 4);
+    L.total = o;
+    return L;
+}
+
+template <typename TA, typename TB>
+void gemm_launch(const TA *A, int64_t a_r, int64_t a_c, const TB *B, int64_t b_r, int64_t b_c,
+                 int64_t M, int64_t N, int64_t Kd, const float *bias, int relu, const __bf16 *mask,
+                 int64_t m_r, float *Cf, __bf16 *Cb, int64_t c_r, int64_t c_c, float *part,
+                 hipStream_t s)
+{
+    // Split the k range when the output tiles alone cannot fill the chip
+    // (weight gradients: small outputs, k = all rows).
+    const int64_t tiles = (int64_t)ucdiv(M, 32) * ucdiv(N, 32);
+    int nz = 1;
+    if (part && tiles < 1024 && Kd >= 4096) {
+        nz = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, 2048 / tiles));
+        nz = (int)std::min<int64_t>(nz, Kd / 1024);
+    }
+    const int64_t kchunk = ((Kd + nz - 1) / nz + 31) / 32 * 32;
+    nz = (int)((Kd + kchunk - 1) / kchunk);
+    dim3 g(ucdiv(N, 32), ucdiv(M, 32), nz);
+    hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), g, dim3(256), 0, s, A, a_r, a_c, B, b_r, b_c, M, N,
+                       Kd, kchunk, bias, relu, mask, m_r, Cf, Cb, c_r, c_c, 0, nz > 1 ? 1 : 0,
+                       part);
+    if (nz > 1)
+        hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(M * N, 256)), dim3(256), 0, s, part, nz, M,
+                           N, Cf, c_r, c_c);
+}
+
+template <typename T>
+void colsum(const T *G, int64_t rows, int64_t N, float *out, float *part, hipStream_t s)
+{
+    const int nz = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, rows / 2048));
+    const int64_t rchunk = (rows + nz - 1) / nz;
+    hipLaunchKernelGGL(k_colsum_part<T>, dim3(ucdiv(N, 64), 1, nz), dim3(256), 0, s, G, rows, N,
+                       rchunk, part);
+    hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(N, 256)), dim3(256), 0, s, part, nz, (int64_t)1,
+                       N, out, (int64_t)0, (int64_t)1);
+}
+
+// Forward over `rows` rows: H1, H2 (bf16, row-major) and the output with
+// strides (o_r, o_c).
+void forward(const gspca_mlp *n, const float *Z, int64_t rows, __bf16 *H1, __bf16 *H2, float *O,
+             int64_t o_r, int64_t o_c, hipStream_t s)
+{
+    const Offs of = param_offsets(n->d0, n->d1, n->d2, n->d3);
+    const __bf16 *wb = reinterpret_cast<const __bf16 *>(n->theta_bf16);
+    const float *th = n->theta;
+    gemm_launch<float, __bf16>(Z, n->d0, 1, wb + of.W1, n->d1, 1, rows, n->d1, n->d0, th + of.b1,
+                               1, nullptr, 0, nullptr, H1, n->d1, 1, nullptr, s);
+    gemm_launch<__bf16, __bf16>(H1, n->d1, 1, wb + of.W2, n->d2, 1, rows, n->d2, n->d1,
+                                th + of.b2, 1, nullptr, 0, nullptr, H2, n->d2, 1, nullptr, s);
+    gemm_launch<__bf16, __bf16>(H2, n->d2, 1, wb + of.W3, n->d3, 1, rows, n->d3, n->d2,
+                                th + of.b3, 0, nullptr, 0, O, nullptr, o_r, o_c, nullptr, s);
+}
+
+gspca_status launched()
+{
+    return hipGetLastError() == hipSuccess ? GSPCA_OK : GSPCA_EDEVICE;
+}
+
+} // namespace
+} // namespace gspca
+
+using namespace gspca;
+
+extern "C" {
+
+int64_t gspca_mlp_param_count(int32_t d0, int32_t d1, int32_t d2, int32_t d3)
+{
+    if (d0 < 1 || d1 < 1 || d2 < 1 || d3 < 1)
+        return 0;
+    return param_offsets(d0, d1, d2, d3).n;
+}
+
+size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst)
+{
+    if (!net || rows < 1 || ninst < 1)
+        return 0;
+    return layout(net, rows, ninst).total;
+}
+
+gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Omega,
+                          int32_t r, float *Y, void *stream)
+{
+    if (!X || !Omega || !Y || r != GSPCA_WS_RANK || M < 1 || N < 1 || ldx < M)
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
+                       N, Omega, Y);
+    return launched();
+}
+
+gspca_status gspca_whiten_sketch(const float *Y, int64_t M, int32_t r, float *Z, double *gamma,
+                                 int32_t *flag, void *stream)
+{
+    if (!Y || !Z || r != GSPCA_WS_RANK || M < r)
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1), dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0,
+                       s, Y, M, Z, gamma, flag);
+    return launched();
+}
+
+gspca_status gspca_mlp_sync(const gspca_mlp *net, void *stream)
+{
+    if (!valid_net(net))
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = param_offsets(net->d0, net->d1, net->d2, net->d3).n;
+    hipLaunchKernelGGL(k_to_bf16, dim3(ucdiv(n, 256)), dim3(256), 0, s, net->theta,
+                       reinterpret_cast<__bf16 *>(net->theta_bf16), n);
+    return launched();
+}
+
+gspca_status gspca_mlp_forward(const gspca_mlp *net, const float *Z, int64_t rows, float *O,
+                               void *ws, size_t ws_bytes, void *stream)
+{
+    if (!valid_net(net) || !Z || !O || rows < 1 || !ws)
+        return GSPCA_EINVAL;
+    const Layout L = layout(net, rows, 1);
+    if (ws_bytes < L.total)
+        return GSPCA_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    forward(net, Z, rows, reinterpret_cast<__bf16 *>(b + L.H1),
+            reinterpret_cast<__bf16 *>(b + L.H2), O, 1, rows, s);
+    return launched();
+}
+
+gspca_status gspca_mlp_loss_grad(const gspca_mlp *net, const float *Z, const float *V,
+                                 int32_t ninst, int64_t rows_per_inst, double *loss, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    if (!valid_net(net) || !net->grad || !Z || !V || ninst < 1 || rows_per_inst < 1 || !ws)
+        return GSPCA_EINVAL;
+    const int64_t rows = (int64_t)ninst * rows_per_inst;
+    const Layout L = layout(net, rows, ninst);
+    if (ws_bytes < L.total)
+        return GSPCA_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    __bf16 *H1 = reinterpret_cast<__bf16 *>(b + L.H1);
+    __bf16 *H2 = reinterpret_cast<__bf16 *>(b + L.H2);
+    float *O = reinterpret_cast<float *>(b + L.O);
+    __bf16 *dO = reinterpret_cast<__bf16 *>(b + L.dO);
+    __bf16 *G2 = reinterpret_cast<__bf16 *>(b + L.G2);
+    __bf16 *G1 = reinterpret_cast<__bf16 *>(b + L.G1);
+    double *lossp = reinterpret_cast<double *>(b + L.lossp);
+    float *part = reinterpret_cast<float *>(b + L.part);
+    const int d0 = net->d0, d1 = net->d1, d2 = net->d2, d3 = net->d3;
+    const Offs of = param_offsets(d0, d1, d2, d3);
+    const __bf16 *wb = reinterpret_cast<const __bf16 *>(net->theta_bf16);
+    float *g = net->grad;
+
+    forward(net, Z, rows, H1, H2, O, d3, 1, s);
+    const double inv = 1.0 / (double)ninst;
+    hipLaunchKernelGGL(k_cos2, dim3(d3, ninst), dim3(256), 0, s, O, V, rows_per_inst, d3, inv, dO,
+                       lossp);
+    if (loss)
+        hipLaunchKernelGGL(k_loss_mean, dim3(1), dim3(1), 0, s, lossp, (int64_t)ninst * d3, inv,
+                           loss);
+    // layer 3: dW3 = H2^T dO, db3 = colsum(dO), G2 = (dO W3^T) * [H2 > 0]
+    gemm_launch<__bf16, __bf16>(H2, 1, d2, dO, d3, 1, d2, d3, rows, nullptr, 0, nullptr, 0,
+                                g + of.W3, nullptr, d3, 1, part, s);
+    colsum<__bf16>(dO, rows, d3, g + of.b3, part, s);
+    gemm_launch<__bf16, __bf16>(dO, d3, 1, wb + of.W3, 1, d3, rows, d2, d3, nullptr, 0, H2, d2,
+                                nullptr, G2, d2, 1, nullptr, s);
+    // layer 2: dW2 = H1^T G2, db2 = colsum(G2), G1 = (G2 W2^T) * [H1 > 0]
+    gemm_launch<__bf16, __bf16>(H1, 1, d1, G2, d2, 1, d1, d2, rows, nullptr, 0, nullptr, 0,
+                                g + of.W2, nullptr, d2, 1, part, s);
+    colsum<__bf16>(G2, rows, d2, g + of.b2, part, s);
+    gemm_launch<__bf16, __bf16>(G2, d2, 1, wb + of.W2, 1, d2, rows, d1, d2, nullptr, 0, H1, d1,
+                                nullptr, G1, d1, 1, nullptr, s);
+    // layer 1: dW1 = Z^T G1 (Z rounded to bf16 as loaded), db1 = colsum(G1)
+    gemm_launch<float, __bf16>(Z, 1, d0, G1, d1, 1, d0, d1, rows, nullptr, 0, nullptr, 0,
+                               g + of.W1, nullptr, d1, 1, part, s);
+    colsum<__bf16>(G1, rows, d1, g + of.b1, part, s);
+    return launched();
+}
+
+gspca_status gspca_mlp_adam(gspca_mlp *net, float lr, float beta1, float beta2, float eps,
+                            void *stream)
+{
+    if (!valid_net(net) || !net->grad || !net->adam_m || !net->adam_v || !(lr > 0.0f) ||
+        !(beta1 >= 0.0f && beta1 < 1.0f) || !(beta2 >= 0.0f && beta2 < 1.0f) || !(eps > 0.0f))
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int64_t n = param_offsets(net->d0, net->d1, net->d2, net->d3).n;
+    net->step += 1;
+    const float c1 = (float)(1.0 - pow((double)beta1, net->step));
+    const float c2 = (float)(1.0 - pow((double)beta2, net->step));
+    hipLaunchKernelGGL(k_adam, dim3(ucdiv(n, 256)), dim3(256), 0, s, net->theta, net->grad,
+                       net->adam_m, net->adam_v, reinterpret_cast<__bf16 *>(net->theta_bf16), n,
+                       lr, beta1, beta2, eps, c1, c2);
+    return launched();
+}
+
+gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx, int64_t M,
+                              int64_t N, const float *Omega, float *T0, void *ws, size_t ws_bytes,
+                              void *stream)
+{
+    if (!valid_net(net) || !X || !Omega || !T0 || M < GSPCA_WS_RANK || N < 1 || ldx < M || !ws)
+        return GSPCA_EINVAL;
+    const Layout L = layout(net, M, 1);
+    if (ws_bytes < L.total)
+        return GSPCA_EWORKSPACE;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    unsigned char *b = static_cast<unsigned char *>(ws);
+    float *Y = reinterpret_cast<float *>(b + L.Y);
+    float *Z = reinterpret_cast<float *>(b + L.Z);
+    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
+                       N, Omega, Y);
+    hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1), dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0,
+                       s, Y, M, Z, nullptr, nullptr);
+    forward(net, Z, M, reinterpret_cast<__bf16 *>(b + L.H1), reinterpret_cast<__bf16 *>(b + L.H2),
+            T0, 1, M, s);
+    return launched();
+}
+
+} // extern "C"
