@@ -188,8 +188,9 @@ gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, i
  * 1 <= K <= min(M, N, 64)) with its own outputs, as in gspca_result, plus an
  * int32 status word written by the device (0 OK, 1 NOT_CONVERGED,
  * -4 ENONFINITE).  GS-PCA with implicit deflation (X is never written); the
- * options' algo must be GS, init MAXNORM or COLUMN_K; replay arrays are taken
- * per problem.  All pointers are device pointers. */
+ * options' algo must be GS; init MAXNORM, COLUMN_K or GIVEN (then every
+ * problem's T0 is required; the fallback rule of a given start applies);
+ * replay arrays are taken per problem.  All pointers are device pointers. */
 typedef struct {
     const float *X;
     int64_t ldx;
@@ -203,6 +204,8 @@ typedef struct {
     const int32_t *replay_iters;     /* K, nullable (testing)                   */
     const int32_t *replay_start_col; /* K, nullable (testing)                   */
     int32_t *status;     /* one int32, nullable                                 */
+    const float *T0;     /* M x K start vectors (leading dimension M), read when
+                            options.init == GSPCA_INIT_GIVEN; else ignored      */
 } gspca_batch_problem;
 
 /* Launch plan filled by gspca_batched_prepare (host memory, opaque). */

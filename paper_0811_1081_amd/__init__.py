@@ -203,7 +203,7 @@ class Batch:
     Outputs are preallocated device tensors; every launch refits all problems."""
 
     def __init__(self, Xs, K, tol=1e-6, max_iter=1000, init="maxnorm", stop="sigma",
-                 replay_iters=None, replay_start=None, stream=None):
+                 replay_iters=None, replay_start=None, T0=None, stream=None):
         import torch
         L = _b.load()
         n = len(Xs)
@@ -213,7 +213,9 @@ class Batch:
         self.T, self.P, self.lam, self.sigma, self.iters, self.start_col = [], [], [], [], [], []
         self.status = torch.zeros(n, dtype=torch.int32, device=dev)
         arr = (_b.BatchProblem * n)()
-        self._keep = [replay_iters, replay_start]
+        self._keep = [replay_iters, replay_start, T0]
+        if (init == "given") != (T0 is not None):
+            raise ValueError("init='given' needs T0 (one column-major (M, K) float32 per problem)")
         for i, X in enumerate(Xs):
             if X.dtype != torch.float32 or X.stride(0) != 1 or not X.is_cuda:
                 raise ValueError("batched problems must be column-major float32 device matrices")
@@ -229,9 +231,16 @@ class Batch:
             self.iters.append(it); self.start_col.append(sc)
             ri = replay_iters[i].data_ptr() if replay_iters is not None else None
             rs = replay_start[i].data_ptr() if replay_start is not None else None
+            t0 = None
+            if T0 is not None:
+                g = T0[i]
+                if (g.dtype != torch.float32 or tuple(g.shape) != (M, k) or g.stride() != (1, M)
+                        or g.device != dev):
+                    raise ValueError("T0[%d] must be a column-major (M, K) float32 device tensor" % i)
+                t0 = g.data_ptr()
             arr[i] = _b.BatchProblem(X.data_ptr(), X.stride(1), M, N, k, T.data_ptr(),
                                      P.data_ptr(), lam.data_ptr(), sig.data_ptr(), it.data_ptr(),
-                                     sc.data_ptr(), ri, rs, self.status.data_ptr() + 4 * i)
+                                     sc.data_ptr(), ri, rs, self.status.data_ptr() + 4 * i, t0)
         self._arr = arr
         nbytes = int(L.gspca_batched_workspace_bytes(arr, n))
         if nbytes == 0:

@@ -64,7 +64,7 @@ class BatchProblem(ctypes.Structure):
                 ("P", ctypes.c_void_p), ("lambda_", ctypes.c_void_p), ("sigma", ctypes.c_void_p),
                 ("iters", ctypes.c_void_p), ("start_col", ctypes.c_void_p),
                 ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
-                ("status", ctypes.c_void_p)]
+                ("status", ctypes.c_void_p), ("T0", ctypes.c_void_p)]
 
 
 class BatchPlan(ctypes.Structure):

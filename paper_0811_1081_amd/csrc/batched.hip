@@ -58,7 +58,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
     extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int cur, bad;
-    __shared__ int64_t sel;
+    __shared__ int64_t sel, selmax;
     __shared__ double sred[16];
     __shared__ int64_t ired[16];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -144,20 +144,53 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 int64_t i0 = ired[0];
                 for (int i = 1; i < nw; ++i)
                     if (sred[i] > b || (sred[i] == b && ired[i] < i0)) { b = sred[i]; i0 = ired[i]; }
-                if (it.replay_start && it.replay_start[k] >= 0 && it.replay_start[k] < N)
+                selmax = i0;
+                const bool replayed =
+                    it.replay_start && it.replay_start[k] >= 0 && it.replay_start[k] < N;
+                if (replayed)
                     i0 = it.replay_start[k];
                 else if (a.init == 1 && sqrt(q[k]) >= a.tiny)
                     i0 = k;
+                else if (a.init == 2 && it.T0)
+                    i0 = -1; // given vector, if it passes the test below
                 sel = i0;
             }
             __syncthreads();
+            if (sel < 0) {
+                // Given start: keep it if its norm is at least tiny and finite
+                // and more than a tenth of it lies outside span(V_(k))
+                // (|g|^2 - sum_i (v_i . g)^2, V orthonormal); else the
+                // largest residual column.
+                const float *g0 = it.T0 + (int64_t)k * M;
+                double gg = 0.0;
+                for (int m = tid; m < M; m += NT)
+                    gg += (double)g0[m] * (double)g0[m];
+                gg = bblock_sum(gg, red);
+                double dd = 0.0;
+                for (int i = 0; i < k; ++i) {
+                    double d = 0.0;
+                    for (int m = tid; m < M; m += NT)
+                        d += (double)T[m + (int64_t)i * M] * (double)g0[m];
+                    d = bblock_sum(d, red);
+                    dd += d * d;
+                }
+                if (tid == 0 && !(sqrt(gg) >= a.tiny && isfinite(gg) && gg - dd >= 0.01 * gg))
+                    sel = selmax;
+                __syncthreads();
+            }
             const int64_t c0 = sel;
-            // t0 = X_c - sum_i s_i v_i P_ci
+            // t0 = X_c - sum_i s_i v_i P_ci, or the given vector
             double ss = 0.0;
             for (int m = tid; m < M; m += NT) {
-                double v = (double)X[m + c0 * ldx];
-                for (int i = 0; i < k; ++i)
-                    v -= sig[i] * (double)T[m + (int64_t)i * M] * (double)P[c0 + (int64_t)i * N];
+                double v;
+                if (c0 >= 0) {
+                    v = (double)X[m + c0 * ldx];
+                    for (int i = 0; i < k; ++i)
+                        v -= sig[i] * (double)T[m + (int64_t)i * M] *
+                             (double)P[c0 + (int64_t)i * N];
+                } else {
+                    v = (double)it.T0[m + (int64_t)k * M];
+                }
                 t[m] = v;
                 ss += v * v;
             }

@@ -152,8 +152,13 @@ gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t npr
 {
     if (!probs || nprob < 1 || !opt || !plan)
         return GSPCA_EINVAL;
-    if (opt->algo != GSPCA_GS || (opt->init != GSPCA_INIT_MAXNORM && opt->init != GSPCA_INIT_COLUMN_K))
+    if (opt->algo != GSPCA_GS || (opt->init != GSPCA_INIT_MAXNORM &&
+                                  opt->init != GSPCA_INIT_COLUMN_K && opt->init != GSPCA_INIT_GIVEN))
         return GSPCA_EINVAL;
+    if (opt->init == GSPCA_INIT_GIVEN)
+        for (int32_t i = 0; i < nprob; ++i)
+            if (!probs[i].T0)
+                return GSPCA_EINVAL;
     if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_iter < 1 ||
         (opt->stop != GSPCA_STOP_SIGMA_REL && opt->stop != GSPCA_STOP_LOADING))
         return GSPCA_EINVAL;
@@ -190,6 +195,7 @@ gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t npr
         b.replay_iters = p.replay_iters;
         b.replay_start = p.replay_start_col;
         b.status = p.status;
+        b.T0 = opt->init == GSPCA_INIT_GIVEN ? p.T0 : nullptr;
         b.W = reinterpret_cast<double *>(base + woff);
         woff = align_b(woff + (size_t)p.N * (size_t)p.K * 8);
         lds = std::max(lds, batched_lds_bytes(p.M, p.N, p.K));

@@ -124,6 +124,7 @@ struct BatchItem {
     const int32_t *replay_iters, *replay_start;
     int32_t *status;
     double *W; // N x K workspace
+    const float *T0; // given start vectors (M x K), init == GIVEN
 };
 struct BatchArgs {
     double tol, tiny;

@@ -145,6 +145,6 @@ def warmstart_instance(i: int, M: int = 2048, N: int = 256, return_factors: bool
 
 
 def sketch_matrix(N: int = 256, r: int = 32) -> np.ndarray:
-    """Fixed Gaussian test matrix Omega (N x r) used for the warm-start sketch X*Omega."""
+    """Fixed Gaussian test matrix Omega (N x r, row-major) for the warm-start sketch X*Omega."""
     rng = rng_for(5, 999_999)
-    return np.asfortranarray(rng.standard_normal((N, r)).astype(np.float32))
+    return np.ascontiguousarray(rng.standard_normal((N, r)).astype(np.float32))

@@ -1,0 +1,353 @@
+"""Learned warm start for GS-PCA (not in the paper; C ABI in ``include/gspca_ws.h``).
+
+The paper starts each component from a residual column (Secs. 2.2-2.3).  Here
+a row-wise network maps the whitened random sketch of X to K start vectors,
+which ``fit(..., init="given", T0=...)`` consumes.  Every step -- sketch,
+whitening, the bf16 matrix-core forward and backward passes, the loss and
+Adam -- runs in ``libgspca.so``; this module only allocates tensors and passes
+pointers.
+
+    net = WarmStartNet(K=16, seed=0)
+    T0 = net.predict(X, Omega)                    # X column-major float32 (M, N)
+    out = gp.fit(X, 16, init="given", T0=T0)
+"""
+from __future__ import annotations
+
+import ctypes
+
+import numpy as np
+
+from . import _binding as _b
+from ._binding import OK, GspcaError
+
+RANK = _b.WS_RANK
+
+
+def _stream(stream, dev):
+    import torch
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    return stream.cuda_stream
+
+
+def _check(st):
+    st = int(st)
+    if st != OK:
+        raise GspcaError(st)
+
+
+def _aligned(nbytes, dev):
+    import torch
+    buf = torch.empty(int(nbytes) + 256, dtype=torch.uint8, device=dev)
+    return buf, buf.data_ptr() + ((-buf.data_ptr()) % 256)
+
+
+def sketch(X, Omega, stream=None):
+    """Y = X Omega (M x 32, row-major float32).  X column-major float32 on the
+    device, Omega (N x 32) float32 on the device (row-major)."""
+    import torch
+    M, N = X.shape
+    if X.dtype != torch.float32 or X.stride(0) != 1:
+        raise ValueError("X must be column-major float32")
+    Om = Omega.contiguous()
+    if tuple(Om.shape) != (N, RANK) or Om.dtype != torch.float32:
+        raise ValueError("Omega must be (N, %d) float32" % RANK)
+    Y = torch.empty((M, RANK), dtype=torch.float32, device=X.device)
+    _check(_b.load().gspca_sketch(X.data_ptr(), X.stride(1), M, N, Om.data_ptr(), RANK,
+                                  Y.data_ptr(), _stream(stream, X.device)))
+    return Y
+
+
+def whiten(Y, stream=None):
+    """(Z, gamma, flag): Z = sqrt(M) Y Q diag(g)^(-1/2) (row-major M x 32)."""
+    import torch
+    M = Y.shape[0]
+    Y = Y.contiguous()
+    Z = torch.empty_like(Y)
+    g = torch.empty(RANK, dtype=torch.float64, device=Y.device)
+    flag = torch.zeros(1, dtype=torch.int32, device=Y.device)
+    _check(_b.load().gspca_whiten_sketch(Y.data_ptr(), M, RANK, Z.data_ptr(), g.data_ptr(),
+                                         flag.data_ptr(), _stream(stream, Y.device)))
+    return Z, g, flag
+
+
+class WarmStartNet:
+    """Row-wise network 32 -> d1 -> d2 -> K with FP32 master weights, bf16
+    copies and Adam state, all device tensors; parameters packed as
+    W1 b1 W2 b2 W3 b3 with W_l row-major (d_in x d_out)."""
+
+    def __init__(self, K, hidden=(256, 256), seed=0, device="cuda"):
+        import torch
+        self.dims = (RANK, int(hidden[0]), int(hidden[1]), int(K))
+        L = _b.load()
+        n = int(L.gspca_mlp_param_count(*self.dims))
+        self.n = n
+        self.device = torch.device(device)
+        f32 = dict(dtype=torch.float32, device=self.device)
+        self.theta = torch.from_numpy(self.init_params(self.dims, seed)).to(self.device)
+        self.theta_bf16 = torch.empty(n, dtype=torch.int16, device=self.device)
+        self.grad = torch.zeros(n, **f32)
+        self.adam_m = torch.zeros(n, **f32)
+        self.adam_v = torch.zeros(n, **f32)
+        self.net = _b.Mlp(*self.dims, self.theta.data_ptr(), self.theta_bf16.data_ptr(),
+                          self.grad.data_ptr(), self.adam_m.data_ptr(), self.adam_v.data_ptr(), 0, 0)
+        self._ws = None
+        self._ws_ptr = 0
+        self._ws_bytes = 0
+        self.sync()
+
+    @staticmethod
+    def init_params(dims, seed):
+        """He-normal weights (std sqrt(2 / d_in)), zero biases, float32."""
+        rng = np.random.default_rng([811, 13, int(seed)])
+        parts = []
+        for a, b in zip(dims[:-1], dims[1:]):
+            parts.append((rng.standard_normal((a, b)) * np.sqrt(2.0 / a)).ravel())
+            parts.append(np.zeros(b))
+        return np.concatenate(parts).astype(np.float32)
+
+    def unpack(self, flat):
+        """Split a packed host vector into (W1, b1, W2, b2, W3, b3)."""
+        out, o = [], 0
+        for a, b in zip(self.dims[:-1], self.dims[1:]):
+            out.append(flat[o:o + a * b].reshape(a, b)); o += a * b
+            out.append(flat[o:o + b]); o += b
+        return out
+
+    @property
+    def step(self):
+        return int(self.net.step)
+
+    def _workspace(self, rows, ninst):
+        need = int(_b.load().gspca_mlp_workspace_bytes(ctypes.byref(self.net), int(rows),
+                                                        int(ninst)))
+        if need > self._ws_bytes:
+            self._ws, self._ws_ptr = _aligned(need, self.device)
+            self._ws_bytes = need
+        return self._ws_ptr, self._ws_bytes
+
+    def sync(self, stream=None):
+        _check(_b.load().gspca_mlp_sync(ctypes.byref(self.net), _stream(stream, self.device)))
+
+    def forward(self, Z, stream=None):
+        """O (rows x K, column-major float32) for row-major float32 Z (rows x 32)."""
+        import torch
+        Z = Z.contiguous()
+        rows = Z.shape[0]
+        O = torch.empty_strided((rows, self.dims[3]), (1, rows), dtype=torch.float32,
+                                device=self.device)
+        p, nb = self._workspace(rows, 1)
+        _check(_b.load().gspca_mlp_forward(ctypes.byref(self.net), Z.data_ptr(), rows,
+                                           O.data_ptr(), p, nb, _stream(stream, self.device)))
+        return O
+
+    def loss_grad(self, Z, V, ninst, rows_per_inst, loss=None, stream=None):
+        """Gradient of the mean loss over ninst matrices into self.grad; returns
+        the loss as a device double tensor.  V: per matrix column-major
+        (rows_per_inst x K) unit scores, stacked."""
+        import torch
+        if loss is None:
+            loss = torch.zeros(1, dtype=torch.float64, device=self.device)
+        p, nb = self._workspace(int(ninst) * int(rows_per_inst), ninst)
+        _check(_b.load().gspca_mlp_loss_grad(ctypes.byref(self.net), Z.data_ptr(), V.data_ptr(),
+                                             int(ninst), int(rows_per_inst), loss.data_ptr(), p,
+                                             nb, _stream(stream, self.device)))
+        return loss
+
+    def adam(self, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8, stream=None):
+        _check(_b.load().gspca_mlp_adam(ctypes.byref(self.net), float(lr), float(beta1),
+                                        float(beta2), float(eps), _stream(stream, self.device)))
+
+    def train_step(self, Z, V, ninst, rows_per_inst, lr=1e-3, stream=None):
+        loss = self.loss_grad(Z, V, ninst, rows_per_inst, stream=stream)
+        self.adam(lr, stream=stream)
+        return loss
+
+    def predict(self, X, Omega, stream=None):
+        """Start vectors T0 (M x K, column-major float32) for column-major float32 X."""
+        import torch
+        M, N = X.shape
+        if X.dtype != torch.float32 or X.stride(0) != 1:
+            raise ValueError("X must be column-major float32")
+        Om = Omega.contiguous()
+        T0 = torch.empty_strided((M, self.dims[3]), (1, M), dtype=torch.float32,
+                                 device=self.device)
+        p, nb = self._workspace(M, 1)
+        _check(_b.load().gspca_ws_predict(ctypes.byref(self.net), X.data_ptr(), X.stride(1), M, N,
+                                          Om.data_ptr(), T0.data_ptr(), p, nb,
+                                          _stream(stream, self.device)))
+        return T0
+
+    def state(self):
+        """Host copy of the weights and Adam state (for np.savez)."""
+        return {"dims": np.array(self.dims), "theta": self.theta.cpu().numpy(),
+                "adam_m": self.adam_m.cpu().numpy(), "adam_v": self.adam_v.cpu().numpy(),
+                "step": np.array(self.step)}
+
+    def load_state(self, st):
+        import torch
+        if tuple(int(x) for x in st["dims"]) != self.dims:
+            raise ValueError("dimension mismatch")
+        for name in ("theta", "adam_m", "adam_v"):
+            getattr(self, name).copy_(torch.from_numpy(np.asarray(st[name], dtype=np.float32)))
+        self.net.step = int(st["step"])
+        self.sync()
+
+
+# ---------------------------------------------------------------------------
+# Training and evaluation on synthetic matrices: s_j = r^j, r ~ U[0.7, 0.95],
+# Haar factors, no noise (synth.warmstart_instance).  Targets are the unit
+# scores of batched GS-PCA fits at a tight tolerance.
+
+def _instance(args):
+    from . import synth
+    i, M, N = args
+    X, U, V, ratio = synth.warmstart_instance(i, M=M, N=N, return_factors=True)
+    return X, V[:, :64].astype(np.float32), ratio
+
+
+def generate(indices, M, N, workers=8):
+    """Host matrices for the given instance numbers (a spawn pool; no GPU)."""
+    import multiprocessing as mp
+    args = [(int(i), M, N) for i in indices]
+    if workers <= 1 or len(args) < 4:
+        return [_instance(a) for a in args]
+    with mp.get_context("spawn").Pool(workers) as pool:
+        return pool.map(_instance, args, chunksize=8)
+
+
+def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512):
+    """Device data for training: X (column-major), whitened sketch Z, and the
+    unit scores V of GS-PCA fits (column-major per matrix, K columns)."""
+    import torch
+    from . import Batch, column_major
+    Xs, Zs, Vs = [], [], []
+    for lo in range(0, len(instances), chunk):
+        part = [column_major(torch.from_numpy(np.ascontiguousarray(x)).cuda())
+                for x, _, _ in instances[lo:lo + chunk]]
+        b = Batch(part, K, tol=tol, max_iter=max_iter)
+        b.launch()
+        for i, X in enumerate(part):
+            Zs.append(whiten(sketch(X, Omega))[0])
+            Vs.append((b.T[i] / b.sigma[i].clamp_min(1e-30).float()).t().contiguous())
+        Xs += part
+    torch.cuda.synchronize()
+    return Xs, Zs, Vs
+
+
+def evaluate(net, Xs, Zs, Vtrue, K, Omega, tol=1e-6, max_iter=3000, stop="sigma"):
+    """Iterations of batched fits from three starts -- max-norm column, the
+    un-learned sketch (first K whitened directions) and the network -- and the
+    final loading error (radians, sign-aligned) against the known factors."""
+    import torch
+    from . import Batch
+    M = Xs[0].shape[0]
+    starts = {"maxnorm": None,
+              "sketch": [(z[:, :K] / np.sqrt(M)).t().contiguous().t() for z in Zs],
+              "learned": [net.forward(z)[:, :K] for z in Zs]}
+    out = {}
+    for name, T0 in starts.items():
+        if T0 is not None:
+            T0 = [t.contiguous().t().contiguous().t() if t.stride() != (1, M) else t for t in T0]
+        b = Batch(Xs, K, tol=tol, max_iter=max_iter, stop=stop,
+                  init="given" if T0 is not None else "maxnorm", T0=T0)
+        ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        ev0.record()
+        b.launch()
+        ev1.record()
+        torch.cuda.synchronize()
+        its = np.stack([x.cpu().numpy() for x in b.iters]).astype(np.float64)
+        sc = np.stack([x.cpu().numpy() for x in b.start_col])
+        err = []
+        for i, P in enumerate(b.P):
+            Pp = P.cpu().numpy().astype(np.float64)
+            Vt = Vtrue[i][:, :K].astype(np.float64)
+            s = np.sign(np.sum(Pp * Vt, axis=0))
+            s[s == 0] = 1
+            d = np.linalg.norm(Pp - Vt * s, axis=0)
+            err.append(2 * np.arcsin(np.minimum(d / 2, 1.0)))
+        err = np.array(err)
+        out[name] = {
+            "iters_per_matrix_mean": float(its.sum(1).mean()),
+            "iters_per_matrix_median": float(np.median(its.sum(1))),
+            "iters_per_component_mean": float(its.mean()),
+            "loading_error_median": float(np.median(err)),
+            "loading_error_max": float(err.max()),
+            "fallback_rate": float(np.mean(sc >= 0)) if T0 is not None else None,
+            "batch_ms": float(ev0.elapsed_time(ev1)),
+            "status_ok": bool(np.all(b.status.cpu().numpy() == 0)),
+        }
+    return out
+
+
+def main(argv=None):
+    import argparse
+    import json
+    import time
+
+    import torch
+    from . import synth
+    ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
+    ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--eval", type=int, default=500)
+    ap.add_argument("--M", type=int, default=2048)
+    ap.add_argument("--N", type=int, default=256)
+    ap.add_argument("--K", type=int, default=16)
+    ap.add_argument("--epochs", type=int, default=8)
+    ap.add_argument("--batch", type=int, default=64, help="matrices per step")
+    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--save", default=None, help="write weights and Adam state (.npz)")
+    ap.add_argument("--out", default=None, help="write the summary JSON here too")
+    a = ap.parse_args(argv)
+    t0 = time.time()
+    M, N, K = a.M, a.N, a.K
+    Om = torch.from_numpy(synth.sketch_matrix(N, RANK)).cuda()
+    ntr, nev = a.train, a.eval
+    # instance numbers: training from 0, evaluation after a gap of 16000
+    train_h = generate(range(ntr), M, N, a.workers)
+    eval_h = generate(range(16000, 16000 + nev), M, N, a.workers)
+    print("generated %d + %d matrices in %.1fs" % (ntr, nev, time.time() - t0), flush=True)
+    Xtr, Ztr, Vtr = prepare(train_h, K, Om)
+    Xev, Zev, Vev = prepare(eval_h, K, Om)
+    del Xtr
+    print("targets and sketches ready at %.1fs" % (time.time() - t0), flush=True)
+    net = WarmStartNet(K=K, seed=0)
+    Zall = torch.cat(Ztr)
+    Vall = torch.stack(Vtr)
+    rng = np.random.default_rng([811, 14])
+    losses = []
+    ev_loss = []
+    Zev_all = torch.cat(Zev)
+    Vev_all = torch.stack(Vev)
+    for ep in range(a.epochs):
+        perm = rng.permutation(ntr)
+        el = []
+        for lo in range(0, ntr - a.batch + 1, a.batch):
+            idx = torch.from_numpy(perm[lo:lo + a.batch]).cuda()
+            zz = Zall.view(ntr, M, RANK)[idx].reshape(-1, RANK)
+            vv = Vall[idx].reshape(-1)
+            el.append(net.train_step(zz, vv, a.batch, M, lr=a.lr))
+        losses.append(float(torch.stack(el).mean().item()))
+        l = net.loss_grad(Zev_all, Vev_all.reshape(-1), nev, M)
+        ev_loss.append(float(l.item()))
+        print("epoch %d train loss %.4f eval loss %.4f (%.1fs)" % (ep, losses[-1], ev_loss[-1],
+                                                                 time.time() - t0), flush=True)
+    res = {"M": M, "N": N, "K": K, "train": ntr, "eval": nev, "epochs": a.epochs,
+           "train_loss": losses, "eval_loss": ev_loss, "tol": a.tol}
+    Vtrue_ev = [v for _, v, _ in eval_h]
+    res["sigma_stop"] = evaluate(net, Xev, Zev, Vtrue_ev, K, Om, tol=a.tol)
+    res["loading_stop"] = evaluate(net, Xev, Zev, Vtrue_ev, K, Om, tol=1e-4, stop="loading")
+    res["seconds"] = time.time() - t0
+    line = json.dumps(res)
+    print(line, flush=True)
+    if a.out:
+        with open(a.out, "w") as f:
+            f.write(line + "\n")
+    if a.save:
+        np.savez(a.save, **net.state())
+
+
+if __name__ == "__main__":
+    main()

@@ -169,3 +169,48 @@ def test_batched_autotune_and_cache(tmp_path):
         assert np.all(b2.status.cpu().numpy() == 0)
     finally:
         del os.environ["GSPCA_TUNE_CACHE"]
+
+
+def test_batched_given_start(orc):
+    """Warm-started batch: given vectors are used unless they fail the
+    fallback rule (non-finite, or less than a tenth outside the earlier
+    scores); results follow the oracle on the same start choice."""
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(8, seed=6, mmax=600, nmax=120)
+    rng = np.random.default_rng(66)
+    Xs, T0s, T0h = [], [], []
+    for X, K in probs:
+        ref = orc.fit(X, K, tol=1e-8, max_iter=2000, implicit=True, tiny=orc.FLT_MIN)
+        V = ref.V
+        M = X.shape[0]
+        G = V + 0.3 * rng.standard_normal(V.shape) / np.sqrt(M)
+        if K >= 3:
+            w = rng.standard_normal(M)
+            w -= V[:, :1] @ (V[:, :1].T @ w)
+            G[:, 1] = V[:, 0] + 0.05 * w / np.linalg.norm(w)  # inside span(v0): falls back
+            G[0, 2] = np.nan                                   # non-finite: falls back
+        G = np.asfortranarray(G.astype(np.float32))
+        T0h.append(G)
+        T0s.append(gp.column_major(torch.from_numpy(np.ascontiguousarray(G)).cuda()))
+        Xs.append(_gh().to_device(X))
+    b = gp.Batch(Xs, [k for _, k in probs], tol=1e-6, max_iter=1000, init="given", T0=T0s)
+    b.launch()
+    torch.cuda.synchronize()
+    assert np.all(b.status.cpu().numpy() == 0)
+    for i, (X, K) in enumerate(probs):
+        sc = b.start_col[i].cpu().numpy()
+        free = orc.fit(X, K, tol=1e-6, max_iter=1000, implicit=True, tiny=orc.FLT_MIN,
+                       init="given", T0=T0h[i].astype(np.float64))
+        assert np.array_equal(sc, free.start_col), (i, sc, free.start_col)
+        if K >= 3:
+            assert sc[0] == -1 and sc[1] >= 0 and sc[2] >= 0
+        its = b.iters[i].cpu().numpy()
+        o = orc.fit(X, K, tol=0.0, max_iter=max(1, int(its.max())), implicit=True,
+                    init="given", T0=T0h[i].astype(np.float64), replay_iters=its,
+                    replay_start=sc, tiny=orc.FLT_MIN)
+        ok = _gapped(o.sigma)
+        if ok.any():
+            assert col_angles(b.P[i].cpu().numpy(), o.P)[ok].max() <= 1e-5
+    with pytest.raises(ValueError):
+        gp.Batch(Xs, [k for _, k in probs], init="given")

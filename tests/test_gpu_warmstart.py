@@ -1,0 +1,246 @@
+"""GPU tests of the learned warm start (gspca_ws.h) against the FP64 oracle:
+sketch, whitening, the bf16 matrix-core network's forward pass, loss and
+gradients at matched bf16 rounding points, Adam, the composed prediction, and
+a small end-to-end check that trained start vectors save iterations.
+
+Tolerances: per-tensor relative Frobenius error <= 2e-3 for bf16 products
+with FP32 accumulation (a few bf16 units, 2^-8 each, on a minority of the
+stored operands); the FP32 sketch within N u sum_j |x_j omega_j| (u = 2^-24).
+"""
+import numpy as np
+import pytest
+
+from metrics import col_angles
+
+pytestmark = pytest.mark.gpu
+
+DIMS = (32, 256, 256, 16)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1081_amd as gp
+    gp.load()
+
+
+def _rel(a, b):
+    return np.linalg.norm(np.asarray(a, np.float64) - np.asarray(b, np.float64)) / max(
+        np.linalg.norm(np.asarray(b, np.float64)), 1e-300)
+
+
+def _dev(a):
+    import torch
+    return torch.from_numpy(np.ascontiguousarray(a, dtype=np.float32)).cuda()
+
+
+def _colmajor(a):
+    import torch
+    a = np.asarray(a, dtype=np.float32)
+    M, N = a.shape
+    t = torch.empty_strided((M, N), (1, M), dtype=torch.float32, device="cuda")
+    t.copy_(torch.from_numpy(np.ascontiguousarray(a)))
+    return t
+
+
+def _oracle_params(orc, net):
+    """Weights as the GPU uses them: bf16-rounded W, FP32 biases."""
+    theta = net.theta.cpu().numpy().astype(np.float64)
+    p = net.unpack(theta)
+    return [orc.bf16_round(x) if i % 2 == 0 else x for i, x in enumerate(p)]
+
+
+def test_sketch_matches_oracle(orc):
+    import torch
+    from paper_0811_1081_amd import synth, warmstart as ws
+    X = synth.warmstart_instance(1, M=1000, N=200)[0]
+    Om = synth.sketch_matrix(200, 32)
+    Y = ws.sketch(_colmajor(X), _dev(Om))
+    torch.cuda.synchronize()
+    Yo = orc.sketch_whiten(X, Om)[0]
+    # sequential FP32 accumulation over N terms: |error| <= N u sum_j |x_j omega_j|
+    bound = 200 * 2.0 ** -24 * (np.abs(X.astype(np.float64)) @ np.abs(Om.astype(np.float64)))
+    assert np.all(np.abs(Y.cpu().numpy() - Yo) <= bound + 1e-30)
+
+
+def test_whitening_matches_oracle(orc):
+    import torch
+    from paper_0811_1081_amd import synth, warmstart as ws
+    X = synth.warmstart_instance(2, M=2048, N=256)[0]
+    Om = synth.sketch_matrix(256, 32)
+    Y = ws.sketch(_colmajor(X), _dev(Om))
+    Z, g, flag = ws.whiten(Y)
+    torch.cuda.synchronize()
+    Yh = Y.cpu().numpy().astype(np.float64)
+    Zo, go = orc.whiten(Yh)  # the same sketch, whitened by the oracle
+    g = g.cpu().numpy()
+    assert int(flag.item()) == 0
+    assert np.abs(g - go).max() <= 1e-10 * go[0]
+    Zg = Z.cpu().numpy().astype(np.float64)
+    M = Zg.shape[0]
+    ok = go > 1e-12 * go[0]
+    gap = np.ones(32, dtype=bool)
+    gap[:-1] &= (go[:-1] - go[1:]) > 1e-3 * go[:-1]
+    gap[1:] &= (go[:-1] - go[1:]) > 1e-3 * go[:-1]
+    sel = ok & gap
+    assert sel.sum() >= 16
+    assert np.abs(Zg[:, sel] - Zo[:, sel]).max() <= 1e-4
+    assert np.abs(Zg[:, ok].T @ Zg[:, ok] / M - np.eye(int(ok.sum()))).max() <= 1e-4
+
+
+def test_forward_matches_oracle(orc):
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=1)
+    rng = np.random.default_rng(7)
+    rows = 3000  # 93.75 tiles of 32 rows: a ragged edge
+    Z = rng.standard_normal((rows, 32)).astype(np.float32)
+    # non-zero biases so that the bias path is exercised
+    p = net.unpack(net.theta.cpu().numpy())
+    for i in (1, 3, 5):
+        p[i][:] = 0.1 * rng.standard_normal(p[i].shape)
+    net.theta.copy_(torch.from_numpy(np.concatenate([x.ravel() for x in p]).astype(np.float32)))
+    net.sync()
+    O = net.forward(_dev(Z))
+    torch.cuda.synchronize()
+    params = _oracle_params(orc, net)
+    H1, H2, Oo = orc.mlp_forward(orc.bf16_round(Z), params, round_bf16=True)
+    assert _rel(O.cpu().numpy(), Oo) <= 2e-3
+    # the bf16 copy is exactly the rounded master
+    tb = (net.theta_bf16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(tb.astype(np.float64), orc.bf16_round(net.theta.cpu().numpy()))
+
+
+def _unit_scores(rng, ninst, Mi, K):
+    V = np.zeros((ninst, K, Mi))  # per matrix: column-major Mi x K
+    for b in range(ninst):
+        q = np.linalg.qr(rng.standard_normal((Mi, K)))[0]
+        V[b] = q.T
+    return V
+
+
+def test_loss_and_gradients_match_oracle(orc):
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=2)
+    rng = np.random.default_rng(8)
+    ninst, Mi, K = 3, 700, DIMS[3]
+    Z = rng.standard_normal((ninst * Mi, 32)).astype(np.float32)
+    V = _unit_scores(rng, ninst, Mi, K).astype(np.float32)
+    loss = net.loss_grad(_dev(Z), _dev(V.ravel()), ninst, Mi)
+    torch.cuda.synchronize()
+    g_gpu = net.unpack(net.grad.cpu().numpy())
+    params = _oracle_params(orc, net)
+    Zr = orc.bf16_round(Z)
+    H1, H2, O = orc.mlp_forward(Zr, params, round_bf16=True)
+    dO = np.zeros_like(O)
+    L = 0.0
+    for b in range(ninst):
+        r = slice(b * Mi, (b + 1) * Mi)
+        Lb, dOb = orc.cos2_loss(O[r], V[b].T.astype(np.float64))
+        L += Lb / ninst
+        dO[r] = dOb / ninst
+    g_orc = orc.mlp_backward(Zr, params, H1, H2, orc.bf16_round(dO), round_bf16=True)
+    assert abs(loss.item() - L) <= 1e-4 * L
+    names = ("W1", "b1", "W2", "b2", "W3", "b3")
+    for n, a, b in zip(names, g_gpu, g_orc):
+        assert _rel(a, b) <= 2e-3, n
+
+
+def test_adam_matches_oracle(orc):
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    net = ws.WarmStartNet(K=4, hidden=(32, 48), seed=3)
+    rng = np.random.default_rng(9)
+    w = net.theta.cpu().numpy().astype(np.float64)
+    m1 = np.zeros_like(w)
+    m2 = np.zeros_like(w)
+    for t in (1, 2, 3):
+        g = rng.standard_normal(w.size).astype(np.float32)
+        net.grad.copy_(torch.from_numpy(g))
+        net.adam(lr=1e-2)
+        orc.adam_step(w, g.astype(np.float64), m1, m2, 1e-2, t)
+    torch.cuda.synchronize()
+    assert net.step == 3
+    wg = net.theta.cpu().numpy()
+    assert np.abs(wg - w).max() <= 1e-6 * (np.abs(w).max() + 1e-2)
+    tb = (net.theta_bf16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
+    assert np.array_equal(tb.astype(np.float64), orc.bf16_round(wg))
+
+
+def test_predict_composes_sketch_whiten_forward(orc):
+    import torch
+    from paper_0811_1081_amd import synth, warmstart as ws
+    # a flat spectrum keeps every whitened direction well conditioned in FP32
+    M, N = 1500, 128
+    X = synth.haar_spectrum(M, N, np.linspace(1.0, 0.3, N), 0.0, seed=(15, 1), centre=False,
+                            dtype=np.float32)
+    Om = synth.sketch_matrix(N, 32)
+    net = ws.WarmStartNet(K=8, hidden=(64, 64), seed=4)
+    T0 = net.predict(_colmajor(X), _dev(Om))
+    torch.cuda.synchronize()
+    _, Zo, _ = orc.sketch_whiten(X, Om)
+    params = _oracle_params(orc, net)
+    _, _, Oo = orc.mlp_forward(orc.bf16_round(Zo), params, round_bf16=True)
+    assert T0.stride() == (1, M)
+    assert _rel(T0.cpu().numpy(), Oo) <= 5e-3
+
+
+def test_errors_are_reported_on_host():
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import warmstart as ws
+    X = torch.zeros((10, 5), dtype=torch.float32, device="cuda").t().contiguous().t()
+    with pytest.raises(ValueError):
+        ws.sketch(X, torch.zeros((4, 32), device="cuda"))
+    with pytest.raises(gp.GspcaError):
+        ws.whiten(torch.zeros((10, 32), device="cuda"))  # M < 32
+    net = ws.WarmStartNet(K=4, hidden=(32, 32), seed=0)
+    with pytest.raises(gp.GspcaError):
+        net.adam(lr=0.0)
+
+
+def test_trained_start_saves_iterations(orc):
+    """Train on small synthetic matrices with GS-PCA targets, then compare the
+    iterations of the GPU fit from the learned start with the max-norm
+    start on held-out matrices (same tol)."""
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth, warmstart as ws
+    M, N, K = 512, 128, 8
+    ntrain, neval = 48, 12
+    Om = _dev(synth.sketch_matrix(N, 32))
+    Xs, Zs = [], []
+    for i in range(ntrain + neval):
+        X = _colmajor(synth.warmstart_instance(i, M=M, N=N)[0])
+        Xs.append(X)
+        Zs.append(ws.whiten(ws.sketch(X, Om))[0])
+    b = gp.Batch(Xs[:ntrain], K, tol=1e-7, max_iter=3000)
+    b.launch()
+    torch.cuda.synchronize()
+    V = torch.stack([(b.T[i] / b.sigma[i].float()).t().contiguous() for i in range(ntrain)])
+    Zt = torch.cat(Zs[:ntrain])
+    net = ws.WarmStartNet(K=K, hidden=(256, 256), seed=5)
+    losses = []
+    per = 16
+    for step in range(300):
+        j = (step * per) % ntrain
+        zz = Zt[j * M:(j + per) * M]
+        vv = V[j:j + per].reshape(-1)
+        losses.append(net.train_step(zz, vv, per, M, lr=1e-3).item())
+    print("loss first %.3f last %.3f" % (np.mean(losses[:5]), np.mean(losses[-20:])))
+    assert np.mean(losses[-20:]) < 0.75 * np.mean(losses[:5])
+    it_warm, it_max = [], []
+    for i in range(ntrain, ntrain + neval):
+        T0 = net.predict(Xs[i], Om)
+        w = gp.fit(Xs[i], K, tol=1e-6, max_iter=3000, init="given", T0=T0)
+        m = gp.fit(Xs[i], K, tol=1e-6, max_iter=3000)
+        it_warm.append(int(w["iters"].sum().item()))
+        it_max.append(int(m["iters"].sum().item()))
+        ok = w["sigma"].cpu().numpy() > 0
+        assert col_angles(w["P"].cpu().numpy(), m["P"].cpu().numpy())[ok][:4].max() <= 1e-2
+    print("iterations per matrix: learned start %.1f, max-norm start %.1f"
+          % (np.mean(it_warm), np.mean(it_max)))
+    assert np.mean(it_warm) < 0.8 * np.mean(it_max), (it_warm, it_max)
