@@ -472,7 +472,7 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
 // 1024 threads (16 waves per compute unit).  PIPE = true prefetches the next
 // panel into a second register buffer; PIPE = false holds one panel and is
 // meant for two workgroups per compute unit.  `skew` != 0 interleaves the
-// panel assignment (see below; requires kd <= blockDim).
+// panel assignment (see below).
 template <class C, int CPT, bool FIRST, bool PL, bool PIPE>
 __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
@@ -499,8 +499,6 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const bool inter = skew != 0;
     const int64_t b0 = inter ? g : NP * g / G, b1 = inter ? NP : NP * (g + 1) / G;
     const int64_t cnt = inter ? (g < NP ? (NP - 1 - g) / G + 1 : 0) : b1 - b0;
-    double dacc = 0.0;
-
     E preg[PL ? 1 : CPT];
     E q[CPT];
     const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
@@ -586,16 +584,6 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
                 const int64_t m = b * PR + tid;
                 t_out[m] = (double)tb[tid];
             }
-            if (inter && tid < kd) {
-                // Gram-Schmidt coefficient d_tid over this panel's rows
-                const E *vc = V + (int64_t)tid * M;
-#pragma unroll
-                for (int r = 0; r < PR; ++r) {
-                    const int64_t m = b * PR + r;
-                    if (m < M)
-                        dacc += (double)vc[m] * (double)tb[r];
-                }
-            }
         }
 #pragma unroll
         for (int c = 0; c < CPT; ++c) {
@@ -662,24 +650,24 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     }
     if (FIRST || kd == 0)
         return;
-    if (inter) {
-        if (tid < kd)
-            d_part[g * kd + tid] = dacc;
-    } else {
-        // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows]:
-        // one wave per column of V, coalesced along the rows just written.
-        __threadfence();
-        __syncthreads();
-        const int64_t r0 = b0 * PR, r1 = min(b1 * PR, M);
-        for (int i = w; i < kd; i += nw) {
-            const E *vc = V + (int64_t)i * M;
-            double s = 0.0;
-            for (int64_t m = r0 + lane; m < r1; m += 64)
+    // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows],
+    // after the stream (a load inside the panel loop would make every wave wait
+    // for the prefetched panel too): one wave per column of V, lanes along the
+    // rows just written (runs of PR rows per panel).
+    __threadfence();
+    __syncthreads();
+    const int64_t nrows = cnt * PR;
+    for (int i = w; i < kd; i += nw) {
+        const E *vc = V + (int64_t)i * M;
+        double s = 0.0;
+        for (int64_t x = lane; x < nrows; x += 64) {
+            const int64_t m = pid(x / PR) * PR + x % PR;
+            if (m < M)
                 s += (double)vc[m] * t_out[m];
-            s = fwave_sum(s);
-            if (lane == 0)
-                d_part[g * kd + i] = s;
         }
+        s = fwave_sum(s);
+        if (lane == 0)
+            d_part[g * kd + i] = s;
     }
     if (!fused_arrive_last(&st->counter[kCntDotM], &last))
         return;

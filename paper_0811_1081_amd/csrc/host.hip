@@ -358,8 +358,6 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
         f.cpt /= 2;
         f.NT *= 2;
     }
-    if (K > f.NT) // the interleaved order keeps one coefficient per thread
-        f.skew = 0;
     const int64_t per_cu = std::max<int64_t>(1, (f.plds ? 1024 : 512) / f.NT) * (f.pipe ? 1 : 2);
     f.G = (int)std::max<int64_t>(1, std::min<int64_t>(ncu * per_cu, std::max<int64_t>(1, f.NP / 2)));
     f.nsplit_cn = (int)std::max<int64_t>(1, std::min<int64_t>(cdiv(2048, cdiv(N, 64)), f.NP));
