@@ -9,6 +9,9 @@
  *   Y = X Omega                          M x r, r = 32, Omega N x r given
  *   Y^T Y = Q diag(g) Q^T                 FP64 Jacobi, g decreasing
  *   Z = sqrt(M) Y Q diag(g)^(-1/2)        whitened rows (unit-variance columns)
+ *   [refinement, `power` times: Y = X (X^T Z / sqrt(M)), whiten again -- one
+ *    step of subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4),
+ *    which turns the sketch's directions into Ritz vectors of X X^T]
  *   o_m = W3^T relu(W2^T relu(W1^T z_m + b1) + b2) + b3   for every row m
  *   T0[:, k] = (o_0k, ..., o_(M-1)k)      start of component k (sign free)
  *
@@ -62,13 +65,21 @@ typedef struct {
 int64_t gspca_mlp_param_count(int32_t d0, int32_t d1, int32_t d2, int32_t d3);
 
 /* Workspace of gspca_mlp_forward / gspca_mlp_loss_grad over `rows` rows in
- * `ninst` matrices, and of gspca_ws_predict for an M-row matrix (ninst = 1). */
-size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst);
+ * `ninst` matrices (cols = 0), and of gspca_ws_predict for an M x N matrix
+ * (rows = M, ninst = 1, cols = N). */
+size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst,
+                                 int64_t cols);
 
 /* Y = X Omega.  X FP32 column-major M x N (ldx >= M), Omega FP32 row-major
  * N x r (Omega[j*r + c]), Y FP32 row-major M x r.  r must be 32. */
 gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Omega,
                           int32_t r, float *Y, void *stream);
+
+/* Refinement step: W = X^T Z / sqrt(M) (N x r, row-major, FP32 accumulation)
+ * and Y = X W (M x r, row-major) for a whitened sketch Z (row-major M x r,
+ * r = 32).  Whiten Y again to finish the step. */
+gspca_status gspca_sketch_refine(const float *X, int64_t ldx, int64_t M, int64_t N,
+                                 const float *Z, int32_t r, float *W, float *Y, void *stream);
 
 /* Z = sqrt(M) Y Q diag(g)^(-1/2) with the eigenpairs of Y^T Y (FP64, cyclic
  * Jacobi) ordered by decreasing g, each eigenvector's largest entry made
@@ -101,12 +112,13 @@ gspca_status gspca_mlp_loss_grad(const gspca_mlp *net, const float *Z, const flo
 gspca_status gspca_mlp_adam(gspca_mlp *net, float lr, float beta1, float beta2, float eps,
                             void *stream);
 
-/* Start vectors for one matrix: sketch, whiten, forward.  X FP32 column-major
- * M x N, Omega as in gspca_sketch, T0 FP32 column-major M x d3 (ready for
- * gspca_options.T0 with init = GSPCA_INIT_GIVEN). */
+/* Start vectors for one matrix: sketch, whiten, `power` refinement steps
+ * (0..4), forward.  X FP32 column-major M x N, Omega as in gspca_sketch, T0
+ * FP32 column-major M x d3 (ready for gspca_options.T0 with
+ * init = GSPCA_INIT_GIVEN). */
 gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx, int64_t M,
-                              int64_t N, const float *Omega, float *T0, void *ws, size_t ws_bytes,
-                              void *stream);
+                              int64_t N, const float *Omega, int32_t power, float *T0, void *ws,
+                              size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

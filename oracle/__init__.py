@@ -65,6 +65,8 @@ def lib() -> ctypes.CDLL:
             L.oracle_bf16_encode.argtypes = [ctypes.c_float]
             L.oracle_bf16_decode.restype = ctypes.c_float
             L.oracle_bf16_decode.argtypes = [ctypes.c_uint16]
+            L.oracle_bf16_round.restype = None
+            L.oracle_bf16_round.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]
             L.oracle_e4m3_encode.restype = ctypes.c_uint8
             L.oracle_e4m3_encode.argtypes = [ctypes.c_float]
             L.oracle_e4m3_decode.restype = ctypes.c_double
@@ -170,15 +172,30 @@ def jacobi_eig(A):
     return w, Q
 
 
-def sketch_whiten(X, Omega):
+def sketch_whiten(X, Omega, power=0):
     """Warm-start input rows (not in the paper): Y = X Omega, then the
     eigen-decomposition Y^T Y = Q diag(g) Q^T by cyclic Jacobi (g decreasing,
     each eigenvector's largest-magnitude entry made positive) and
-    Z = sqrt(M) Y Q diag(g)^(-1/2); columns with g <= 0 are zero.  FP64.
-    Returns (Y, Z, g)."""
+    Z = sqrt(M) Y Q diag(g)^(-1/2); columns with g <= 0 are zero.  Each of the
+    `power` refinement steps (one step of subspace iteration, Halko, Martinsson
+    & Tropp 2011, Alg. 4.4) replaces Y by X (X^T Z / sqrt(M)) and whitens
+    again.  FP64.  Returns (Y, Z, g) of the last step."""
     X = np.asarray(X, dtype=np.float64)
     Y = X @ np.asarray(Omega, dtype=np.float64)
-    return (Y,) + whiten(Y)
+    Z, g = whiten(Y)
+    for _ in range(int(power)):
+        Y = sketch_refine(X, Z)[1]
+        Z, g = whiten(Y)
+    return Y, Z, g
+
+
+def sketch_refine(X, Z):
+    """One refinement step on a whitened sketch Z (M x r): W = X^T Z / sqrt(M)
+    (N x r) and Y = X W.  FP64.  Returns (W, Y)."""
+    X = np.asarray(X, dtype=np.float64)
+    Z = np.asarray(Z, dtype=np.float64)
+    W = X.T @ Z / np.sqrt(X.shape[0])
+    return W, X @ W
 
 
 def whiten(Y):
@@ -193,6 +210,14 @@ def whiten(Y):
             Q[:, c] = -Q[:, c]
     scale = np.where(g > 0, np.sqrt(M) / np.sqrt(np.where(g > 0, g, 1.0)), 0.0)
     return (Y @ Q) * scale, g
+
+
+def bf16_round(a):
+    """Element-wise value of a stored as FP32 then bfloat16 (float64 array)."""
+    a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+    out = np.empty_like(a)
+    lib().oracle_bf16_round(_ptr(a), _ptr(out), a.size)
+    return out
 
 
 def bf16_encode(x: float) -> int:

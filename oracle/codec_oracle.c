@@ -121,3 +121,11 @@ int oracle_dequantize(const void *codes, const float *scale, int64_t M, int64_t 
         }
     return 0;
 }
+
+/* out[i] = bf16(fl32(in[i])) as a double: the value an FP64 number takes when
+ * it is stored as FP32 and then as bfloat16 (both round to nearest even). */
+void oracle_bf16_round(const double *in, double *out, int64_t n)
+{
+    for (int64_t i = 0; i < n; ++i)
+        out[i] = (double)oracle_bf16_decode(oracle_bf16_encode((float)in[i]));
+}

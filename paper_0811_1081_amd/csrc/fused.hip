@@ -463,9 +463,10 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
 
 // ---------------------------------------------------------------------------
 // The fused pass.  FIRST: q = A^T t_in only (the start of a component).
-// Otherwise: t = A (p / |p|) (written to t_out in FP64), q = A^T t, and the
-// Gram-Schmidt coefficients d = V_(k)^T t (FP64, finished by the last
-// workgroup).  q is left as per-workgroup partials q_part[g][j].
+// Otherwise: t = A (p / |p|) (written to t_out in FP64) and q = A^T t.  q is
+// left as per-workgroup partials q_part[g][j].  The pass only streams A: the
+// Gram-Schmidt coefficients d = V_(k)^T t are formed by a separate coalesced
+// reduction over the rows of t_out.
 
 // Variants: PL = false keeps the loading in registers (at most 512 threads,
 // 8 waves per compute unit); PL = true keeps it in LDS, freeing registers for
@@ -478,8 +479,7 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
     const float *__restrict__ scale, const double *__restrict__ p,
     const typename C::acc *__restrict__ t_in, double *__restrict__ t_out,
-    const typename C::acc *__restrict__ V, int kd, typename C::acc *__restrict__ q_part,
-    double *__restrict__ d_part, double *__restrict__ d, LoopState *st, int skew)
+    typename C::acc *__restrict__ q_part, LoopState *st, int skew)
 {
     if (st->done)
         return;
@@ -487,7 +487,6 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     using RT = typename C::raw;
     constexpr int PR = C::PR;
     __shared__ E red[2][16][PR];
-    __shared__ int last;
     extern __shared__ unsigned char pass_smem[];
     E *pl = reinterpret_cast<E *>(pass_smem);
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -648,37 +647,6 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
             q_part[g * N + j] = v;
         }
     }
-    if (FIRST || kd == 0)
-        return;
-    // Gram-Schmidt coefficients of this workgroup's rows, d_g = V[rows,:]^T t[rows],
-    // after the stream (a load inside the panel loop would make every wave wait
-    // for the prefetched panel too): one wave per column of V, lanes along the
-    // rows just written (runs of PR rows per panel).
-    __threadfence();
-    __syncthreads();
-    const int64_t nrows = cnt * PR;
-    for (int i = w; i < kd; i += nw) {
-        const E *vc = V + (int64_t)i * M;
-        double s = 0.0;
-        for (int64_t x = lane; x < nrows; x += 64) {
-            const int64_t m = pid(x / PR) * PR + x % PR;
-            if (m < M)
-                s += (double)vc[m] * t_out[m];
-        }
-        s = fwave_sum(s);
-        if (lane == 0)
-            d_part[g * kd + i] = s;
-    }
-    if (!fused_arrive_last(&st->counter[kCntDotM], &last))
-        return;
-    for (int i = tid; i < kd; i += NT) {
-        double s = 0.0;
-        for (int64_t gg = 0; gg < G; ++gg)
-            s += d_part[gg * kd + i];
-        d[i] = s;
-    }
-    if (tid == 0)
-        st->counter[kCntDotM] = 0;
 }
 
 // q = sum_g q_part[g] (FP64, fixed order), q' = q - W d (the Gram-Schmidt
@@ -865,14 +833,13 @@ template <class C, bool FIRST>
 static void launch_pass(int cpt, int G, int NT, int plds, int skew, int pipe,
                         const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                         const float *scale, const double *p, const typename C::acc *t_in,
-                        double *t_out, const typename C::acc *V, int kd,
-                        typename C::acc *q_part, double *d_part, double *d, LoopState *st,
+                        double *t_out, typename C::acc *q_part, LoopState *st,
                         hipStream_t s)
 {
     const size_t lds = plds ? (size_t)cpt * NT * sizeof(typename C::acc) : 0;
 #define GSPCA_PASS(CP, PLV, PIV)                                                               \
     hipLaunchKernelGGL((k_pass<C, CP, FIRST, PLV, PIV>), dim3(G), dim3(NT), lds, s, A, N, NP,  \
-                       ldp, M, scale, p, t_in, t_out, V, kd, q_part, d_part, d, st, skew)
+                       ldp, M, scale, p, t_in, t_out, q_part, st, skew)
 #define GSPCA_PASS_CPT(PLV, PIV)                                                               \
     switch (cpt) {                                                                             \
     case 1: GSPCA_PASS(1, PLV, PIV); break;                                                    \
@@ -894,16 +861,16 @@ template <int F>
 void Fused<F>::pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                     const unsigned char *A,
                     int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
-                    const double *p, const E *t_in, double *t_out, const E *V, int kd, E *q_part,
-                    double *d_part, double *d, LoopState *st, hipStream_t s)
+                    const double *p, const E *t_in, double *t_out, E *q_part, LoopState *st,
+                    hipStream_t s)
 {
     using C = typename CodecOf<F>::type;
     if (first)
         launch_pass<C, true>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                             t_out, V, 0, q_part, d_part, d, st, s);
+                             t_out, q_part, st, s);
     else
         launch_pass<C, false>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                              t_out, V, kd, q_part, d_part, d, st, s);
+                              t_out, q_part, st, s);
 }
 
 template <int F>

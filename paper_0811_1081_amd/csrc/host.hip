@@ -300,7 +300,7 @@ struct FusedPlan {
     int cpt, NT, G, nsplit_cn, nbM, nbN;
     int plds, skew, pipe; // pass-kernel variant: loading in LDS (1024 threads), panel-order
                           // skew, register double buffering (else two workgroups per CU)
-    size_t off_state, off_A, off_tE, off_td, off_qpart, off_dpart, off_d, off_c, off_qy, off_p,
+    size_t off_state, off_A, off_tE, off_td, off_qpart, off_d, off_c, off_qy, off_p,
         off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
 };
 
@@ -372,7 +372,6 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     f.off_tE = o;     o = align_up(o + len * esize);
     f.off_td = o;     o = align_up(o + len * 8);
     f.off_qpart = o;  o = align_up(o + (size_t)f.G * N * esize);
-    f.off_dpart = o;  o = align_up(o + (size_t)f.G * (K + 1) * 8);
     f.off_d = o;      o = align_up(o + (size_t)(K + 1) * 8);
     f.off_c = o;      o = align_up(o + (size_t)(K + 1) * 8);
     f.off_qy = o;     o = align_up(o + (size_t)N * 8);
@@ -418,7 +417,6 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     E *tE = reinterpret_cast<E *>(base + f.off_tE);
     double *td = reinterpret_cast<double *>(base + f.off_td);
     E *qpart = reinterpret_cast<E *>(base + f.off_qpart);
-    double *dpart = reinterpret_cast<double *>(base + f.off_dpart);
     double *dvec = reinterpret_cast<double *>(base + f.off_d);
     double *cvec = reinterpret_cast<double *>(base + f.off_c);
     double *qy = reinterpret_cast<double *>(base + f.off_qy);
@@ -496,8 +494,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                     op->replay_start_col};
         F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-        F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE, td, T, 0,
-                qpart, dpart, dvec, st, s);
+        F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE,
+                td, qpart, st, s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
         L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol, limit,
                     replay, tiny, stop, s);
@@ -511,10 +509,14 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 const int it = enq + i + 1;
                 if (prof)
                     (void)hipEventRecord(ev[2 * i], s);
-                F::pass(0, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE, td,
-                        T, kg, qpart, dpart, dvec, st, s);
+                F::pass(0, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p,
+                        tE, td, qpart, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
+                // Gram-Schmidt coefficients of the score, d = V_(k)^T t (coalesced
+                // over the rows, kept out of the streaming pass)
+                if (kg > 0)
+                    L::gs_dot(td, 1, len, M, T, M, kg, nullptr, cpart, dvec, st, kCntDotM, s);
                 L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, nullptr, tE, sq, st, 1, tol,
                             limit, replay, tiny, stop, s);
                 F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);

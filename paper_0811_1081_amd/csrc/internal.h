@@ -103,8 +103,8 @@ struct Fused {
     static void pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                      const unsigned char *A,
                      int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
-                     const double *p, const E *t_in, double *t_out, const E *V, int kd,
-                     E *q_part, double *d_part, double *d, LoopState *st, hipStream_t s);
+                     const double *p, const E *t_in, double *t_out, E *q_part, LoopState *st,
+                     hipStream_t s);
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);

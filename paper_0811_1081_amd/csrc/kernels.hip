@@ -367,7 +367,8 @@ __global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ pa
     if (r < L) {
         for (int s = 0; s < nsplit; ++s)
             v += part[(int64_t)s * ldpart + r];
-        y[r] = v;
+        if (y)
+            y[r] = v;
     }
     ys[threadIdx.x] = v;
     __syncthreads();

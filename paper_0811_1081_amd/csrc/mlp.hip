@@ -254,6 +254,48 @@ __global__ __launch_bounds__(256) void k_sketch(const float *__restrict__ X, int
         Y[m * R + c] = acc[c];
 }
 
+// W = s X^T Z (N x R, row-major) for a row-major M x R sketch Z: one wave per
+// column of X, lanes along the rows (coalesced), R accumulators per lane,
+// then a butterfly sum per accumulator.
+template <int R>
+__global__ __launch_bounds__(256) void k_sketch_t(const float *__restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t N,
+                                                  const float *__restrict__ Z, float s,
+                                                  float *__restrict__ W)
+{
+    typedef float f4 __attribute__((ext_vector_type(4)));
+    const int lane = threadIdx.x & 63;
+    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
+    if (j >= N)
+        return;
+    float acc[R];
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+        acc[c] = 0.0f;
+    const float *xc = X + j * ldx;
+    for (int64_t m = lane; m < M; m += 64) {
+        const float x = xc[m];
+        const f4 *zr = reinterpret_cast<const f4 *>(Z + m * R);
+#pragma unroll
+        for (int c4 = 0; c4 < R / 4; ++c4) {
+            const f4 z = zr[c4];
+            acc[4 * c4 + 0] += x * z[0];
+            acc[4 * c4 + 1] += x * z[1];
+            acc[4 * c4 + 2] += x * z[2];
+            acc[4 * c4 + 3] += x * z[3];
+        }
+    }
+#pragma unroll
+    for (int c = 0; c < R; ++c) {
+        float v = acc[c];
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1)
+            v += __shfl_xor(v, o, 64);
+        if (lane == c)
+            W[j * R + c] = v * s;
+    }
+}
+
 // G = Y^T Y in FP64 (thread per entry), parallel cyclic Jacobi (round-robin
 // pairing: R/2 disjoint rotations per round, R-1 rounds per sweep; rotation
 // of Golub & Van Loan's symmetric Schur step) until the off-diagonal mass is
@@ -420,9 +462,9 @@ bool valid_net(const gspca_mlp *n)
 constexpr int kMaxSplit = 64;
 
 struct Layout {
-    size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, total;
+    size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, W, total;
 };
-Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst)
+Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst, int64_t cols)
 {
     Layout L{};
     size_t o = 0;
@@ -442,6 +484,7 @@ Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst)
     put(L.part, (size_t)kMaxSplit * dmax * dmax * 4);
     put(L.Y, (size_t)rows * GSPCA_WS_RANK * 4);
     put(L.Z, (size_t)rows * GSPCA_WS_RANK * 4);
+    put(L.W, (size_t)std::max<int64_t>(cols, 1) * GSPCA_WS_RANK * 4);
     L.total = o;
     return L;
 }
@@ -517,11 +560,12 @@ int64_t gspca_mlp_param_count(int32_t d0, int32_t d1, int32_t d2, int32_t d3)
     return param_offsets(d0, d1, d2, d3).n;
 }
 
-size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst)
+size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst,
+                                 int64_t cols)
 {
-    if (!net || rows < 1 || ninst < 1)
+    if (!net || rows < 1 || ninst < 1 || cols < 0)
         return 0;
-    return layout(net, rows, ninst).total;
+    return layout(net, rows, ninst, cols).total;
 }
 
 gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Omega,
@@ -532,6 +576,19 @@ gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, con
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
                        N, Omega, Y);
+    return launched();
+}
+
+gspca_status gspca_sketch_refine(const float *X, int64_t ldx, int64_t M, int64_t N,
+                                 const float *Z, int32_t r, float *W, float *Y, void *stream)
+{
+    if (!X || !Z || !W || !Y || r != GSPCA_WS_RANK || M < 1 || N < 1 || ldx < M)
+        return GSPCA_EINVAL;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipLaunchKernelGGL(k_sketch_t<GSPCA_WS_RANK>, dim3(ucdiv(N, 4)), dim3(256), 0, s, X, ldx, M, N,
+                       Z, (float)(1.0 / sqrt((double)M)), W);
+    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
+                       N, W, Y);
     return launched();
 }
 
@@ -562,7 +619,7 @@ gspca_status gspca_mlp_forward(const gspca_mlp *net, const float *Z, int64_t row
 {
     if (!valid_net(net) || !Z || !O || rows < 1 || !ws)
         return GSPCA_EINVAL;
-    const Layout L = layout(net, rows, 1);
+    const Layout L = layout(net, rows, 1, 0);
     if (ws_bytes < L.total)
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -579,7 +636,7 @@ gspca_status gspca_mlp_loss_grad(const gspca_mlp *net, const float *Z, const flo
     if (!valid_net(net) || !net->grad || !Z || !V || ninst < 1 || rows_per_inst < 1 || !ws)
         return GSPCA_EINVAL;
     const int64_t rows = (int64_t)ninst * rows_per_inst;
-    const Layout L = layout(net, rows, ninst);
+    const Layout L = layout(net, rows, ninst, 0);
     if (ws_bytes < L.total)
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
@@ -641,22 +698,32 @@ gspca_status gspca_mlp_adam(gspca_mlp *net, float lr, float beta1, float beta2, 
 }
 
 gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx, int64_t M,
-                              int64_t N, const float *Omega, float *T0, void *ws, size_t ws_bytes,
-                              void *stream)
+                              int64_t N, const float *Omega, int32_t power, float *T0, void *ws,
+                              size_t ws_bytes, void *stream)
 {
-    if (!valid_net(net) || !X || !Omega || !T0 || M < GSPCA_WS_RANK || N < 1 || ldx < M || !ws)
+    if (!valid_net(net) || !X || !Omega || !T0 || M < GSPCA_WS_RANK || N < 1 || ldx < M || !ws ||
+        power < 0 || power > 4)
         return GSPCA_EINVAL;
-    const Layout L = layout(net, M, 1);
+    const Layout L = layout(net, M, 1, N);
     if (ws_bytes < L.total)
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char *b = static_cast<unsigned char *>(ws);
     float *Y = reinterpret_cast<float *>(b + L.Y);
     float *Z = reinterpret_cast<float *>(b + L.Z);
+    float *W = reinterpret_cast<float *>(b + L.W);
     hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
                        N, Omega, Y);
     hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1), dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0,
                        s, Y, M, Z, nullptr, nullptr);
+    for (int it = 0; it < power; ++it) {
+        hipLaunchKernelGGL(k_sketch_t<GSPCA_WS_RANK>, dim3(ucdiv(N, 4)), dim3(256), 0, s, X, ldx,
+                           M, N, Z, (float)(1.0 / sqrt((double)M)), W);
+        hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx,
+                           M, N, W, Y);
+        hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1),
+                           dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0, s, Y, M, Z, nullptr, nullptr);
+    }
     forward(net, Z, M, reinterpret_cast<__bf16 *>(b + L.H1), reinterpret_cast<__bf16 *>(b + L.H2),
             T0, 1, M, s);
     return launched();

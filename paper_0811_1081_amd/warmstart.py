@@ -58,6 +58,31 @@ def sketch(X, Omega, stream=None):
     return Y
 
 
+def sketch_refine(X, Z, stream=None):
+    """One refinement step: (W, Y) with W = X^T Z / sqrt(M) (N x 32) and
+    Y = X W (M x 32); whiten Y to finish it."""
+    import torch
+    M, N = X.shape
+    if X.dtype != torch.float32 or X.stride(0) != 1:
+        raise ValueError("X must be column-major float32")
+    Z = Z.contiguous()
+    if tuple(Z.shape) != (M, RANK) or Z.dtype != torch.float32:
+        raise ValueError("Z must be (M, %d) float32" % RANK)
+    W = torch.empty((N, RANK), dtype=torch.float32, device=X.device)
+    Y = torch.empty((M, RANK), dtype=torch.float32, device=X.device)
+    _check(_b.load().gspca_sketch_refine(X.data_ptr(), X.stride(1), M, N, Z.data_ptr(), RANK,
+                                         W.data_ptr(), Y.data_ptr(), _stream(stream, X.device)))
+    return W, Y
+
+
+def features(X, Omega, power=1, stream=None):
+    """Whitened sketch after `power` refinement steps (the network's input)."""
+    Z = whiten(sketch(X, Omega, stream), stream)[0]
+    for _ in range(int(power)):
+        Z = whiten(sketch_refine(X, Z, stream)[1], stream)[0]
+    return Z
+
+
 def whiten(Y, stream=None):
     """(Z, gamma, flag): Z = sqrt(M) Y Q diag(g)^(-1/2) (row-major M x 32)."""
     import torch
@@ -118,9 +143,9 @@ class WarmStartNet:
     def step(self):
         return int(self.net.step)
 
-    def _workspace(self, rows, ninst):
+    def _workspace(self, rows, ninst, cols=0):
         need = int(_b.load().gspca_mlp_workspace_bytes(ctypes.byref(self.net), int(rows),
-                                                        int(ninst)))
+                                                        int(ninst), int(cols)))
         if need > self._ws_bytes:
             self._ws, self._ws_ptr = _aligned(need, self.device)
             self._ws_bytes = need
@@ -163,8 +188,9 @@ class WarmStartNet:
         self.adam(lr, stream=stream)
         return loss
 
-    def predict(self, X, Omega, stream=None):
-        """Start vectors T0 (M x K, column-major float32) for column-major float32 X."""
+    def predict(self, X, Omega, power=1, stream=None):
+        """Start vectors T0 (M x K, column-major float32) for column-major float32 X
+        (sketch, `power` refinement steps, network)."""
         import torch
         M, N = X.shape
         if X.dtype != torch.float32 or X.stride(0) != 1:
@@ -172,9 +198,9 @@ class WarmStartNet:
         Om = Omega.contiguous()
         T0 = torch.empty_strided((M, self.dims[3]), (1, M), dtype=torch.float32,
                                  device=self.device)
-        p, nb = self._workspace(M, 1)
+        p, nb = self._workspace(M, 1, N)
         _check(_b.load().gspca_ws_predict(ctypes.byref(self.net), X.data_ptr(), X.stride(1), M, N,
-                                          Om.data_ptr(), T0.data_ptr(), p, nb,
+                                          Om.data_ptr(), int(power), T0.data_ptr(), p, nb,
                                           _stream(stream, self.device)))
         return T0
 
@@ -206,17 +232,36 @@ def _instance(args):
     return X, V[:, :64].astype(np.float32), ratio
 
 
-def generate(indices, M, N, workers=8):
-    """Host matrices for the given instance numbers (a spawn pool; no GPU)."""
+def generate(indices, M, N, workers=8, log=None):
+    """Host matrices for the given instance numbers.  The worker pool starts
+    new interpreters, so call this before the process touches the GPU."""
     import multiprocessing as mp
     args = [(int(i), M, N) for i in indices]
     if workers <= 1 or len(args) < 4:
         return [_instance(a) for a in args]
-    with mp.get_context("spawn").Pool(workers) as pool:
-        return pool.map(_instance, args, chunksize=8)
+    out = []
+    # one BLAS thread per worker (the workers read these at start-up)
+    import os
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            for r in pool.imap(_instance, args, chunksize=8):
+                out.append(r)
+                if log and len(out) % 256 == 0:
+                    log("generated %d / %d" % (len(out), len(args)))
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+    return out
 
 
-def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512):
+def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512, power=1):
     """Device data for training: X (column-major), whitened sketch Z, and the
     unit scores V of GS-PCA fits (column-major per matrix, K columns)."""
     import torch
@@ -228,7 +273,7 @@ def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512):
         b = Batch(part, K, tol=tol, max_iter=max_iter)
         b.launch()
         for i, X in enumerate(part):
-            Zs.append(whiten(sketch(X, Omega))[0])
+            Zs.append(features(X, Omega, power))
             Vs.append((b.T[i] / b.sigma[i].clamp_min(1e-30).float()).t().contiguous())
         Xs += part
     torch.cuda.synchronize()
@@ -298,19 +343,25 @@ def main(argv=None):
     ap.add_argument("--lr", type=float, default=1e-3)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--workers", type=int, default=8)
+    ap.add_argument("--power", type=int, default=1, help="sketch refinement steps")
     ap.add_argument("--save", default=None, help="write weights and Adam state (.npz)")
     ap.add_argument("--out", default=None, help="write the summary JSON here too")
     a = ap.parse_args(argv)
     t0 = time.time()
     M, N, K = a.M, a.N, a.K
-    Om = torch.from_numpy(synth.sketch_matrix(N, RANK)).cuda()
     ntr, nev = a.train, a.eval
-    # instance numbers: training from 0, evaluation after a gap of 16000
-    train_h = generate(range(ntr), M, N, a.workers)
-    eval_h = generate(range(16000, 16000 + nev), M, N, a.workers)
-    print("generated %d + %d matrices in %.1fs" % (ntr, nev, time.time() - t0), flush=True)
-    Xtr, Ztr, Vtr = prepare(train_h, K, Om)
-    Xev, Zev, Vev = prepare(eval_h, K, Om)
+
+    def log(msg):
+        print("%s (%.1fs)" % (msg, time.time() - t0), flush=True)
+
+    # host data first: the generator pool must start before the GPU is in use.
+    # Instance numbers: training from 0, evaluation from 16000.
+    train_h = generate(range(ntr), M, N, a.workers, log)
+    eval_h = generate(range(16000, 16000 + nev), M, N, a.workers, log)
+    log("generated %d + %d matrices" % (ntr, nev))
+    Om = torch.from_numpy(synth.sketch_matrix(N, RANK)).cuda()
+    Xtr, Ztr, Vtr = prepare(train_h, K, Om, power=a.power)
+    Xev, Zev, Vev = prepare(eval_h, K, Om, power=a.power)
     del Xtr
     print("targets and sketches ready at %.1fs" % (time.time() - t0), flush=True)
     net = WarmStartNet(K=K, seed=0)
@@ -334,7 +385,7 @@ def main(argv=None):
         ev_loss.append(float(l.item()))
         print("epoch %d train loss %.4f eval loss %.4f (%.1fs)" % (ep, losses[-1], ev_loss[-1],
                                                                  time.time() - t0), flush=True)
-    res = {"M": M, "N": N, "K": K, "train": ntr, "eval": nev, "epochs": a.epochs,
+    res = {"M": M, "N": N, "K": K, "train": ntr, "eval": nev, "epochs": a.epochs, "power": a.power,
            "train_loss": losses, "eval_loss": ev_loss, "tol": a.tol}
     Vtrue_ev = [v for _, v, _ in eval_h]
     res["sigma_stop"] = evaluate(net, Xev, Zev, Vtrue_ev, K, Om, tol=a.tol)

@@ -101,3 +101,27 @@ def test_backward_rounding_points(orc):
     # rounding moves each gradient by at most a few bf16 units
     for a, b in zip(g0, g1):
         assert np.linalg.norm(a - b) <= 2e-2 * np.linalg.norm(a)
+
+
+def test_refined_sketch_recovers_singular_vectors(orc):
+    """One subspace-iteration step on the whitened sketch: for an exactly
+    rank-r matrix X with r <= 32 the sketch spans range(X) and the refined,
+    whitened directions are X's left singular vectors (a Ritz step), whatever
+    the spectral gaps; the plain sketch's directions are not."""
+    rng = np.random.default_rng(4)
+    M, N, r = 400, 90, 20
+    U = np.linalg.qr(rng.standard_normal((M, r)))[0]
+    V = np.linalg.qr(rng.standard_normal((N, r)))[0]
+    s = 0.97 ** np.arange(r)  # small gaps
+    X = (U * s) @ V.T
+    Om = rng.standard_normal((N, 32))
+    _, Z0, _ = orc.sketch_whiten(X, Om)
+    _, Z1, g1 = orc.sketch_whiten(X, Om, power=1)
+    ang1 = col_angles(Z1[:, :r] / np.sqrt(M), U)
+    ang0 = col_angles(Z0[:, :r] / np.sqrt(M), U)
+    assert ang1.max() <= 1e-6
+    assert ang0.max() >= 0.1
+    # the refined eigenvalues are (sigma^4 / M-scaled) Ritz values of X X^T on the sketch
+    W, Y = orc.sketch_refine(X, Z0)
+    assert np.allclose(Y, X @ (X.T @ Z0) / np.sqrt(M), rtol=0, atol=1e-12)
+    assert np.allclose(np.sort(g1[:r])[::-1] / g1[0], s ** 4 / s[0] ** 4, rtol=1e-8)
