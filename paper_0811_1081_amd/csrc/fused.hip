@@ -107,20 +107,6 @@ __device__ inline T fwave_sum(T v)
     return v;
 }
 
-__device__ inline bool fused_arrive_last(uint32_t *counter, int *flag_lds)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(counter, 1u);
-        *flag_lds = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last)
-        __threadfence();
-    return last;
-}
 
 // Element (m, j) of the panel matrix in the arithmetic type (scaled for codes).
 template <class C>
@@ -654,24 +640,22 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
 // Gram-Schmidt coefficients c = P_(k)^T q' (Sec. 2.3), finished by the last
 // workgroup.  `it` is the iteration this launch belongs to: when the
 // component stopped in that iteration only q' is formed (it feeds W); when
-// it stopped earlier the launch does nothing.  Workgroup: 64 columns x 4
-// groups of partials (the partial sums are read with 16 loads in flight per
-// thread and combined in a fixed order).
+// it stopped earlier the launch does nothing.  Workgroup: 64 columns x
+// kFinGroups groups of partials (4 loads in flight per thread; the group sums
+// are combined in a fixed order).
 template <typename E>
-__global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int64_t G, int64_t N,
-                                               const double *__restrict__ W, int kd,
-                                               const double *__restrict__ d,
-                                               const E *__restrict__ P, int kg,
-                                               double *__restrict__ qy,
-                                               double *__restrict__ cpart,
-                                               double *__restrict__ c, LoopState *st, int it)
+__global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
+    const E *__restrict__ q_part, int64_t G, int64_t N, const double *__restrict__ W, int kd,
+    const double *__restrict__ d, const E *__restrict__ P, int kg, double *__restrict__ qy,
+    double *__restrict__ cpart, double *__restrict__ c, LoopState *st, int it)
 {
     if (st->degenerate)
         return;
     const int done = st->done;
     if (done && st->iter != it)
         return;
-    __shared__ double part4[4][64];
+    constexpr int NG = kFinGroups;
+    __shared__ double part[NG][64];
     __shared__ double ys[64];
     __shared__ int last;
     const int lane = threadIdx.x & 63, grp = threadIdx.x >> 6;
@@ -680,27 +664,34 @@ __global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (j < N) {
         int64_t g = grp;
-        for (; g + 12 < G; g += 16) {
+        for (; g + 3 * NG < G; g += 4 * NG) {
             a0 += (double)q_part[g * N + j];
-            a1 += (double)q_part[(g + 4) * N + j];
-            a2 += (double)q_part[(g + 8) * N + j];
-            a3 += (double)q_part[(g + 12) * N + j];
+            a1 += (double)q_part[(g + NG) * N + j];
+            a2 += (double)q_part[(g + 2 * NG) * N + j];
+            a3 += (double)q_part[(g + 3 * NG) * N + j];
         }
-        for (; g < G; g += 4)
+        for (; g < G; g += NG)
             a0 += (double)q_part[g * N + j];
     }
-    part4[grp][lane] = (a0 + a1) + (a2 + a3);
-    // W d, the W columns split over the four groups
+    part[grp][lane] = (a0 + a1) + (a2 + a3);
+    // W d, the W columns split over the groups
     double pr = 0.0;
     if (j < N)
-        for (int i = grp; i < kd; i += 4)
+        for (int i = grp; i < kd; i += NG)
             pr += W[j + (int64_t)i * N] * d[i];
     __syncthreads();
-    const double v = part4[0][lane] + part4[1][lane] + part4[2][lane] + part4[3][lane];
+    double v = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+        v += part[q][lane];
     __syncthreads();
-    part4[grp][lane] = pr;
+    part[grp][lane] = pr;
     __syncthreads();
-    const double qv = v - (part4[0][lane] + part4[1][lane] + part4[2][lane] + part4[3][lane]);
+    double wd = 0.0;
+#pragma unroll
+    for (int q = 0; q < NG; ++q)
+        wd += part[q][lane];
+    const double qv = v - wd;
     if (grp == 0) {
         if (j < N)
             qy[j] = qv;
@@ -709,22 +700,60 @@ __global__ __launch_bounds__(256) void k_fin_q(const E *__restrict__ q_part, int
     if (done || kg == 0)
         return;
     __syncthreads();
-    for (int i = grp; i < kg; i += 4) {
+    for (int i = grp; i < kg; i += NG) {
         const double sv = (j < N) ? (double)P[j + (int64_t)i * N] * ys[lane] : 0.0;
         const double sum = fwave_sum(sv);
         if (lane == 0)
             cpart[(int64_t)blockIdx.x * kg + i] = sum;
     }
-    if (!fused_arrive_last(&st->counter[kCntDotN], &last))
+    if (!arrive_last(&st->counter[kCntDotN], &last))
         return;
-    for (int i = threadIdx.x; i < kg; i += 256) {
-        double sum = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b)
-            sum += cpart[(int64_t)b * kg + i];
-        c[i] = sum;
-    }
+    reduce_partials(cpart, gridDim.x, kg, c, &part[0][0]);
     if (threadIdx.x == 0)
         st->counter[kCntDotN] = 0;
+}
+
+// Gram-Schmidt coefficients of the score, d = V_(k)^T t (FP64), from the
+// complete t of the pass: workgroup b takes `rows` consecutive rows (staged in
+// LDS), one wave per column of V with 8 loads in flight per lane, per-group
+// partials, and the last workgroup adds them in a fixed order.
+template <typename E>
+__global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t, int64_t M,
+                                                   const E *__restrict__ V, int kd, int64_t rows,
+                                                   double *__restrict__ cpart,
+                                                   double *__restrict__ d, LoopState *st)
+{
+    if (st->done)
+        return;
+    __shared__ double ts[kScoreRows];
+    __shared__ double lds[256];
+    __shared__ int last;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * rows;
+    const int n = (int)(M - r0 < rows ? M - r0 : rows);
+    for (int x = tid; x < n; x += 256)
+        ts[x] = t[r0 + x];
+    __syncthreads();
+    for (int i = w; i < kd; i += 4) {
+        const E *vc = V + (int64_t)i * M + r0;
+        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        int x = lane;
+        for (; x + 7 * 64 < n; x += 8 * 64) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                a[u] += (double)vc[x + u * 64] * ts[x + u * 64];
+        }
+        for (; x < n; x += 64)
+            a[0] += (double)vc[x] * ts[x];
+        const double sum = fwave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
+        if (lane == 0)
+            cpart[(int64_t)blockIdx.x * kd + i] = sum;
+    }
+    if (!arrive_last(&st->counter[kCntDotM], &last))
+        return;
+    reduce_partials(cpart, gridDim.x, kd, d, lds);
+    if (tid == 0)
+        st->counter[kCntDotM] = 0;
 }
 
 // Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
@@ -874,11 +903,21 @@ void Fused<F>::pass(int first, int cpt, int G, int NT, int plds, int skew, int p
 }
 
 template <int F>
+void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, double *cpart, double *d,
+                         LoopState *st, hipStream_t s)
+{
+    const int64_t rows = score_rows(M);
+    hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows)), dim3(256), 0, s, t, M, V, kd, rows,
+                       cpart, d, st);
+}
+
+template <int F>
 void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                      const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                      LoopState *st, int it, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 64)), dim3(256), 0, s, q_part, G, N, W, kd, d, P,
+    hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 64)), dim3(64 * kFinGroups), 0, s, q_part, G, N,
+                       W, kd, d, P,
                        kg, qy, cpart, c, st, it);
 }
 

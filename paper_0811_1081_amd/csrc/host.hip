@@ -516,7 +516,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 // Gram-Schmidt coefficients of the score, d = V_(k)^T t (coalesced
                 // over the rows, kept out of the streaming pass)
                 if (kg > 0)
-                    L::gs_dot(td, 1, len, M, T, M, kg, nullptr, cpart, dvec, st, kCntDotM, s);
+                    F::score_dot(td, M, T, kg, cpart, dvec, st, s);
                 L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, nullptr, tE, sq, st, 1, tol,
                             limit, replay, tiny, stop, s);
                 F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);

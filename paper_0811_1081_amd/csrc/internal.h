@@ -38,6 +38,74 @@ struct LoopState {
 
 enum Counter { kCntDotN = 0, kCntApplyN = 1, kCntDotM = 2, kCntApplyM = 3 };
 
+// Last-arriving workgroup detection.  Each workgroup has written its partial
+// results before calling.  The barrier orders every wave's writes before
+// thread 0, whose device-scope release fence then publishes them to all XCDs
+// (one L2 write-back per workgroup rather than one per wave, which costs tens
+// of microseconds on wide grids); its atomic elects the final workgroup, whose
+// threads acquire before reading the partials.  The winner resets the counter.
+__device__ inline bool arrive_last(uint32_t *counter, int *flag_lds)
+{
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        __threadfence();
+        const uint32_t prev = atomicAdd(counter, 1u);
+        *flag_lds = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
+    }
+    __syncthreads();
+    const bool last = *flag_lds != 0;
+    if (last)
+        __threadfence();
+    return last;
+}
+
+// out[i] = sum over b < nb of part[b*k + i], i < k, by one whole workgroup:
+// column i gets S = blockDim / k threads (slice s sums partials b = s, s+S,
+// ...), and the S slice sums are added in slice order, so the result is the
+// same on every run.  `lds` holds blockDim doubles.  All threads must call it.
+__device__ inline void reduce_partials(const double *__restrict__ part, int64_t nb, int k,
+                                       double *__restrict__ out, double *lds)
+{
+    const int nt = blockDim.x, t = threadIdx.x;
+    for (int c0 = 0; c0 < k; c0 += nt) {
+        const int kk = k - c0 < nt ? k - c0 : nt;
+        const int S = nt / kk;
+        const int i = t % kk, sl = t / kk;
+        double a0 = 0.0, a1 = 0.0;
+        if (sl < S) {
+            int64_t b = sl;
+            for (; b + S < nb; b += 2 * S) {
+                a0 += part[b * k + c0 + i];
+                a1 += part[(b + S) * k + c0 + i];
+            }
+            if (b < nb)
+                a0 += part[b * k + c0 + i];
+        }
+        __syncthreads();
+        lds[t] = a0 + a1;
+        __syncthreads();
+        if (t < kk) {
+            double r = 0.0;
+            for (int q = 0; q < S; ++q)
+                r += lds[q * kk + t];
+            out[c0 + t] = r;
+        }
+    }
+}
+
+// Groups of partial sums per workgroup of the loading-side finish (64
+// columns each; 64 * kFinGroups threads).
+constexpr int kFinGroups = 16;
+
+// Rows per workgroup of the score coefficient reduction: about 128
+// workgroups, whole waves, at most kScoreRows.
+constexpr int64_t kScoreRows = 2048;
+inline int64_t score_rows(int64_t M)
+{
+    const int64_t r = ((M + 127) / 128 + 63) / 64 * 64;
+    return r < 256 ? 256 : (r > kScoreRows ? kScoreRows : r);
+}
+
 struct StartArgs {
     int32_t k;
     int32_t init;           // gspca_init
@@ -105,6 +173,8 @@ struct Fused {
                      int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
                      const double *p, const E *t_in, double *t_out, E *q_part, LoopState *st,
                      hipStream_t s);
+    static void score_dot(const double *t, int64_t M, const E *V, int kd, double *cpart,
+                          double *d, LoopState *st, hipStream_t s);
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);

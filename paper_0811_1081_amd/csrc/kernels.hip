@@ -58,23 +58,6 @@ __device__ inline T block_sum(T v, T *lds4)
     return r;
 }
 
-// Last-arriving workgroup detection.  Each workgroup has written its partial
-// results before calling; the fence publishes them device-wide (all XCDs),
-// the counter elects the final workgroup, which resets it for the next use.
-__device__ inline bool arrive_last(uint32_t *counter, int *flag_lds)
-{
-    __threadfence();
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        const uint32_t prev = atomicAdd(counter, 1u);
-        *flag_lds = (prev == gridDim.x * gridDim.y - 1) ? 1 : 0;
-    }
-    __syncthreads();
-    const bool last = *flag_lds != 0;
-    if (last)
-        __threadfence();
-    return last;
-}
 
 // ---------------------------------------------------------------------------
 // R <- X (Sec. 2.2/2.3 first step) into the padded layout; flags NaN/Inf.
@@ -385,12 +368,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ pa
     }
     if (!arrive_last(&st->counter[counter], &last))
         return;
-    for (int i = threadIdx.x; i < k; i += kBlock) {
-        double s = 0.0;
-        for (int b = 0; b < (int)gridDim.x; ++b)
-            s += cpart[(int64_t)b * k + i];
-        c[i] = s;
-    }
+    reduce_partials(cpart, gridDim.x, k, c, ys);
     if (threadIdx.x == 0)
         st->counter[counter] = 0;
 }
@@ -441,9 +419,20 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
         for (int i = threadIdx.x; i < n; i += kBlock)
             cs[i] = c[i0 + i];
         __syncthreads();
-        if (r < L)
-            for (int i = 0; i < n; ++i)
+        if (r < L) {
+            // four independent sums so that the column loads overlap
+            double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            int i = 0;
+            for (; i + 3 < n; i += 4) {
                 proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
+                p1 += (double)Q[r + (int64_t)(i0 + i + 1) * ldq] * cs[i + 1];
+                p2 += (double)Q[r + (int64_t)(i0 + i + 2) * ldq] * cs[i + 2];
+                p3 += (double)Q[r + (int64_t)(i0 + i + 3) * ldq] * cs[i + 3];
+            }
+            for (; i < n; ++i)
+                proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
+            proj = (proj + p1) + (p2 + p3);
+        }
     }
     v -= proj;
     double dot_old = 0.0;
