@@ -12,10 +12,12 @@
  *   [refinement, `power` times: Y = X (X^T Z / sqrt(M)), whiten again -- one
  *    step of subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4),
  *    which turns the sketch's directions into Ritz vectors of X X^T]
- *   o_m = W3^T relu(W2^T relu(W1^T z_m + b1) + b2) + b3   for every row m
+ *   o_m = z_m[:d3] + W3^T relu(W2^T relu(W1^T z_m + b1) + b2) + b3  (every row m)
  *   T0[:, k] = (o_0k, ..., o_(M-1)k)      start of component k (sign free)
  *
- * The network is row-wise (the same map for every row and every matrix).
+ * The network is row-wise (the same map for every row and every matrix): the
+ * first d3 whitened directions (Ritz vectors of the sketch) plus a learned
+ * correction; with W3 = 0 it returns the un-learned sketch start.
  * Products run on bfloat16 matrix cores with FP32 accumulation; rounding
  * points (round to nearest even): the input rows z_m, the weights W1..W3, the
  * stored hidden activations, and in the backward pass the incoming gradient
@@ -49,7 +51,7 @@ extern "C" {
  * W1, b1, W2, b2, W3, b3; W_l is row-major d_(l-1) x d_l (W[i*d_l + j] maps
  * input i to output j).  theta_bf16, grad, adam_m and adam_v use the same
  * packing.  d0 must be 32, d1 and d2 in [16, 1024], d3 (the number of
- * components predicted) in [1, 64]. */
+ * components predicted) in [1, 32]. */
 typedef struct {
     int32_t d0, d1, d2, d3;
     float *theta;      /* FP32 master parameters (caller initialises)          */

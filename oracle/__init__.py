@@ -78,7 +78,7 @@ def lib() -> ctypes.CDLL:
             ci = ctypes.c_int
             L.oracle_mlp_forward.restype = None
             L.oracle_mlp_forward.argtypes = [vp, i64, ci, ci, ci, ci, vp, vp, vp, vp, vp, vp, ci,
-                                             vp, vp, vp]
+                                             ci, vp, vp, vp, vp]
             L.oracle_cos2_loss.restype = dbl
             L.oracle_cos2_loss.argtypes = [vp, vp, i64, ci, vp]
             L.oracle_mlp_backward.restype = None
@@ -269,16 +269,20 @@ def _c64(a):
     return np.ascontiguousarray(a, dtype=np.float64)
 
 
-def mlp_forward(Z, params, round_bf16=False):
+def mlp_forward(Z, params, round_bf16=False, skip=None):
     """params = (W1, b1, W2, b2, W3, b3) with W_l of shape (d_in, d_out).
-    Returns (H1, H2, O); rows of Z are samples."""
+    Returns (H1, H2, O); rows of Z are samples.  skip: an (M, d0) array whose
+    first d3 columns are added to the output (the network's skip term; pass
+    the unrounded inputs), or None."""
     W1, b1, W2, b2, W3, b3 = [_c64(x) for x in params]
     Z = _c64(Z)
     M, d0 = Z.shape
     d1, d2, d3 = W1.shape[1], W2.shape[1], W3.shape[1]
     H1 = np.zeros((M, d1)); H2 = np.zeros((M, d2)); O = np.zeros((M, d3))
+    Zs = _c64(skip) if skip is not None else Z
     lib().oracle_mlp_forward(_ptr(Z), M, d0, d1, d2, d3, _ptr(W1), _ptr(b1), _ptr(W2), _ptr(b2),
-                             _ptr(W3), _ptr(b3), int(bool(round_bf16)), _ptr(H1), _ptr(H2), _ptr(O))
+                             _ptr(W3), _ptr(b3), int(bool(round_bf16)), int(skip is not None),
+                             _ptr(Zs), _ptr(H1), _ptr(H2), _ptr(O))
     return H1, H2, O
 
 

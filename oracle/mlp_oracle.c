@@ -8,7 +8,8 @@
  * column, Secs. 2.2-2.3).  It is this project's learned initial score: a
  * row-wise multilayer perceptron maps each row z_m of a whitened random
  * sketch of X to row m of the K initial scores,
- *     h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), o = h2 W3 + b3,
+ *     h1 = relu(z W1 + b1), h2 = relu(h1 W2 + b2), o = z[:d3] + h2 W3 + b3
+ * (the skip term z[:d3] -- the first d3 inputs -- only when `skip` is set),
  * and is trained with the sign-invariant loss
  *     L = sum_k [ 1 - (o_k . v_k)^2 / (|o_k|^2 |v_k|^2) ]
  * between each output column o_k (over the rows) and the converged
@@ -52,12 +53,16 @@ static void layer(const double *X, int64_t M, int din, int dout, const double *W
 
 void oracle_mlp_forward(const double *Z, int64_t M, int d0, int d1, int d2, int d3,
                         const double *W1, const double *b1, const double *W2, const double *b2,
-                        const double *W3, const double *b3, int round_bf16_act, double *H1,
-                        double *H2, double *O)
+                        const double *W3, const double *b3, int round_bf16_act, int skip,
+                        const double *Zskip, double *H1, double *H2, double *O)
 {
     layer(Z, M, d0, d1, W1, b1, 1, round_bf16_act, H1);
     layer(H1, M, d1, d2, W2, b2, 1, round_bf16_act, H2);
     layer(H2, M, d2, d3, W3, b3, 0, 0, O);
+    if (skip)
+        for (int64_t m = 0; m < M; ++m)
+            for (int k = 0; k < d3; ++k)
+                O[m * d3 + k] += Zskip[m * d0 + k];
 }
 
 /* Loss and its gradient dO = dL/dO (M x K). */

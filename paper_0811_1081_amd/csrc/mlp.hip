@@ -38,18 +38,19 @@ __device__ inline __bf16 to_bf16(__bf16 x) { return x; }
 // rounded to bf16 as they are loaded.  One wave computes a 16 x 16 tile, a
 // workgroup of four waves a 32 x 32 tile.  blockIdx.z splits the k range into
 // chunks of `kchunk` (a multiple of 32):
-//   - split == 0: C(i, j) at Cf[i*c_r + j*c_c] (FP32, + bias, relu, mask,
-//     optionally added to the old value) or Cb (bf16); mask zeroes C(i, j)
-//     where the stored activation mask[i*m_r + j] is not positive;
+//   - split == 0: C(i, j) at Cf[i*c_r + j*c_c] (FP32, + bias, + skip(i, j) =
+//     skip[i*s_r + j], relu, mask, optionally added to the old value) or Cb
+//     (bf16); mask zeroes C(i, j) where the stored activation mask[i*m_r + j]
+//     is not positive;
 //   - split != 0: raw partial sums to part[z*M*N + i*N + j].
 
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(
     const TA *__restrict__ A, int64_t a_r, int64_t a_c, const TB *__restrict__ B, int64_t b_r,
     int64_t b_c, int64_t M, int64_t N, int64_t Kd, int64_t kchunk, const float *__restrict__ bias,
-    int relu, const __bf16 *__restrict__ mask, int64_t m_r, float *__restrict__ Cf,
-    __bf16 *__restrict__ Cb, int64_t c_r, int64_t c_c, int accumulate, int split,
-    float *__restrict__ part)
+    int relu, const __bf16 *__restrict__ mask, int64_t m_r, const float *__restrict__ skip,
+    int64_t s_r, float *__restrict__ Cf, __bf16 *__restrict__ Cb, int64_t c_r, int64_t c_c,
+    int accumulate, int split, float *__restrict__ part)
 {
     const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
     const int64_t i0 = (int64_t)blockIdx.y * 32 + (w >> 1) * 16;
@@ -90,6 +91,8 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(
         }
         if (bias)
             v += bias[j];
+        if (skip)
+            v += skip[i * s_r + j];
         if (relu && !(v > 0.0f))
             v = 0.0f;
         if (mask && !((float)mask[i * m_r + j] > 0.0f))
@@ -454,7 +457,7 @@ Offs param_offsets(int d0, int d1, int d2, int d3)
 bool valid_net(const gspca_mlp *n)
 {
     return n && n->d0 == GSPCA_WS_RANK && n->d1 >= 16 && n->d1 <= 1024 && n->d2 >= 16 &&
-           n->d2 <= 1024 && n->d3 >= 1 && n->d3 <= 64 && n->theta && n->theta_bf16;
+           n->d2 <= 1024 && n->d3 >= 1 && n->d3 <= n->d0 && n->theta && n->theta_bf16;
 }
 
 // Split-K partial buffer: enough for any weight gradient with <= kMaxSplit
@@ -493,7 +496,7 @@ template <typename TA, typename TB>
 void gemm_launch(const TA *A, int64_t a_r, int64_t a_c, const TB *B, int64_t b_r, int64_t b_c,
                  int64_t M, int64_t N, int64_t Kd, const float *bias, int relu, const __bf16 *mask,
                  int64_t m_r, float *Cf, __bf16 *Cb, int64_t c_r, int64_t c_c, float *part,
-                 hipStream_t s)
+                 hipStream_t s, const float *skip = nullptr, int64_t s_r = 0)
 {
     // Split the k range when the output tiles alone cannot fill the chip
     // (weight gradients: small outputs, k = all rows).
@@ -507,8 +510,8 @@ void gemm_launch(const TA *A, int64_t a_r, int64_t a_c, const TB *B, int64_t b_r
     nz = (int)((Kd + kchunk - 1) / kchunk);
     dim3 g(ucdiv(N, 32), ucdiv(M, 32), nz);
     hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), g, dim3(256), 0, s, A, a_r, a_c, B, b_r, b_c, M, N,
-                       Kd, kchunk, bias, relu, mask, m_r, Cf, Cb, c_r, c_c, 0, nz > 1 ? 1 : 0,
-                       part);
+                       Kd, kchunk, bias, relu, mask, m_r, skip, s_r, Cf, Cb, c_r, c_c, 0,
+                       nz > 1 ? 1 : 0, part);
     if (nz > 1)
         hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(M * N, 256)), dim3(256), 0, s, part, nz, M,
                            N, Cf, c_r, c_c);
@@ -537,8 +540,10 @@ void forward(const gspca_mlp *n, const float *Z, int64_t rows, __bf16 *H1, __bf1
                                1, nullptr, 0, nullptr, H1, n->d1, 1, nullptr, s);
     gemm_launch<__bf16, __bf16>(H1, n->d1, 1, wb + of.W2, n->d2, 1, rows, n->d2, n->d1,
                                 th + of.b2, 1, nullptr, 0, nullptr, H2, n->d2, 1, nullptr, s);
+    // output = z[:d3] + W3^T h2 + b3: the whitened directions plus a learned correction
     gemm_launch<__bf16, __bf16>(H2, n->d2, 1, wb + of.W3, n->d3, 1, rows, n->d3, n->d2,
-                                th + of.b3, 0, nullptr, 0, O, nullptr, o_r, o_c, nullptr, s);
+                                th + of.b3, 0, nullptr, 0, O, nullptr, o_r, o_c, nullptr, s, Z,
+                                n->d0);
 }
 
 gspca_status launched()

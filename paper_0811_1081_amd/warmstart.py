@@ -97,11 +97,12 @@ def whiten(Y, stream=None):
 
 
 class WarmStartNet:
-    """Row-wise network 32 -> d1 -> d2 -> K with FP32 master weights, bf16
-    copies and Adam state, all device tensors; parameters packed as
-    W1 b1 W2 b2 W3 b3 with W_l row-major (d_in x d_out)."""
+    """Row-wise network 32 -> d1 -> d2 -> K (K <= 32) with the skip term
+    o = z[:K] + W3^T h2 + b3, FP32 master weights, bf16 copies and Adam state,
+    all device tensors; parameters packed as W1 b1 W2 b2 W3 b3 with W_l
+    row-major (d_in x d_out)."""
 
-    def __init__(self, K, hidden=(256, 256), seed=0, device="cuda"):
+    def __init__(self, K, hidden=(256, 256), seed=0, device="cuda", last_zero=True):
         import torch
         self.dims = (RANK, int(hidden[0]), int(hidden[1]), int(K))
         L = _b.load()
@@ -109,7 +110,7 @@ class WarmStartNet:
         self.n = n
         self.device = torch.device(device)
         f32 = dict(dtype=torch.float32, device=self.device)
-        self.theta = torch.from_numpy(self.init_params(self.dims, seed)).to(self.device)
+        self.theta = torch.from_numpy(self.init_params(self.dims, seed, last_zero)).to(self.device)
         self.theta_bf16 = torch.empty(n, dtype=torch.int16, device=self.device)
         self.grad = torch.zeros(n, **f32)
         self.adam_m = torch.zeros(n, **f32)
@@ -122,12 +123,18 @@ class WarmStartNet:
         self.sync()
 
     @staticmethod
-    def init_params(dims, seed):
-        """He-normal weights (std sqrt(2 / d_in)), zero biases, float32."""
+    def init_params(dims, seed, last_zero=True):
+        """He-normal weights (std sqrt(2 / d_in)), zero biases, float32; the
+        last layer zero (last_zero) so that the untrained network returns the
+        sketch directions through its skip term."""
         rng = np.random.default_rng([811, 13, int(seed)])
         parts = []
-        for a, b in zip(dims[:-1], dims[1:]):
-            parts.append((rng.standard_normal((a, b)) * np.sqrt(2.0 / a)).ravel())
+        nl = len(dims) - 1
+        for l, (a, b) in enumerate(zip(dims[:-1], dims[1:])):
+            w = rng.standard_normal((a, b)) * np.sqrt(2.0 / a)
+            if last_zero and l == nl - 1:
+                w = np.zeros((a, b))
+            parts.append(w.ravel())
             parts.append(np.zeros(b))
         return np.concatenate(parts).astype(np.float32)
 

@@ -112,7 +112,7 @@ def test_whitening_matches_oracle(orc):
 def test_forward_matches_oracle(orc):
     import torch
     from paper_0811_1081_amd import warmstart as ws
-    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=1)
+    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=1, last_zero=False)
     rng = np.random.default_rng(7)
     rows = 3000  # 93.75 tiles of 32 rows: a ragged edge
     Z = rng.standard_normal((rows, 32)).astype(np.float32)
@@ -125,7 +125,7 @@ def test_forward_matches_oracle(orc):
     O = net.forward(_dev(Z))
     torch.cuda.synchronize()
     params = _oracle_params(orc, net)
-    H1, H2, Oo = orc.mlp_forward(orc.bf16_round(Z), params, round_bf16=True)
+    H1, H2, Oo = orc.mlp_forward(orc.bf16_round(Z), params, round_bf16=True, skip=Z)
     assert _rel(O.cpu().numpy(), Oo) <= 2e-3
     # the bf16 copy is exactly the rounded master
     tb = (net.theta_bf16.cpu().numpy().astype(np.uint16).astype(np.uint32) << 16).view(np.float32)
@@ -143,7 +143,7 @@ def _unit_scores(rng, ninst, Mi, K):
 def test_loss_and_gradients_match_oracle(orc):
     import torch
     from paper_0811_1081_amd import warmstart as ws
-    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=2)
+    net = ws.WarmStartNet(K=DIMS[3], hidden=DIMS[1:3], seed=2, last_zero=False)
     rng = np.random.default_rng(8)
     ninst, Mi, K = 3, 700, DIMS[3]
     Z = rng.standard_normal((ninst * Mi, 32)).astype(np.float32)
@@ -153,7 +153,7 @@ def test_loss_and_gradients_match_oracle(orc):
     g_gpu = net.unpack(net.grad.cpu().numpy())
     params = _oracle_params(orc, net)
     Zr = orc.bf16_round(Z)
-    H1, H2, O = orc.mlp_forward(Zr, params, round_bf16=True)
+    H1, H2, O = orc.mlp_forward(Zr, params, round_bf16=True, skip=Z)
     dO = np.zeros_like(O)
     L = 0.0
     for b in range(ninst):
@@ -197,15 +197,27 @@ def test_predict_composes_sketch_whiten_forward(orc):
     X = synth.haar_spectrum(M, N, np.linspace(1.0, 0.3, N), 0.0, seed=(15, 1), centre=False,
                             dtype=np.float32)
     Om = synth.sketch_matrix(N, 32)
-    net = ws.WarmStartNet(K=8, hidden=(64, 64), seed=4)
+    net = ws.WarmStartNet(K=8, hidden=(64, 64), seed=4, last_zero=False)
     params = _oracle_params(orc, net)
     for power in (0, 1):
         T0 = net.predict(_colmajor(X), _dev(Om), power=power)
         torch.cuda.synchronize()
         _, Zo, _ = orc.sketch_whiten(X, Om, power=power)
-        _, _, Oo = orc.mlp_forward(orc.bf16_round(Zo), params, round_bf16=True)
+        _, _, Oo = orc.mlp_forward(orc.bf16_round(Zo), params, round_bf16=True, skip=Zo)
         assert T0.stride() == (1, M)
         assert _rel(T0.cpu().numpy(), Oo) <= 5e-3, power
+
+
+def test_untrained_network_returns_the_sketch_directions():
+    """With the last layer zero the output is the skip term: the first K
+    whitened directions, exactly (FP32 copy)."""
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    net = ws.WarmStartNet(K=12, seed=6)
+    Z = torch.randn(777, 32, device="cuda")
+    O = net.forward(Z)
+    torch.cuda.synchronize()
+    assert torch.equal(O, Z[:, :12])
 
 
 def test_errors_are_reported_on_host():

@@ -89,3 +89,31 @@ def test_adam_matches_definition(orc):
     orc.adam_step(w, g1, m1, m2, lr=0.01, t=1)
     # first step: m_hat = g, v_hat = g^2 -> w -= lr * g / (|g| + eps)
     assert np.allclose(w, w0 - 0.01 * g1 / (np.abs(g1) + 1e-8), rtol=0, atol=1e-15)
+
+
+def test_skip_term(orc):
+    """The skip adds the first d3 inputs to the output and changes the
+    parameter gradients only through dL/dO (finite differences)."""
+    rng = np.random.default_rng(12)
+    dims = (6, 9, 7, 3)
+    M = 10
+    Z = rng.standard_normal((M, dims[0]))
+    V = rng.standard_normal((M, dims[-1]))
+    params = _params(rng, dims)
+    _, _, O0 = orc.mlp_forward(Z, params)
+    H1, H2, O = orc.mlp_forward(Z, params, skip=Z)
+    assert np.array_equal(O, O0 + Z[:, :3])
+    L, dO = orc.cos2_loss(O, V)
+    grads = orc.mlp_backward(Z, params, H1, H2, dO)
+    h = 1e-6
+    P = params[2]
+    num = np.zeros_like(P)
+    for idx in np.ndindex(P.shape):
+        old = P[idx]
+        P[idx] = old + h
+        lp = orc.cos2_loss(orc.mlp_forward(Z, params, skip=Z)[2], V)[0]
+        P[idx] = old - h
+        lm = orc.cos2_loss(orc.mlp_forward(Z, params, skip=Z)[2], V)[0]
+        P[idx] = old
+        num[idx] = (lp - lm) / (2 * h)
+    assert np.linalg.norm(num - grads[2]) <= 1e-6 * np.linalg.norm(grads[2])
