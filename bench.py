@@ -56,6 +56,25 @@ def cpu_baseline(X, mean_iters, n_short=1, n_long=6):
     }
 
 
+def measured_traffic(kernel, form, M, N):
+    """HBM bytes per launch of the dominant kernel from the committed counter
+    summary (profiles/traffic.json), or None when that record is for another
+    configuration or the kernel's source has changed since it was measured."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    try:
+        with open(path) as f:
+            rec = json.load(f).get("%s %s %dx%d" % (kernel, form, M, N))
+        if rec is None:
+            return None
+        with open(os.path.join(ROOT, rec["kernel_source"]), "rb") as f:
+            if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
+                return None
+        return float(rec["bytes"])
+    except (OSError, ValueError, KeyError):
+        return None
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -154,6 +173,10 @@ def main():
     orth_p = float((P.T @ P - eye).abs().max())
     orth_v = float((V.T @ V - eye).abs().max())
 
+    form = "%s_%s_%s" % ({"f32": "plain_fp32", "bf16": "bf16_codes",
+                          "e4m3": "fp8_e4m3_codes"}[args.form],
+                         "implicit" if args.implicit else "explicit",
+                         "single_pass" if prof.single_pass else "two_pass")
     res = {
         "metric": METRIC, "value": value, "unit": "components/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
@@ -162,12 +185,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "large_f32_lowrank_%dx%d_K%d" % (M, N, K), "M": M, "N": N,
                    "K": K, "tol": args.tol, "max_iter": args.max_iter, "algo": "gs",
-                   "form": "%s_%s_%s" % ({"f32": "plain_fp32", "bf16": "bf16_codes",
-                                           "e4m3": "fp8_e4m3_codes"}[args.form],
-                                          "implicit" if args.implicit else "explicit",
-                                          "single_pass" if prof.single_pass else "two_pass")},
+                   "form": form},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": achieved, "peak": HBM_PEAK_GBPS,
-                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
+                     "traffic": measured_traffic(dom, form, M, N),
                      "avg_launch_us": avg_s * 1e6, "bytes_per_launch": bytes_per_launch,
                      "launches_timed": int(n_l)},
         "iters_mean": float(iters.mean()),
