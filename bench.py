@@ -8,7 +8,9 @@ noise, tol 1e-6, max_iter 1000, through the C ABI, inputs resident in HBM.
 
 Prints one JSON line with whole-job throughput (components/s), the roofline
 of the dominant streaming kernel (HIP-event timed inside the timed region),
-and the FP64 CPU oracle timed on a bounded sample of the same workload.
+the FP64 CPU oracle timed on a bounded sample of the same workload, and (FP32
+runs) the BF16 + warm-start form against plain FP32 at the same loading
+accuracy ("precision_form").
 """
 from __future__ import annotations
 
@@ -56,6 +58,95 @@ def cpu_baseline(X, mean_iters, n_short=1, n_long=6):
     }
 
 
+def loading_angles(P, R):
+    """Sign-aligned chordal angles between the columns of P and R (radians)."""
+    import torch
+    P = P.double()
+    R = R.double()
+    s = torch.sign((P * R).sum(0))
+    s[s == 0] = 1
+    d = (P - R * s).norm(dim=0)
+    return 2 * torch.asin(torch.clamp(d / 2, max=1.0))
+
+
+def reference_loadings(Xd, P0, K, steps=12, extra=32):
+    """Loadings of X to FP64 accuracy, independent of the library: subspace
+    iteration on the Gram matrix X^T X (FP64, torch/rocBLAS) from P0 plus
+    `extra` random columns, then a Rayleigh-Ritz step.  With the large
+    workload's spectrum the error falls by (sigma_65 / sigma_32)^2 ~ 0.03 per
+    step."""
+    import torch
+    X64 = Xd.double()
+    G = X64.T @ X64
+    del X64
+    gen = torch.Generator(device=Xd.device).manual_seed(811)
+    Q = torch.cat([P0.double(), torch.randn(G.shape[0], extra, dtype=torch.float64,
+                                            device=Xd.device, generator=gen)], 1)
+    for _ in range(steps):
+        Q, _ = torch.linalg.qr(G @ Q)
+    w, U = torch.linalg.eigh(Q.T @ G @ Q)
+    idx = torch.argsort(w, descending=True)[:K]
+    return Q @ U[:, idx]
+
+
+def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
+    """Reduced-precision forms against plain FP32 at the same loading
+    accuracy.  Every form ends with the same loading stop (|p_j - s p_(j-1)|
+    < tol_loading) on the FP32 matrix, and every result is compared with the
+    FP64 reference loadings.
+      plain:      FP32 fit, max-norm starts.
+      bf16:       BF16 codes (one quantisation pass), BF16 fit (implicit
+                  deflation) with the loading stop at low_tol -- about where
+                  the BF16 representation error stops further progress --
+                  then FP32 refinement from the BF16 scores.
+      bf16_warm:  the same with warm starts for the BF16 fit: the whitened
+                  sketch after one refinement step (the network's skip path).
+    Times are HIP-event totals with the input resident in HBM."""
+    import torch
+    from paper_0811_1081_amd import synth, warmstart as ws
+    M, N = Xd.shape
+
+    def timed(fn):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        torch.cuda.synchronize()
+        a.record()
+        out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        return out, a.elapsed_time(b)
+
+    plain, ms_plain = timed(lambda: gp.fit(Xd, K, tol=tol_loading, max_iter=max_iter,
+                                           stop="loading", check=False))
+    Pref = reference_loadings(Xd, plain["P"], K)
+    log("precision form: plain FP32 %.1f ms" % ms_plain)
+    Om = torch.from_numpy(synth.sketch_matrix(N, ws.RANK)).cuda()
+    net = ws.WarmStartNet(K=K, seed=0)  # last layer zero: the skip path (Ritz start)
+    net.predict(Xd, Om, power=1)        # workspace allocation outside the timing
+    Q, ms_q = timed(lambda: gp.quantize(Xd, "bf16"))
+    out = {"loading_stop_tol": tol_loading, "bf16_loading_tol": low_tol,
+           "plain_fp32": {"ms": ms_plain, "iters_mean": float(plain["iters"].double().mean()),
+                          "max_loading_err": float(loading_angles(plain["P"], Pref).max()),
+                          "status": int(plain["status"])}}
+    for name, warm in (("bf16", False), ("bf16_warm", True)):
+        T0, ms_ws = (timed(lambda: net.predict(Xd, Om, power=1)) if warm else (None, 0.0))
+        kw = {"init": "given", "T0": T0} if warm else {}
+        low, ms_low = timed(lambda: gp.fit(Q, K, tol=low_tol, max_iter=max_iter, stop="loading",
+                                           check=False, **kw))
+        fin, ms_fin = timed(lambda: gp.fit(Xd, K, tol=tol_loading, max_iter=max_iter,
+                                           init="given", T0=low["T"], stop="loading",
+                                           check=False))
+        total = ms_q + ms_ws + ms_low + ms_fin
+        out[name] = {"ms": total, "speedup_vs_plain": ms_plain / total, "quantize_ms": ms_q,
+                     "warm_start_ms": ms_ws, "bf16_fit_ms": ms_low, "fp32_refine_ms": ms_fin,
+                     "bf16_iters_mean": float(low["iters"].double().mean()),
+                     "refine_iters_mean": float(fin["iters"].double().mean()),
+                     "bf16_max_loading_err": float(loading_angles(low["P"], Pref).max()),
+                     "max_loading_err": float(loading_angles(fin["P"], Pref).max()),
+                     "status": int(fin["status"])}
+        log("precision form: %s %.1f ms" % (name, total))
+    return out
+
+
 def measured_traffic(kernel, form, M, N):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (profiles/traffic.json), or None when that record is for another
@@ -90,6 +181,10 @@ def main():
     ap.add_argument("--form", default="f32", choices=["f32", "bf16", "e4m3"],
                     help="storage of X streamed by the iteration (bf16/e4m3: quantised codes, "
                          "implicit deflation)")
+    ap.add_argument("--no-precision-form", action="store_true",
+                    help="skip the BF16 + warm-start vs FP32 comparison at equal loading error")
+    ap.add_argument("--loading-tol", type=float, default=5e-7,
+                    help="loading stop of that comparison")
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
@@ -198,6 +293,10 @@ def main():
         "orth_P": orth_p, "orth_V": orth_v,
         "cpu_baseline": None,
     }
+    if args.form == "f32" and not args.no_precision_form:
+        del ws, ws_view, outs, out
+        torch.cuda.empty_cache()
+        res["precision_form"] = precision_form(gp, Xd, K, args.loading_tol, 3000, log)
     if not args.no_cpu_baseline:
         log("timing the FP64 oracle on a bounded sample")
         res["cpu_baseline"] = cpu_baseline(X, float(iters.mean()))
