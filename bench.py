@@ -166,6 +166,119 @@ def measured_traffic(kernel, form, M, N):
         return None
 
 
+def _batched_instance(args):
+    from paper_0811_1081_amd import synth
+    i, M, N = args
+    return synth.batched_instance(i, M, N)
+
+
+def generate_batched(shapes, workers=8):
+    """Host matrices of the batched workload (a spawn pool with one BLAS
+    thread per worker; call before the process touches the GPU)."""
+    import multiprocessing as mp
+    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
+    saved = {k: os.environ.get(k) for k in keys}
+    for k in keys:
+        os.environ[k] = "1"
+    try:
+        with mp.get_context("spawn").Pool(workers) as pool:
+            return pool.map(_batched_instance, [(i, m, n) for i, (m, n, _) in enumerate(shapes)],
+                            chunksize=16)
+    finally:
+        for k, v in saved.items():
+            if v is None:
+                os.environ.pop(k, None)
+            else:
+                os.environ[k] = v
+
+
+def bench_batched(args):
+    """The batched form: 2048 uneven FP32 problems (M ~ U{64..4096},
+    N ~ U{16..512}, rank min(16, N), s_i = 0.8^i, 1e-3 noise, K = min(8, N)),
+    tol 1e-6, fitted by one persistent launch replayed from a hipGraph, with
+    the autotuned launch shape.  One step = one replay (every problem refit)."""
+    import numpy as np
+    from paper_0811_1081_amd import synth
+    shapes = synth.batched_shapes(args.batch_count)
+    log("generating %d batched problems" % len(shapes))
+    t0 = time.perf_counter()
+    host = generate_batched(shapes)
+    log("generated in %.1f s" % (time.perf_counter() - t0))
+    import torch
+    import paper_0811_1081_amd as gp
+    gp.load()
+    Xs = [gp.column_major(torch.from_numpy(x).cuda()) for x in host]
+    del host
+    Ks = [k for _, _, k in shapes]
+    b = gp.Batch(Xs, Ks, tol=args.tol, max_iter=args.max_iter)
+    b.tune()
+    threads, occ = b.shape()
+    s = torch.cuda.Stream()
+    s.wait_stream(torch.cuda.current_stream())
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g, stream=s):
+        b.launch(stream=s)
+    torch.cuda.synchronize()
+    for _ in range(args.warmup):
+        g.replay()
+    torch.cuda.synchronize()
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    ev0.record()
+    for _ in range(args.steps):
+        g.replay()
+    ev1.record()
+    torch.cuda.synchronize()
+    elapsed = time.perf_counter() - t0
+    ms = ev0.elapsed_time(ev1) / args.steps
+    st = b.status.cpu().numpy()
+    its = [x.cpu().numpy() for x in b.iters]
+    comps = sum(Ks)
+    mn = np.array([m * n for m, n, _ in shapes], dtype=np.float64)
+    it_sum = np.array([int(x.sum()) for x in its], dtype=np.float64)
+    compulsory = float(mn.sum() * 4)              # every matrix read from HBM once
+    streamed = float((2.0 * mn * 4 * it_sum).sum())  # X read for t and for q every iteration
+    res = {
+        "metric": "batched GS-PCA components/s (2048 uneven problems, one persistent launch)",
+        "value": comps * args.steps / elapsed, "unit": "components/s", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": elapsed / args.steps * 1e3,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "batched_f32_%d_problems" % len(shapes), "problems": len(shapes),
+                   "sum_MN": int(mn.sum()), "K_total": comps, "tol": args.tol,
+                   "max_iter": args.max_iter, "threads": threads, "workgroups_per_cu": occ},
+        "roofline": {"bound": "hbm", "kernel": "k_batched", "achieved": compulsory / ms / 1e6,
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s",
+                     "frac": compulsory / ms / 1e6 / HBM_PEAK_GBPS, "traffic": None,
+                     "bytes_per_launch": compulsory, "avg_launch_us": ms * 1e3,
+                     "note": "achieved = one read of every matrix per launch; the iterations "
+                             "re-read each matrix from the caches (<= 8 MB per problem)"},
+        "cache_stream_GBps": streamed / ms / 1e6,
+        "iters_mean": float(it_sum.sum() / comps),
+        "status_ok": int((st == 0).sum()), "status_not_converged": int((st == 1).sum()),
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu_baseline:
+        import oracle
+        log("timing the FP64 oracle on a bounded sample of the batch")
+        dt = 0.0
+        done = 0
+        for i, (m, n, k) in enumerate(shapes):
+            X = synth.batched_instance(i, m, n)
+            t0 = time.perf_counter()
+            oracle.fit(X, k, tol=args.tol, max_iter=args.max_iter, implicit=True,
+                       tiny=oracle.FLT_MIN)
+            dt += time.perf_counter() - t0
+            done += k
+            if dt > 15.0:
+                break
+        res["cpu_baseline"] = {"value": done / dt, "unit": "components/s", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "FP64 oracle on the first %d problems of the batch "
+                                         "(%d components, %.1f s of fitting)" % (i + 1, done, dt)}
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -188,11 +301,17 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
+    ap.add_argument("--workload", default="large", choices=["large", "batched"],
+                    help="large: the 65536 x 8192 fit (default); batched: 2048 uneven problems")
+    ap.add_argument("--batch-count", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
               "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
+    if args.workload == "batched":
+        bench_batched(args)
+        return
 
     import numpy as np
     import torch
