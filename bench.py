@@ -101,6 +101,8 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
                   then FP32 refinement from the BF16 scores.
       bf16_warm:  the same with warm starts for the BF16 fit: the whitened
                   sketch after one refinement step (the network's skip path).
+      e4m3:       as bf16 with FP8 E4M3 codes (loading stop 3 x low_tol: the
+                  FP8 representation error is larger).
     Times are HIP-event totals with the input resident in HBM."""
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
@@ -122,21 +124,27 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
     Om = torch.from_numpy(synth.sketch_matrix(N, ws.RANK)).cuda()
     net = ws.WarmStartNet(K=K, seed=0)  # last layer zero: the skip path (Ritz start)
     net.predict(Xd, Om, power=1)        # workspace allocation outside the timing
-    Q, ms_q = timed(lambda: gp.quantize(Xd, "bf16"))
+    codes = {}
+    for fmt in ("bf16", "e4m3"):
+        codes[fmt] = timed(lambda: gp.quantize(Xd, fmt))
     out = {"loading_stop_tol": tol_loading, "bf16_loading_tol": low_tol,
            "plain_fp32": {"ms": ms_plain, "iters_mean": float(plain["iters"].double().mean()),
                           "max_loading_err": float(loading_angles(plain["P"], Pref).max()),
                           "status": int(plain["status"])}}
-    for name, warm in (("bf16", False), ("bf16_warm", True)):
+    for name, fmt, warm, ltol in (("bf16", "bf16", False, low_tol),
+                                  ("bf16_warm", "bf16", True, low_tol),
+                                  ("e4m3", "e4m3", False, 3 * low_tol)):
+        Q, ms_q = codes[fmt]
         T0, ms_ws = (timed(lambda: net.predict(Xd, Om, power=1)) if warm else (None, 0.0))
         kw = {"init": "given", "T0": T0} if warm else {}
-        low, ms_low = timed(lambda: gp.fit(Q, K, tol=low_tol, max_iter=max_iter, stop="loading",
+        low, ms_low = timed(lambda: gp.fit(Q, K, tol=ltol, max_iter=max_iter, stop="loading",
                                            check=False, **kw))
         fin, ms_fin = timed(lambda: gp.fit(Xd, K, tol=tol_loading, max_iter=max_iter,
                                            init="given", T0=low["T"], stop="loading",
                                            check=False))
         total = ms_q + ms_ws + ms_low + ms_fin
-        out[name] = {"ms": total, "speedup_vs_plain": ms_plain / total, "quantize_ms": ms_q,
+        out[name] = {"ms": total, "speedup_vs_plain": ms_plain / total, "low_loading_tol": ltol,
+                     "quantize_ms": ms_q,
                      "warm_start_ms": ms_ws, "bf16_fit_ms": ms_low, "fp32_refine_ms": ms_fin,
                      "bf16_iters_mean": float(low["iters"].double().mean()),
                      "refine_iters_mean": float(fin["iters"].double().mean()),

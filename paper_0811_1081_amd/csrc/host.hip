@@ -353,7 +353,11 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     const char *e_pipe = getenv("GSPCA_PASS_PIPE");
     f.plds = (e_lds && e_lds[0] == '1' && f.cpt >= 2 && f.NT <= 512) ? 1 : 0;
     f.skew = e_skew ? (e_skew[0] == '1' ? 1 : 0) : (fmt == kFmtBF16 ? 0 : 1);
-    f.pipe = (e_pipe && e_pipe[0] == '0') ? 0 : 1;
+    // Register double buffering pays for FP32 (318 vs 330 us per pass at 65536
+    // x 8192); with decoded codes the second buffer spills (BF16 218 vs 185
+    // us, FP8 210 vs 140 us with one buffer and two workgroups per CU).
+    const int pipe_default = (fmt == kFmtBF16 || fmt == kFmtFP8) ? 0 : 1;
+    f.pipe = e_pipe ? (e_pipe[0] == '0' ? 0 : 1) : pipe_default;
     if (f.plds) {
         f.cpt /= 2;
         f.NT *= 2;
