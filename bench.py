@@ -89,7 +89,7 @@ def reference_loadings(Xd, P0, K, steps=12, extra=32):
     return Q @ U[:, idx]
 
 
-def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
+def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5, refine_implicit=True):
     """Reduced-precision forms against plain FP32 at the same loading
     accuracy.  Every form ends with the same loading stop (|p_j - s p_(j-1)|
     < tol_loading) on the FP32 matrix, and every result is compared with the
@@ -98,7 +98,8 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
       bf16:       BF16 codes (one quantisation pass), BF16 fit (implicit
                   deflation) with the loading stop at low_tol -- about where
                   the BF16 representation error stops further progress --
-                  then FP32 refinement from the BF16 scores.
+                  then FP32 refinement from the BF16 scores (implicit
+                  deflation: X is read-only, no per-component rewrite).
       bf16_warm:  the same with warm starts for the BF16 fit: the whitened
                   sketch after one refinement step (the network's skip path).
       e4m3:       as bf16 with FP8 E4M3 codes (loading stop 3 x low_tol: the
@@ -141,7 +142,7 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5):
                                            check=False, **kw))
         fin, ms_fin = timed(lambda: gp.fit(Xd, K, tol=tol_loading, max_iter=max_iter,
                                            init="given", T0=low["T"], stop="loading",
-                                           check=False))
+                                           check=False, implicit=refine_implicit))
         total = ms_q + ms_ws + ms_low + ms_fin
         out[name] = {"ms": total, "speedup_vs_plain": ms_plain / total, "low_loading_tol": ltol,
                      "quantize_ms": ms_q,
