@@ -465,7 +465,7 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
     const float *__restrict__ scale, const double *__restrict__ p,
     const typename C::acc *__restrict__ t_in, double *__restrict__ t_out,
-    typename C::acc *__restrict__ q_part, LoopState *st, int skew)
+    double *__restrict__ tsq, typename C::acc *__restrict__ q_part, LoopState *st, int skew)
 {
     if (st->done)
         return;
@@ -486,6 +486,7 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
     const int64_t cnt = inter ? (g < NP ? (NP - 1 - g) / G + 1 : 0) : b1 - b0;
     E preg[PL ? 1 : CPT];
     E q[CPT];
+    double tacc = 0.0; // |t|^2 over this workgroup's rows (threads tid < PR)
     const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
 #pragma unroll
     for (int c = 0; c < CPT; ++c) {
@@ -567,7 +568,9 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
             }
             if (tid < PR) {
                 const int64_t m = b * PR + tid;
-                t_out[m] = (double)tb[tid];
+                const double tv = (double)tb[tid];
+                t_out[m] = tv;
+                tacc += tv * tv; // rows past M are zero
             }
         }
 #pragma unroll
@@ -632,6 +635,11 @@ __global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
                 v *= scale[j];
             q_part[g * N + j] = v;
         }
+    }
+    if (!FIRST && w == 0) {
+        const double tt = fwave_sum(tacc); // lanes >= PR hold 0
+        if (lane == 0)
+            tsq[g] = tt;
     }
 }
 
@@ -720,8 +728,11 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
 template <typename E>
 __global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t, int64_t M,
                                                    const E *__restrict__ V, int kd, int64_t rows,
+                                                   const double *__restrict__ tsq, int G,
                                                    double *__restrict__ cpart,
-                                                   double *__restrict__ d, LoopState *st)
+                                                   double *__restrict__ d, LoopState *st,
+                                                   double tol, int32_t limit, int replay,
+                                                   double tiny, int stop)
 {
     if (st->done)
         return;
@@ -751,9 +762,21 @@ __global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t,
     }
     if (!arrive_last(&st->counter[kCntDotM], &last))
         return;
-    reduce_partials(cpart, gridDim.x, kd, d, lds);
-    if (tid == 0)
-        st->counter[kCntDotM] = 0;
+    if (kd > 0)
+        reduce_partials(cpart, gridDim.x, kd, d, lds);
+    __shared__ double tt;
+    reduce_partials(tsq, G, 1, &tt, lds);
+    __syncthreads();
+    if (tid != 0)
+        return;
+    st->counter[kCntDotM] = 0;
+    // sigma = |t - V d| = sqrt(|t|^2 - |d|^2) (V orthonormal; d is at rounding
+    // level once t has been formed from a loading orthogonal to P_(k))
+    double dd = 0.0;
+    for (int i = 0; i < kd; ++i)
+        dd += d[i] * d[i];
+    const double s2 = tt - dd;
+    score_test(st, s2 > 0.0 ? sqrt(s2) : 0.0, tol, limit, replay, tiny, stop);
 }
 
 // Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
@@ -761,7 +784,9 @@ __global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t,
 //   A^T v_k = q' / sigma (q' = A^T t of the last pass), minus sigma p_k when A
 //   is the explicitly deflated residual (R <- R - sigma v_k p_k^T).
 template <typename E>
-__global__ __launch_bounds__(256) void k_comp_end(const E *__restrict__ t, int64_t M, int64_t N,
+__global__ __launch_bounds__(256) void k_comp_end(const double *__restrict__ td,
+                                                  const double *__restrict__ d, int kd,
+                                                  E *__restrict__ tE, int64_t M, int64_t N,
                                                   const double *__restrict__ p,
                                                   const double *__restrict__ qy, int k, int gs,
                                                   int explicit_defl, E *__restrict__ T,
@@ -772,8 +797,17 @@ __global__ __launch_bounds__(256) void k_comp_end(const E *__restrict__ t, int64
     const int deg = st->degenerate;
     const double s = st->sigma, pn = st->pnorm;
     const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (i < M)
-        T[i + (int64_t)k * M] = deg ? E(0) : (gs ? (E)((double)t[i] / s) : t[i]);
+    if (i < M) {
+        // the score after its Gram-Schmidt pass, t' = t - V_(k) d (Sec. 2.3)
+        double v = 0.0;
+        if (!deg) {
+            v = td[i];
+            for (int j = 0; j < kd; ++j)
+                v -= (double)T[i + (int64_t)j * M] * d[j];
+        }
+        tE[i] = (E)v;
+        T[i + (int64_t)k * M] = deg ? E(0) : (gs ? (E)(v / s) : (E)v);
+    }
     if (i < N) {
         const double pk = p[i] / pn;
         P[i + (int64_t)k * N] = (E)pk;
@@ -862,13 +896,13 @@ template <class C, bool FIRST>
 static void launch_pass(int cpt, int G, int NT, int plds, int skew, int pipe,
                         const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                         const float *scale, const double *p, const typename C::acc *t_in,
-                        double *t_out, typename C::acc *q_part, LoopState *st,
+                        double *t_out, double *tsq, typename C::acc *q_part, LoopState *st,
                         hipStream_t s)
 {
     const size_t lds = plds ? (size_t)cpt * NT * sizeof(typename C::acc) : 0;
 #define GSPCA_PASS(CP, PLV, PIV)                                                               \
     hipLaunchKernelGGL((k_pass<C, CP, FIRST, PLV, PIV>), dim3(G), dim3(NT), lds, s, A, N, NP,  \
-                       ldp, M, scale, p, t_in, t_out, q_part, st, skew)
+                       ldp, M, scale, p, t_in, t_out, tsq, q_part, st, skew)
 #define GSPCA_PASS_CPT(PLV, PIV)                                                               \
     switch (cpt) {                                                                             \
     case 1: GSPCA_PASS(1, PLV, PIV); break;                                                    \
@@ -890,25 +924,26 @@ template <int F>
 void Fused<F>::pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                     const unsigned char *A,
                     int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
-                    const double *p, const E *t_in, double *t_out, E *q_part, LoopState *st,
-                    hipStream_t s)
+                    const double *p, const E *t_in, double *t_out, double *tsq, E *q_part,
+                    LoopState *st, hipStream_t s)
 {
     using C = typename CodecOf<F>::type;
     if (first)
         launch_pass<C, true>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                             t_out, q_part, st, s);
+                             t_out, tsq, q_part, st, s);
     else
         launch_pass<C, false>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                              t_out, q_part, st, s);
+                              t_out, tsq, q_part, st, s);
 }
 
 template <int F>
-void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, double *cpart, double *d,
-                         LoopState *st, hipStream_t s)
+void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, const double *tsq,
+                         int G, double *cpart, double *d, LoopState *st, double tol,
+                         int32_t limit, int replay, double tiny, int stop, hipStream_t s)
 {
     const int64_t rows = score_rows(M);
     hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows)), dim3(256), 0, s, t, M, V, kd, rows,
-                       cpart, d, st);
+                       tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
 }
 
 template <int F>
@@ -922,12 +957,14 @@ void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int
 }
 
 template <int F>
-void Fused<F>::comp_end(const E *t, int64_t M, int64_t N, const double *p, const double *qy,
-                        int k, int gs, int explicit_defl, E *T, E *P, double *W, double *sigma,
-                        int32_t *iters, int32_t *start_col, LoopState *st, hipStream_t s)
+void Fused<F>::comp_end(const double *td, const double *d, int kd, E *tE, int64_t M, int64_t N,
+                        const double *p, const double *qy, int k, int gs, int explicit_defl,
+                        E *T, E *P, double *W, double *sigma, int32_t *iters,
+                        int32_t *start_col, LoopState *st, hipStream_t s)
 {
-    hipLaunchKernelGGL(k_comp_end<E>, dim3(fcdiv(M > N ? M : N, 256)), dim3(256), 0, s, t, M, N,
-                       p, qy, k, gs, explicit_defl, T, P, W, sigma, iters, start_col, st);
+    hipLaunchKernelGGL(k_comp_end<E>, dim3(fcdiv(M > N ? M : N, 256)), dim3(256), 0, s, td, d, kd,
+                       tE, M, N, p, qy, k, gs, explicit_defl, T, P, W, sigma, iters, start_col,
+                       st);
 }
 
 template struct Fused<kFmtF64>;

@@ -300,7 +300,7 @@ struct FusedPlan {
     int cpt, NT, G, nsplit_cn, nbM, nbN;
     int plds, skew, pipe; // pass-kernel variant: loading in LDS (1024 threads), panel-order
                           // skew, register double buffering (else two workgroups per CU)
-    size_t off_state, off_A, off_tE, off_td, off_qpart, off_d, off_c, off_qy, off_p,
+    size_t off_state, off_A, off_tE, off_td, off_tsq, off_qpart, off_d, off_c, off_qy, off_p,
         off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
 };
 
@@ -375,6 +375,7 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     f.off_A = o;      o = align_up(o + (quantised ? 0 : (size_t)f.NP * f.ldp * 16));
     f.off_tE = o;     o = align_up(o + len * esize);
     f.off_td = o;     o = align_up(o + len * 8);
+    f.off_tsq = o;    o = align_up(o + (size_t)f.G * 8);
     f.off_qpart = o;  o = align_up(o + (size_t)f.G * N * esize);
     f.off_d = o;      o = align_up(o + (size_t)(K + 1) * 8);
     f.off_c = o;      o = align_up(o + (size_t)(K + 1) * 8);
@@ -420,6 +421,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                                  : base + f.off_A;
     E *tE = reinterpret_cast<E *>(base + f.off_tE);
     double *td = reinterpret_cast<double *>(base + f.off_td);
+    double *tsq = reinterpret_cast<double *>(base + f.off_tsq);
     E *qpart = reinterpret_cast<E *>(base + f.off_qpart);
     double *dvec = reinterpret_cast<double *>(base + f.off_d);
     double *cvec = reinterpret_cast<double *>(base + f.off_c);
@@ -442,7 +444,6 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     const int implicit = (op->implicit_deflation || quantised) ? 1 : 0;
     const double tol = op->tol;
     const int stop = op->stop;
-    const int64_t len = f.NP * f.PR;
 
     std::vector<int32_t> rit;
     const bool replay = op->replay_iters != nullptr;
@@ -499,7 +500,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
         F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE,
-                td, qpart, st, s);
+                td, tsq, qpart, st, s);
         F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
         L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol, limit,
                     replay, tiny, stop, s);
@@ -514,15 +515,14 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 if (prof)
                     (void)hipEventRecord(ev[2 * i], s);
                 F::pass(0, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p,
-                        tE, td, qpart, st, s);
+                        tE, td, tsq, qpart, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[2 * i + 1], s);
-                // Gram-Schmidt coefficients of the score, d = V_(k)^T t (coalesced
-                // over the rows, kept out of the streaming pass)
-                if (kg > 0)
-                    F::score_dot(td, M, T, kg, cpart, dvec, st, s);
-                L::gs_apply(td, 1, len, M, td, T, M, kg, dvec, nullptr, nullptr, tE, sq, st, 1, tol,
-                            limit, replay, tiny, stop, s);
+                // score side: d = V_(k)^T t (coalesced over the rows, kept out of
+                // the streaming pass), sigma = |t - V d| and the stop test; t - V d
+                // itself is formed once, when the component ends
+                F::score_dot(td, M, T, kg, tsq, f.G, cpart, dvec, st, tol, limit, replay, tiny,
+                             stop, s);
                 F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);
                 L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol,
                             limit, replay, tiny, stop, s);
@@ -551,8 +551,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
             return GSPCA_EDEVICE;
         if (h.degenerate)
             L::degenerate_p(P, N, (int)k, p, st, s);
-        F::comp_end(tE, M, N, p, qy, (int)k, gs, implicit ? 0 : 1, T, P, gs ? W : nullptr, sig,
-                    rs->iters, rs->start_col, st, s);
+        F::comp_end(td, dvec, kg, tE, M, N, p, qy, (int)k, gs, implicit ? 0 : 1, T, P,
+                    gs ? W : nullptr, sig, rs->iters, rs->start_col, st, s);
         if (k + 1 < K) {
             if (!implicit) {
                 F::deflate(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, scale,

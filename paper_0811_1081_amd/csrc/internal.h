@@ -59,6 +59,42 @@ __device__ inline bool arrive_last(uint32_t *counter, int *flag_lds)
     return last;
 }
 
+// End of an iteration on the score side, by one thread: sigma = |t| after
+// the Gram-Schmidt pass, then the stop test -- the relative sigma test of the
+// host programs (Appendices 1, 3) when stop == 0, the loading change below
+// tol when stop == 1, or the replayed count -- and the loop state.
+__device__ inline void score_test(LoopState *st, double nrm, double tol, int32_t limit,
+                                  int replay, double tiny, int stop)
+{
+    const int it = st->iter + 1;
+    st->iter = it;
+    st->sigma = nrm;
+    if (!(nrm >= tiny)) {
+        st->degenerate = 1;
+        st->done = 1;
+        return;
+    }
+    const double mu = st->mu;
+    st->delta_prev = st->delta;
+    st->delta = stop == 1 ? st->dp : fabs(nrm - mu) / nrm;
+    if (replay) {
+        if (it >= limit)
+            st->done = 1;
+        return;
+    }
+    const bool pass_test = stop == 1 ? (st->dp < tol) : (fabs(mu - nrm) < tol * nrm);
+    if (pass_test) {
+        st->converged = 1;
+        st->done = 1;
+        return;
+    }
+    st->mu = nrm;
+    if (it >= limit) {
+        st->done = 1;
+        st->not_converged = 1;
+    }
+}
+
 // out[i] = sum over b < nb of part[b*k + i], i < k, by one whole workgroup:
 // column i gets S = blockDim / k threads (slice s sums partials b = s, s+S,
 // ...), and the S slice sums are added in slice order, so the result is the
@@ -171,16 +207,18 @@ struct Fused {
     static void pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                      const unsigned char *A,
                      int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
-                     const double *p, const E *t_in, double *t_out, E *q_part, LoopState *st,
-                     hipStream_t s);
-    static void score_dot(const double *t, int64_t M, const E *V, int kd, double *cpart,
-                          double *d, LoopState *st, hipStream_t s);
+                     const double *p, const E *t_in, double *t_out, double *tsq, E *q_part,
+                     LoopState *st, hipStream_t s);
+    static void score_dot(const double *t, int64_t M, const E *V, int kd, const double *tsq,
+                          int G, double *cpart, double *d, LoopState *st, double tol,
+                          int32_t limit, int replay, double tiny, int stop, hipStream_t s);
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);
-    static void comp_end(const E *t, int64_t M, int64_t N, const double *p, const double *qy,
-                         int k, int gs, int explicit_defl, E *T, E *P, double *W, double *sigma,
-                         int32_t *iters, int32_t *start_col, LoopState *st, hipStream_t s);
+    static void comp_end(const double *td, const double *d, int kd, E *tE, int64_t M, int64_t N,
+                         const double *p, const double *qy, int k, int gs, int explicit_defl,
+                         E *T, E *P, double *W, double *sigma, int32_t *iters,
+                         int32_t *start_col, LoopState *st, hipStream_t s);
 };
 
 // Batched path (batched.hip): one workgroup per problem, persistent queue.

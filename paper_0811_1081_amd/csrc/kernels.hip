@@ -491,33 +491,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
         }
         return;
     }
-    const int it = st->iter + 1;
-    st->iter = it;
-    st->sigma = nrm;
-    if (!(nrm >= tiny)) {
-        st->degenerate = 1;
-        st->done = 1;
-        return;
-    }
-    const double mu = st->mu;
-    st->delta_prev = st->delta;
-    st->delta = stop == 1 ? st->dp : fabs(nrm - mu) / nrm;
-    if (replay) {
-        if (it >= limit)
-            st->done = 1;
-        return;
-    }
-    const bool pass_test = stop == 1 ? (st->dp < tol) : (fabs(mu - nrm) < tol * nrm);
-    if (pass_test) {
-        st->converged = 1;
-        st->done = 1;
-        return;
-    }
-    st->mu = nrm;
-    if (it >= limit) {
-        st->done = 1;
-        st->not_converged = 1;
-    }
+    score_test(st, nrm, tol, limit, replay, tiny, stop);
 }
 
 // Degenerate component: the first unit vector whose Gram-Schmidt residual
