@@ -6,13 +6,13 @@
  * GSPCA_INIT_GIVEN accepts any start vector instead.  This header produces
  * one per component from a random sketch of X:
  *
- *   Y = X Omega                          M x r, r = 32, Omega N x r given
+ *   Y = X Omega                          M x r, r = 32 or 64, Omega N x r given
  *   Y^T Y = Q diag(g) Q^T                 FP64 Jacobi, g decreasing
  *   Z = sqrt(M) Y Q diag(g)^(-1/2)        whitened rows (unit-variance columns)
  *   [refinement, `power` times: Y = X (X^T Z / sqrt(M)), whiten again -- one
  *    step of subspace iteration (Halko, Martinsson & Tropp 2011, Alg. 4.4),
  *    which turns the sketch's directions into Ritz vectors of X X^T]
- *   o_m = z_m[:d3] + W3^T relu(W2^T relu(W1^T z_m + b1) + b2) + b3  (every row m)
+ *   o_m = z_m[:d3] + W3^T relu(W2^T relu(W1^T z_m[:32] + b1) + b2) + b3  (row m)
  *   T0[:, k] = (o_0k, ..., o_(M-1)k)      start of component k (sign free)
  *
  * The network is row-wise (the same map for every row and every matrix): the
@@ -45,7 +45,8 @@
 extern "C" {
 #endif
 
-#define GSPCA_WS_RANK 32 /* sketch width r */
+#define GSPCA_WS_RANK 32 /* network input width d0 (the first d0 whitened directions) */
+#define GSPCA_WS_RMAX 64 /* widest sketch: r is 32 or 64 */
 
 /* Network state.  Parameters are packed in one FP32 array in the order
  * W1, b1, W2, b2, W3, b3; W_l is row-major d_(l-1) x d_l (W[i*d_l + j] maps
@@ -73,23 +74,31 @@ size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t nin
                                  int64_t cols);
 
 /* Y = X Omega.  X FP32 column-major M x N (ldx >= M), Omega FP32 row-major
- * N x r (Omega[j*r + c]), Y FP32 row-major M x r.  r must be 32. */
+ * N x r (Omega[j*r + c]), Y FP32 row-major M x r.  r is 32 or 64. */
 gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Omega,
                           int32_t r, float *Y, void *stream);
 
-/* Refinement step: W = X^T Z / sqrt(M) (N x r, row-major, FP32 accumulation)
- * and Y = X W (M x r, row-major) for a whitened sketch Z (row-major M x r,
- * r = 32).  Whiten Y again to finish the step. */
+/* Device workspace of gspca_sketch_refine for an M x N matrix and width r;
+ * it also covers gspca_whiten_sketch of M rows (0 for invalid sizes). */
+size_t gspca_sketch_workspace_bytes(int64_t M, int64_t N, int32_t r);
+
+/* Refinement step: W = X^T Z / sqrt(M) (N x r, row-major; FP32 sums over row
+ * slices, added in slice order) and Y = X W (M x r, row-major) for a whitened
+ * sketch Z (row-major M x r, r = 32 or 64).  Whiten Y again to finish the
+ * step.  ws: gspca_sketch_workspace_bytes(M, N, r) bytes. */
 gspca_status gspca_sketch_refine(const float *X, int64_t ldx, int64_t M, int64_t N,
-                                 const float *Z, int32_t r, float *W, float *Y, void *stream);
+                                 const float *Z, int32_t r, float *W, float *Y, void *ws,
+                                 size_t ws_bytes, void *stream);
 
 /* Z = sqrt(M) Y Q diag(g)^(-1/2) with the eigenpairs of Y^T Y (FP64, cyclic
  * Jacobi) ordered by decreasing g, each eigenvector's largest entry made
- * positive.  Y, Z row-major M x r (r = 32; M >= r); gamma (nullable) receives
+ * positive.  Y, Z row-major M x r (r = 32 or 64; M >= r); gamma (nullable) receives
  * g (r doubles); *flag (nullable) is set to 1 on the device if some g is not
- * positive and finite (the matching columns of Z are then 0), else 0. */
+ * positive and finite (the matching columns of Z are then 0), else 0.  Y^T Y
+ * is summed in FP64 over row slices, added in slice order.  ws: at least
+ * gspca_sketch_workspace_bytes(M, 1, r) bytes. */
 gspca_status gspca_whiten_sketch(const float *Y, int64_t M, int32_t r, float *Z, double *gamma,
-                                 int32_t *flag, void *stream);
+                                 int32_t *flag, void *ws, size_t ws_bytes, void *stream);
 
 /* theta_bf16 <- bf16(theta). */
 gspca_status gspca_mlp_sync(const gspca_mlp *net, void *stream);
@@ -114,13 +123,14 @@ gspca_status gspca_mlp_loss_grad(const gspca_mlp *net, const float *Z, const flo
 gspca_status gspca_mlp_adam(gspca_mlp *net, float lr, float beta1, float beta2, float eps,
                             void *stream);
 
-/* Start vectors for one matrix: sketch, whiten, `power` refinement steps
- * (0..4), forward.  X FP32 column-major M x N, Omega as in gspca_sketch, T0
- * FP32 column-major M x d3 (ready for gspca_options.T0 with
- * init = GSPCA_INIT_GIVEN). */
+/* Start vectors for one matrix: sketch of width r (32 or 64), whiten, `power`
+ * refinement steps (0..4), forward on the first 32 whitened directions.  X
+ * FP32 column-major M x N (M >= r), Omega FP32 row-major N x r, T0 FP32
+ * column-major M x d3 (ready for gspca_options.T0 with
+ * init = GSPCA_INIT_GIVEN).  A width above K oversamples the subspace. */
 gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx, int64_t M,
-                              int64_t N, const float *Omega, int32_t power, float *T0, void *ws,
-                              size_t ws_bytes, void *stream);
+                              int64_t N, const float *Omega, int32_t r, int32_t power, float *T0,
+                              void *ws, size_t ws_bytes, void *stream);
 
 #ifdef __cplusplus
 }

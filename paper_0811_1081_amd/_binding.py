@@ -27,13 +27,15 @@ EXPORTS = (
     "gspca_quantize", "gspca_batched_workspace_bytes", "gspca_batched_prepare",
     "gspca_batched_launch", "gspca_batched_tune",
     # gspca_ws.h (learned warm start)
-    "gspca_mlp_param_count", "gspca_mlp_workspace_bytes", "gspca_sketch", "gspca_sketch_refine",
+    "gspca_mlp_param_count", "gspca_mlp_workspace_bytes", "gspca_sketch",
+    "gspca_sketch_workspace_bytes", "gspca_sketch_refine",
     "gspca_whiten_sketch",
     "gspca_mlp_sync", "gspca_mlp_forward", "gspca_mlp_loss_grad", "gspca_mlp_adam",
     "gspca_ws_predict",
 )
 
-WS_RANK = 32  # GSPCA_WS_RANK
+WS_RANK = 32  # GSPCA_WS_RANK (network input width)
+WS_RMAX = 64  # GSPCA_WS_RMAX (widest sketch)
 
 
 class Problem(ctypes.Structure):
@@ -138,15 +140,17 @@ def load() -> ctypes.CDLL:
         for name, res, args in (
                 ("gspca_mlp_param_count", i64, [i32, i32, i32, i32]),
                 ("gspca_mlp_workspace_bytes", sz, [mlp, i64, i32, i64]),
-                ("gspca_sketch_refine", ctypes.c_int, [vp, i64, i64, i64, vp, i32, vp, vp, vp]),
+                ("gspca_sketch_workspace_bytes", sz, [i64, i64, i32]),
+                ("gspca_sketch_refine", ctypes.c_int,
+                 [vp, i64, i64, i64, vp, i32, vp, vp, vp, sz, vp]),
                 ("gspca_sketch", ctypes.c_int, [vp, i64, i64, i64, vp, i32, vp, vp]),
-                ("gspca_whiten_sketch", ctypes.c_int, [vp, i64, i32, vp, vp, vp, vp]),
+                ("gspca_whiten_sketch", ctypes.c_int, [vp, i64, i32, vp, vp, vp, vp, sz, vp]),
                 ("gspca_mlp_sync", ctypes.c_int, [mlp, vp]),
                 ("gspca_mlp_forward", ctypes.c_int, [mlp, vp, i64, vp, vp, sz, vp]),
                 ("gspca_mlp_loss_grad", ctypes.c_int, [mlp, vp, vp, i32, i64, vp, vp, sz, vp]),
                 ("gspca_mlp_adam", ctypes.c_int, [mlp, flt, flt, flt, flt, vp]),
                 ("gspca_ws_predict", ctypes.c_int,
-                 [mlp, vp, i64, i64, i64, vp, i32, vp, vp, sz, vp])):
+                 [mlp, vp, i64, i64, i64, vp, i32, i32, vp, vp, sz, vp])):
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args

@@ -232,83 +232,225 @@ __global__ __launch_bounds__(256) void k_to_bf16(const float *__restrict__ x,
 // ---------------------------------------------------------------------------
 // Sketch and whitening.
 
-// Y = X Omega: thread per row, R accumulators (X column-major, Omega
-// row-major N x R, read uniformly by the wave).
+// Y = X Omega (M x R, row-major) for column-major X and row-major N x R
+// Omega.  Workgroup b owns rows [64b, 64b + 64): 32-column tiles of X (read
+// along the rows) and the matching 32 rows of Omega are staged in LDS, and
+// each of the 256 threads accumulates a 4 x (R/16) block of Y in FP32.
 template <int R>
 __global__ __launch_bounds__(256) void k_sketch(const float *__restrict__ X, int64_t ldx,
                                                 int64_t M, int64_t N, const float *__restrict__ Om,
                                                 float *__restrict__ Y)
 {
-    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (m >= M)
-        return;
-    float acc[R];
+    constexpr int RB = R / 16;
+    __shared__ float xs[32][65];
+    __shared__ float os[32][R + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4; // rows 4tx..4tx+3, sketch columns RB*ty..
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    float acc[4][RB];
 #pragma unroll
-    for (int c = 0; c < R; ++c)
-        acc[c] = 0.0f;
-    for (int64_t j = 0; j < N; ++j) {
-        const float x = X[m + j * ldx];
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c = 0; c < R; ++c)
-            acc[c] += x * Om[j * R + c];
+        for (int b = 0; b < RB; ++b)
+            acc[a][b] = 0.0f;
+    for (int64_t j0 = 0; j0 < N; j0 += 32) {
+        __syncthreads();
+        for (int e = tid; e < 32 * 64; e += 256) { // X tile, rows fastest
+            const int i = e & 63, c = e >> 6;
+            const int64_t m = m0 + i, j = j0 + c;
+            xs[c][i] = (m < M && j < N) ? X[m + j * ldx] : 0.0f;
+        }
+        for (int e = tid; e < 32 * R; e += 256) { // Omega tile, sketch columns fastest
+            const int c = e / R, col = e % R;
+            const int64_t j = j0 + c;
+            os[c][col] = j < N ? Om[j * R + col] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int c = 0; c < 32; ++c) {
+            float xv[4], ov[RB];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                xv[a] = xs[c][4 * tx + a];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                ov[b] = os[c][RB * ty + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[a][b] += xv[a] * ov[b];
+        }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c)
-        Y[m * R + c] = acc[c];
+    for (int a = 0; a < 4; ++a) {
+        const int64_t m = m0 + 4 * tx + a;
+        if (m < M)
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                Y[m * R + RB * ty + b] = acc[a][b];
+    }
 }
 
-// W = s X^T Z (N x R, row-major) for a row-major M x R sketch Z: one wave per
-// column of X, lanes along the rows (coalesced), R accumulators per lane,
-// then a butterfly sum per accumulator.
+// W = s X^T Z (N x R, row-major) for a row-major M x R sketch Z, as partial
+// sums over row slices.  Workgroup (b, y) owns columns [64b, 64b + 64) of X
+// over row slice y: 32-row tiles of X (64 columns, read along the rows) and
+// of Z (R columns) are staged in LDS, and each of the 256 threads accumulates
+// a 4 x (R/16) block in FP32; slice y's block goes to W + y*N*R.
 template <int R>
 __global__ __launch_bounds__(256) void k_sketch_t(const float *__restrict__ X, int64_t ldx,
                                                   int64_t M, int64_t N,
                                                   const float *__restrict__ Z, float s,
-                                                  float *__restrict__ W)
+                                                  int64_t rows, float *__restrict__ W)
 {
-    typedef float f4 __attribute__((ext_vector_type(4)));
-    const int lane = threadIdx.x & 63;
-    const int64_t j = (int64_t)blockIdx.x * 4 + (threadIdx.x >> 6);
-    if (j >= N)
-        return;
-    float acc[R];
+    constexpr int RB = R / 16; // sketch columns per thread
+    __shared__ float xs[32][65];
+    __shared__ float zs[32][R + 1];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4; // X columns 4tx..4tx+3, sketch columns RB*ty..
+    const int64_t j0 = (int64_t)blockIdx.x * 64;
+    float acc[4][RB];
 #pragma unroll
-    for (int c = 0; c < R; ++c)
-        acc[c] = 0.0f;
-    const float *xc = X + j * ldx;
-    for (int64_t m = lane; m < M; m += 64) {
-        const float x = xc[m];
-        const f4 *zr = reinterpret_cast<const f4 *>(Z + m * R);
+    for (int a = 0; a < 4; ++a)
 #pragma unroll
-        for (int c4 = 0; c4 < R / 4; ++c4) {
-            const f4 z = zr[c4];
-            acc[4 * c4 + 0] += x * z[0];
-            acc[4 * c4 + 1] += x * z[1];
-            acc[4 * c4 + 2] += x * z[2];
-            acc[4 * c4 + 3] += x * z[3];
+        for (int b = 0; b < RB; ++b)
+            acc[a][b] = 0.0f;
+    // row slice blockIdx.y: rows [y*rows, y*rows + rows); W gets slice y's partial
+    const int64_t rb = (int64_t)blockIdx.y * rows;
+    const int64_t re = M < rb + rows ? M : rb + rows;
+    W += (int64_t)blockIdx.y * N * R;
+    for (int64_t r0 = rb; r0 < re; r0 += 32) {
+        __syncthreads();
+        for (int e = tid; e < 32 * 64; e += 256) { // X tile, rows fastest
+            const int i = e & 31, c = e >> 5;
+            const int64_t m = r0 + i, j = j0 + c;
+            xs[i][c] = (m < re && j < N) ? X[m + j * ldx] : 0.0f;
+        }
+        for (int e = tid; e < 32 * R; e += 256) { // Z tile, sketch columns fastest
+            const int i = e / R, c = e % R;
+            const int64_t m = r0 + i;
+            zs[i][c] = m < re ? Z[m * R + c] : 0.0f;
+        }
+        __syncthreads();
+#pragma unroll 4
+        for (int i = 0; i < 32; ++i) {
+            float xv[4], zv[RB];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+                xv[a] = xs[i][4 * tx + a];
+#pragma unroll
+            for (int b = 0; b < RB; ++b)
+                zv[b] = zs[i][RB * ty + b];
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[a][b] += xv[a] * zv[b];
         }
     }
 #pragma unroll
-    for (int c = 0; c < R; ++c) {
-        float v = acc[c];
+    for (int a = 0; a < 4; ++a) {
+        const int64_t j = j0 + 4 * tx + a;
+        if (j < N)
 #pragma unroll
-        for (int o = 32; o > 0; o >>= 1)
-            v += __shfl_xor(v, o, 64);
-        if (lane == c)
-            W[j * R + c] = v * s;
+            for (int b = 0; b < RB; ++b)
+                W[j * R + RB * ty + b] = acc[a][b] * s;
     }
 }
 
-// G = Y^T Y in FP64 (thread per entry), parallel cyclic Jacobi (round-robin
-// pairing: R/2 disjoint rotations per round, R-1 rounds per sweep; rotation
-// of Golub & Van Loan's symmetric Schur step) until the off-diagonal mass is
-// below 1e-28 of |G|_F^2, then Z = sqrt(M) Y Q diag(g)^(-1/2) with the
-// eigenpairs by decreasing g and each eigenvector's largest entry positive.
+// G_y = Y[rows of slice y]^T Y[rows of slice y] in FP64: 64-row tiles staged in
+// LDS, each of the 256 threads owns an (R/16) x (R/16) block of G_y.
 template <int R>
-__global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, int64_t M,
-                                                 float *__restrict__ Z, double *__restrict__ gout,
-                                                 int32_t *__restrict__ flag)
+__global__ __launch_bounds__(256) void k_gram(const float *__restrict__ Y, int64_t M,
+                                              int64_t rows, double *__restrict__ part)
 {
+    constexpr int TB = R / 16;
+    __shared__ float ys[64][R + 1];
+    const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
+    const int64_t rb = (int64_t)blockIdx.x * rows;
+    const int64_t re = M < rb + rows ? M : rb + rows;
+    double acc[TB][TB];
+#pragma unroll
+    for (int a = 0; a < TB; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+            acc[a][b] = 0.0;
+    for (int64_t r0 = rb; r0 < re; r0 += 64) {
+        __syncthreads();
+        for (int e = tid; e < 64 * R; e += 256) {
+            const int i = e / R, c = e % R;
+            const int64_t m = r0 + i;
+            ys[i][c] = m < re ? Y[m * R + c] : 0.0f;
+        }
+        __syncthreads();
+        for (int i = 0; i < 64; ++i) {
+            double ya[TB], yb[TB];
+#pragma unroll
+            for (int a = 0; a < TB; ++a)
+                ya[a] = (double)ys[i][TB * ta + a];
+#pragma unroll
+            for (int b = 0; b < TB; ++b)
+                yb[b] = (double)ys[i][TB * tb + b];
+#pragma unroll
+            for (int a = 0; a < TB; ++a)
+#pragma unroll
+                for (int b = 0; b < TB; ++b)
+                    acc[a][b] += ya[a] * yb[b];
+        }
+    }
+    double *g = part + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+    for (int a = 0; a < TB; ++a)
+#pragma unroll
+        for (int b = 0; b < TB; ++b)
+            g[(TB * ta + a) * R + TB * tb + b] = acc[a][b];
+}
+
+// Z = Y QS (row-major, FP64 sums): 64-row tiles, QS (R x R) staged in LDS.
+template <int R>
+__global__ __launch_bounds__(256) void k_whiten_apply(const float *__restrict__ Y, int64_t M,
+                                                      const double *__restrict__ QS,
+                                                      float *__restrict__ Z)
+{
+    __shared__ double qs[R][R + 1];
+    __shared__ float ys[64][R + 1];
+    const int tid = threadIdx.x;
+    const int64_t m0 = (int64_t)blockIdx.x * 64;
+    for (int e = tid; e < R * R; e += 256)
+        qs[e / R][e % R] = QS[e];
+    for (int e = tid; e < 64 * R; e += 256) {
+        const int i = e / R, c = e % R;
+        const int64_t m = m0 + i;
+        ys[i][c] = m < M ? Y[m * R + c] : 0.0f;
+    }
+    __syncthreads();
+    for (int e = tid; e < 64 * R; e += 256) {
+        const int i = e / R, b = e % R;
+        const int64_t m = m0 + i;
+        if (m >= M)
+            continue;
+        double z = 0.0;
+        for (int r = 0; r < R; ++r)
+            z += (double)ys[i][r] * qs[r][b];
+        Z[m * R + b] = (float)z;
+    }
+}
+
+// Eigen-decomposition of the sketch's Gram matrix by one workgroup of 1024
+// threads (R = 32 or 64): G = sum of the nslice partials from k_gram (fixed
+// order, FP64), parallel cyclic Jacobi (round-robin pairing: R/2 disjoint
+// rotations per round, R-1 rounds per sweep; rotation of Golub & Van Loan's
+// symmetric Schur step) until the off-diagonal mass is below 1e-28 of
+// |G|_F^2; eigenpairs by decreasing g, each eigenvector's largest entry made
+// positive.  Writes QS = sqrt(M) Q[:, perm] diag(g)^(-1/2) (R x R, row-major;
+// zero columns where g is not positive and finite), g, and the flag.
+template <int R>
+__global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ part, int nslice,
+                                                     int64_t M, double *__restrict__ QS,
+                                                     double *__restrict__ gout,
+                                                     int32_t *__restrict__ flag)
+{
+    constexpr int NT = 1024, EPT = R * R / NT; // Gram entries per thread (1 or 4)
     __shared__ double G[R][R + 1];
     __shared__ double Q[R][R + 1];
     __shared__ double cs[R / 2], sn[R / 2];
@@ -317,15 +459,19 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
     __shared__ int perm[R];
     __shared__ double scale[R];
     __shared__ double offsum[2];
-    const int a = threadIdx.x / R, b = threadIdx.x % R;
-    double s = 0.0;
-    for (int64_t m = 0; m < M; ++m)
-        s += (double)Y[m * R + a] * (double)Y[m * R + b];
-    G[a][b] = s;
-    Q[a][b] = a == b ? 1.0 : 0.0;
+    const int tid = threadIdx.x;
+#pragma unroll
+    for (int e = 0; e < EPT; ++e) {
+        const int idx = tid + e * NT, a = idx / R, b = idx % R;
+        double acc = 0.0;
+        for (int y = 0; y < nslice; ++y)
+            acc += part[(int64_t)y * R * R + idx];
+        G[a][b] = acc;
+        Q[a][b] = a == b ? 1.0 : 0.0;
+    }
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
-        if (threadIdx.x == 0) {
+        if (tid == 0) {
             double off = 0.0, fro = 0.0;
             for (int i = 0; i < R; ++i)
                 for (int j = 0; j < R; ++j) {
@@ -340,9 +486,9 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
         if (!(offsum[0] > 1e-28 * offsum[1]))
             break;
         for (int round = 0; round < R - 1; ++round) {
-            if (threadIdx.x < R / 2) {
+            if (tid < R / 2) {
                 // position 0 holds index 0; positions 1..R-1 rotate
-                const int i = threadIdx.x;
+                const int i = tid;
                 const int pos_a = i, pos_b = R - 1 - i;
                 int p = pos_a == 0 ? 0 : 1 + (pos_a - 1 + round) % (R - 1);
                 int q = 1 + (pos_b - 1 + round) % (R - 1);
@@ -366,7 +512,8 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
                 sn[i] = sv;
             }
             __syncthreads();
-            if (b < R / 2) { // G <- G J, Q <- Q J (thread: row a, pair b)
+            for (int e = tid; e < R * (R / 2); e += NT) { // G <- G J, Q <- Q J (row a, pair b)
+                const int a = e / (R / 2), b = e % (R / 2);
                 const int p = pa[b], q = pb[b];
                 const double c = cs[b], sv = sn[b];
                 const double gp = G[a][p], gq = G[a][q];
@@ -377,7 +524,8 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
                 Q[a][q] = sv * qp + c * qq;
             }
             __syncthreads();
-            if (b < R / 2) { // G <- J^T G (thread: column a, pair b)
+            for (int e = tid; e < R * (R / 2); e += NT) { // G <- J^T G (column a, pair b)
+                const int a = e / (R / 2), b = e % (R / 2);
                 const int p = pa[b], q = pb[b];
                 const double c = cs[b], sv = sn[b];
                 const double gp = G[p][a], gq = G[q][a];
@@ -387,7 +535,7 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
             __syncthreads();
         }
     }
-    if (threadIdx.x == 0) {
+    if (tid == 0) {
         for (int i = 0; i < R; ++i) {
             eig[i] = G[i][i];
             perm[i] = i;
@@ -420,13 +568,9 @@ __global__ __launch_bounds__(R *R) void k_whiten(const float *__restrict__ Y, in
             *flag = bad;
     }
     __syncthreads();
-    // Z = Y Q[:, perm] diag(scale): thread (row offset a, output column b)
-    const int c = perm[b];
-    for (int64_t m = a; m < M; m += R) {
-        double z = 0.0;
-        for (int r = 0; r < R; ++r)
-            z += (double)Y[m * R + r] * Q[r][c];
-        Z[m * R + b] = (float)(z * scale[b]);
+    for (int e = tid; e < R * R; e += NT) {
+        const int r = e / R, b = e % R;
+        QS[e] = Q[r][perm[b]] * scale[b];
     }
 }
 
@@ -464,8 +608,35 @@ bool valid_net(const gspca_mlp *n)
 // splits.
 constexpr int kMaxSplit = 64;
 
+// Row slices of the refinement's X^T Z (about 2048 workgroups) and of the Gram
+// matrix (at most 256 workgroups), and the workspace they use.
+struct SketchPlan {
+    int64_t st, rows_t, sg, rows_g;
+    size_t off_gpart, off_qs, off_wpart, total; // whitening needs off_wpart bytes
+};
+SketchPlan sketch_plan(int64_t M, int64_t N, int r)
+{
+    SketchPlan P{};
+    const int64_t cb = (N + 63) / 64;
+    P.st = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 2048 / cb));
+    P.rows_t = ((M + P.st - 1) / P.st + 31) / 32 * 32;
+    P.st = (M + P.rows_t - 1) / P.rows_t;
+    P.sg = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 256));
+    P.rows_g = ((M + P.sg - 1) / P.sg + 63) / 64 * 64;
+    P.sg = (M + P.rows_g - 1) / P.rows_g;
+    size_t o = 0; // Gram part first: its offsets do not depend on N
+    P.off_gpart = o;
+    o = align256(o + (size_t)P.sg * r * r * 8);
+    P.off_qs = o;
+    o = align256(o + (size_t)r * r * 8);
+    P.off_wpart = o;
+    o = align256(o + (size_t)P.st * N * r * 4);
+    P.total = o;
+    return P;
+}
+
 struct Layout {
-    size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, W, total;
+    size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, W, SK, total;
 };
 Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst, int64_t cols)
 {
@@ -485,9 +656,10 @@ Layout layout(const gspca_mlp *n, int64_t rows, int32_t ninst, int64_t cols)
     put(L.G1, (size_t)rows * n->d1 * 2);
     put(L.lossp, (size_t)std::max<int32_t>(ninst, 1) * n->d3 * 8);
     put(L.part, (size_t)kMaxSplit * dmax * dmax * 4);
-    put(L.Y, (size_t)rows * GSPCA_WS_RANK * 4);
-    put(L.Z, (size_t)rows * GSPCA_WS_RANK * 4);
-    put(L.W, (size_t)std::max<int64_t>(cols, 1) * GSPCA_WS_RANK * 4);
+    put(L.Y, (size_t)rows * GSPCA_WS_RMAX * 4);
+    put(L.Z, (size_t)rows * GSPCA_WS_RMAX * 4);
+    put(L.W, (size_t)std::max<int64_t>(cols, 1) * GSPCA_WS_RMAX * 4);
+    put(L.SK, cols > 0 ? sketch_plan(rows, cols, GSPCA_WS_RMAX).total : 0);
     L.total = o;
     return L;
 }
@@ -530,25 +702,72 @@ void colsum(const T *G, int64_t rows, int64_t N, float *out, float *part, hipStr
 
 // Forward over `rows` rows: H1, H2 (bf16, row-major) and the output with
 // strides (o_r, o_c).
-void forward(const gspca_mlp *n, const float *Z, int64_t rows, __bf16 *H1, __bf16 *H2, float *O,
-             int64_t o_r, int64_t o_c, hipStream_t s)
+void forward(const gspca_mlp *n, const float *Z, int64_t zs, int64_t rows, __bf16 *H1,
+             __bf16 *H2, float *O, int64_t o_r, int64_t o_c, hipStream_t s)
 {
     const Offs of = param_offsets(n->d0, n->d1, n->d2, n->d3);
     const __bf16 *wb = reinterpret_cast<const __bf16 *>(n->theta_bf16);
     const float *th = n->theta;
-    gemm_launch<float, __bf16>(Z, n->d0, 1, wb + of.W1, n->d1, 1, rows, n->d1, n->d0, th + of.b1,
+    // input row m = the first d0 entries of Z's row m (row stride zs >= d0)
+    gemm_launch<float, __bf16>(Z, zs, 1, wb + of.W1, n->d1, 1, rows, n->d1, n->d0, th + of.b1,
                                1, nullptr, 0, nullptr, H1, n->d1, 1, nullptr, s);
     gemm_launch<__bf16, __bf16>(H1, n->d1, 1, wb + of.W2, n->d2, 1, rows, n->d2, n->d1,
                                 th + of.b2, 1, nullptr, 0, nullptr, H2, n->d2, 1, nullptr, s);
     // output = z[:d3] + W3^T h2 + b3: the whitened directions plus a learned correction
     gemm_launch<__bf16, __bf16>(H2, n->d2, 1, wb + of.W3, n->d3, 1, rows, n->d3, n->d2,
                                 th + of.b3, 0, nullptr, 0, O, nullptr, o_r, o_c, nullptr, s, Z,
-                                n->d0);
+                                zs);
 }
 
 gspca_status launched()
 {
     return hipGetLastError() == hipSuccess ? GSPCA_OK : GSPCA_EDEVICE;
+}
+
+bool valid_rank(int32_t r) { return r == 32 || r == GSPCA_WS_RMAX; }
+
+void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
+                   float *Y, hipStream_t s)
+{
+    if (r == 32)
+        hipLaunchKernelGGL(k_sketch<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N, Om, Y);
+    else
+        hipLaunchKernelGGL(k_sketch<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N, Om, Y);
+}
+
+void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Z, int r,
+                     float *W, unsigned char *ws, hipStream_t s)
+{
+    const SketchPlan P = sketch_plan(M, N, r);
+    const float sc = (float)(1.0 / sqrt((double)M));
+    float *dst = P.st == 1 ? W : reinterpret_cast<float *>(ws + P.off_wpart);
+    const dim3 g(ucdiv(N, 64), (unsigned)P.st);
+    if (r == 32)
+        hipLaunchKernelGGL(k_sketch_t<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t, dst);
+    else
+        hipLaunchKernelGGL(k_sketch_t<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t, dst);
+    if (P.st > 1) // slice partials added in slice order
+        hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(N * r, 256)), dim3(256), 0, s, dst,
+                           (int)P.st, N, (int64_t)r, W, (int64_t)r, (int64_t)1);
+}
+
+void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_t *flag,
+                   unsigned char *ws, hipStream_t s)
+{
+    const SketchPlan P = sketch_plan(M, 1, r);
+    double *gp = reinterpret_cast<double *>(ws + P.off_gpart);
+    double *qs = reinterpret_cast<double *>(ws + P.off_qs);
+    if (r == 32) {
+        hipLaunchKernelGGL(k_gram<32>, dim3((unsigned)P.sg), dim3(256), 0, s, Y, M, P.rows_g, gp);
+        hipLaunchKernelGGL(k_whiten_eig<32>, dim3(1), dim3(1024), 0, s, gp, (int)P.sg, M, qs, g,
+                           flag);
+        hipLaunchKernelGGL(k_whiten_apply<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, Y, M, qs, Z);
+    } else {
+        hipLaunchKernelGGL(k_gram<64>, dim3((unsigned)P.sg), dim3(256), 0, s, Y, M, P.rows_g, gp);
+        hipLaunchKernelGGL(k_whiten_eig<64>, dim3(1), dim3(1024), 0, s, gp, (int)P.sg, M, qs, g,
+                           flag);
+        hipLaunchKernelGGL(k_whiten_apply<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, Y, M, qs, Z);
+    }
 }
 
 } // namespace
@@ -576,35 +795,43 @@ size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t nin
 gspca_status gspca_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Omega,
                           int32_t r, float *Y, void *stream)
 {
-    if (!X || !Omega || !Y || r != GSPCA_WS_RANK || M < 1 || N < 1 || ldx < M)
+    if (!X || !Omega || !Y || !valid_rank(r) || M < 1 || N < 1 || ldx < M)
         return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
-                       N, Omega, Y);
+    launch_sketch(X, ldx, M, N, Omega, r, Y, s);
     return launched();
 }
 
-gspca_status gspca_sketch_refine(const float *X, int64_t ldx, int64_t M, int64_t N,
-                                 const float *Z, int32_t r, float *W, float *Y, void *stream)
+size_t gspca_sketch_workspace_bytes(int64_t M, int64_t N, int32_t r)
 {
-    if (!X || !Z || !W || !Y || r != GSPCA_WS_RANK || M < 1 || N < 1 || ldx < M)
+    if (M < 1 || N < 1 || !valid_rank(r))
+        return 0;
+    return sketch_plan(M, N, r).total;
+}
+
+gspca_status gspca_sketch_refine(const float *X, int64_t ldx, int64_t M, int64_t N,
+                                 const float *Z, int32_t r, float *W, float *Y, void *ws,
+                                 size_t ws_bytes, void *stream)
+{
+    if (!X || !Z || !W || !Y || !valid_rank(r) || M < 1 || N < 1 || ldx < M || !ws)
         return GSPCA_EINVAL;
+    if (ws_bytes < sketch_plan(M, N, r).total)
+        return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_sketch_t<GSPCA_WS_RANK>, dim3(ucdiv(N, 4)), dim3(256), 0, s, X, ldx, M, N,
-                       Z, (float)(1.0 / sqrt((double)M)), W);
-    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
-                       N, W, Y);
+    launch_sketch_t(X, ldx, M, N, Z, r, W, static_cast<unsigned char *>(ws), s);
+    launch_sketch(X, ldx, M, N, W, r, Y, s);
     return launched();
 }
 
 gspca_status gspca_whiten_sketch(const float *Y, int64_t M, int32_t r, float *Z, double *gamma,
-                                 int32_t *flag, void *stream)
+                                 int32_t *flag, void *ws, size_t ws_bytes, void *stream)
 {
-    if (!Y || !Z || r != GSPCA_WS_RANK || M < r)
+    if (!Y || !Z || !valid_rank(r) || M < r || !ws)
         return GSPCA_EINVAL;
+    if (ws_bytes < sketch_plan(M, 1, r).off_wpart)
+        return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1), dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0,
-                       s, Y, M, Z, gamma, flag);
+    launch_whiten(Y, M, r, Z, gamma, flag, static_cast<unsigned char *>(ws), s);
     return launched();
 }
 
@@ -629,7 +856,7 @@ gspca_status gspca_mlp_forward(const gspca_mlp *net, const float *Z, int64_t row
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
     unsigned char *b = static_cast<unsigned char *>(ws);
-    forward(net, Z, rows, reinterpret_cast<__bf16 *>(b + L.H1),
+    forward(net, Z, net->d0, rows, reinterpret_cast<__bf16 *>(b + L.H1),
             reinterpret_cast<__bf16 *>(b + L.H2), O, 1, rows, s);
     return launched();
 }
@@ -659,7 +886,7 @@ gspca_status gspca_mlp_loss_grad(const gspca_mlp *net, const float *Z, const flo
     const __bf16 *wb = reinterpret_cast<const __bf16 *>(net->theta_bf16);
     float *g = net->grad;
 
-    forward(net, Z, rows, H1, H2, O, d3, 1, s);
+    forward(net, Z, d0, rows, H1, H2, O, d3, 1, s);
     const double inv = 1.0 / (double)ninst;
     hipLaunchKernelGGL(k_cos2, dim3(d3, ninst), dim3(256), 0, s, O, V, rows_per_inst, d3, inv, dO,
                        lossp);
@@ -703,11 +930,11 @@ gspca_status gspca_mlp_adam(gspca_mlp *net, float lr, float beta1, float beta2, 
 }
 
 gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx, int64_t M,
-                              int64_t N, const float *Omega, int32_t power, float *T0, void *ws,
-                              size_t ws_bytes, void *stream)
+                              int64_t N, const float *Omega, int32_t r, int32_t power, float *T0,
+                              void *ws, size_t ws_bytes, void *stream)
 {
-    if (!valid_net(net) || !X || !Omega || !T0 || M < GSPCA_WS_RANK || N < 1 || ldx < M || !ws ||
-        power < 0 || power > 4)
+    if (!valid_net(net) || !X || !Omega || !T0 || !valid_rank(r) || M < r || N < 1 || ldx < M ||
+        !ws || power < 0 || power > 4)
         return GSPCA_EINVAL;
     const Layout L = layout(net, M, 1, N);
     if (ws_bytes < L.total)
@@ -717,20 +944,16 @@ gspca_status gspca_ws_predict(const gspca_mlp *net, const float *X, int64_t ldx,
     float *Y = reinterpret_cast<float *>(b + L.Y);
     float *Z = reinterpret_cast<float *>(b + L.Z);
     float *W = reinterpret_cast<float *>(b + L.W);
-    hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx, M,
-                       N, Omega, Y);
-    hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1), dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0,
-                       s, Y, M, Z, nullptr, nullptr);
+    unsigned char *sk = b + L.SK;
+    launch_sketch(X, ldx, M, N, Omega, r, Y, s);
+    launch_whiten(Y, M, r, Z, nullptr, nullptr, sk, s);
     for (int it = 0; it < power; ++it) {
-        hipLaunchKernelGGL(k_sketch_t<GSPCA_WS_RANK>, dim3(ucdiv(N, 4)), dim3(256), 0, s, X, ldx,
-                           M, N, Z, (float)(1.0 / sqrt((double)M)), W);
-        hipLaunchKernelGGL(k_sketch<GSPCA_WS_RANK>, dim3(ucdiv(M, 256)), dim3(256), 0, s, X, ldx,
-                           M, N, W, Y);
-        hipLaunchKernelGGL(k_whiten<GSPCA_WS_RANK>, dim3(1),
-                           dim3(GSPCA_WS_RANK * GSPCA_WS_RANK), 0, s, Y, M, Z, nullptr, nullptr);
+        launch_sketch_t(X, ldx, M, N, Z, r, W, sk, s);
+        launch_sketch(X, ldx, M, N, W, r, Y, s);
+        launch_whiten(Y, M, r, Z, nullptr, nullptr, sk, s);
     }
-    forward(net, Z, M, reinterpret_cast<__bf16 *>(b + L.H1), reinterpret_cast<__bf16 *>(b + L.H2),
-            T0, 1, M, s);
+    forward(net, Z, r, M, reinterpret_cast<__bf16 *>(b + L.H1),
+            reinterpret_cast<__bf16 *>(b + L.H2), T0, 1, M, s);
     return launched();
 }
 

@@ -42,18 +42,22 @@ def _aligned(nbytes, dev):
     return buf, buf.data_ptr() + ((-buf.data_ptr()) % 256)
 
 
+RANKS = (32, _b.WS_RMAX)  # sketch widths
+
+
 def sketch(X, Omega, stream=None):
-    """Y = X Omega (M x 32, row-major float32).  X column-major float32 on the
-    device, Omega (N x 32) float32 on the device (row-major)."""
+    """Y = X Omega (M x r, row-major float32).  X column-major float32 on the
+    device, Omega (N x r) float32 on the device (row-major), r = 32 or 64."""
     import torch
     M, N = X.shape
     if X.dtype != torch.float32 or X.stride(0) != 1:
         raise ValueError("X must be column-major float32")
     Om = Omega.contiguous()
-    if tuple(Om.shape) != (N, RANK) or Om.dtype != torch.float32:
-        raise ValueError("Omega must be (N, %d) float32" % RANK)
-    Y = torch.empty((M, RANK), dtype=torch.float32, device=X.device)
-    _check(_b.load().gspca_sketch(X.data_ptr(), X.stride(1), M, N, Om.data_ptr(), RANK,
+    r = Om.shape[1] if Om.dim() == 2 else -1
+    if Om.dim() != 2 or Om.shape[0] != N or r not in RANKS or Om.dtype != torch.float32:
+        raise ValueError("Omega must be (N, r) float32 with r in %s" % (RANKS,))
+    Y = torch.empty((M, r), dtype=torch.float32, device=X.device)
+    _check(_b.load().gspca_sketch(X.data_ptr(), X.stride(1), M, N, Om.data_ptr(), r,
                                   Y.data_ptr(), _stream(stream, X.device)))
     return Y
 
@@ -66,12 +70,16 @@ def sketch_refine(X, Z, stream=None):
     if X.dtype != torch.float32 or X.stride(0) != 1:
         raise ValueError("X must be column-major float32")
     Z = Z.contiguous()
-    if tuple(Z.shape) != (M, RANK) or Z.dtype != torch.float32:
-        raise ValueError("Z must be (M, %d) float32" % RANK)
-    W = torch.empty((N, RANK), dtype=torch.float32, device=X.device)
-    Y = torch.empty((M, RANK), dtype=torch.float32, device=X.device)
-    _check(_b.load().gspca_sketch_refine(X.data_ptr(), X.stride(1), M, N, Z.data_ptr(), RANK,
-                                         W.data_ptr(), Y.data_ptr(), _stream(stream, X.device)))
+    r = Z.shape[1] if Z.dim() == 2 else -1
+    if Z.dim() != 2 or Z.shape[0] != M or r not in RANKS or Z.dtype != torch.float32:
+        raise ValueError("Z must be (M, r) float32 with r in %s" % (RANKS,))
+    W = torch.empty((N, r), dtype=torch.float32, device=X.device)
+    Y = torch.empty((M, r), dtype=torch.float32, device=X.device)
+    nb = int(_b.load().gspca_sketch_workspace_bytes(M, N, r))
+    buf, wp = _aligned(nb, X.device)
+    _check(_b.load().gspca_sketch_refine(X.data_ptr(), X.stride(1), M, N, Z.data_ptr(), r,
+                                         W.data_ptr(), Y.data_ptr(), wp, nb,
+                                         _stream(stream, X.device)))
     return W, Y
 
 
@@ -84,15 +92,17 @@ def features(X, Omega, power=1, stream=None):
 
 
 def whiten(Y, stream=None):
-    """(Z, gamma, flag): Z = sqrt(M) Y Q diag(g)^(-1/2) (row-major M x 32)."""
+    """(Z, gamma, flag): Z = sqrt(M) Y Q diag(g)^(-1/2) (row-major M x r)."""
     import torch
-    M = Y.shape[0]
+    M, r = Y.shape
     Y = Y.contiguous()
     Z = torch.empty_like(Y)
-    g = torch.empty(RANK, dtype=torch.float64, device=Y.device)
+    g = torch.empty(r, dtype=torch.float64, device=Y.device)
     flag = torch.zeros(1, dtype=torch.int32, device=Y.device)
-    _check(_b.load().gspca_whiten_sketch(Y.data_ptr(), M, RANK, Z.data_ptr(), g.data_ptr(),
-                                         flag.data_ptr(), _stream(stream, Y.device)))
+    nb = int(_b.load().gspca_sketch_workspace_bytes(M, 1, r)) if M >= 1 and r in RANKS else 0
+    buf, wp = _aligned(max(nb, 1), Y.device)
+    _check(_b.load().gspca_whiten_sketch(Y.data_ptr(), M, r, Z.data_ptr(), g.data_ptr(),
+                                         flag.data_ptr(), wp, nb, _stream(stream, Y.device)))
     return Z, g, flag
 
 
@@ -197,17 +207,20 @@ class WarmStartNet:
 
     def predict(self, X, Omega, power=1, stream=None):
         """Start vectors T0 (M x K, column-major float32) for column-major float32 X
-        (sketch, `power` refinement steps, network)."""
+        (sketch of width Omega.shape[1], `power` refinement steps, network)."""
         import torch
         M, N = X.shape
         if X.dtype != torch.float32 or X.stride(0) != 1:
             raise ValueError("X must be column-major float32")
         Om = Omega.contiguous()
+        r = Om.shape[1]
+        if Om.dim() != 2 or Om.shape[0] != N or r not in RANKS:
+            raise ValueError("Omega must be (N, r) float32 with r in %s" % (RANKS,))
         T0 = torch.empty_strided((M, self.dims[3]), (1, M), dtype=torch.float32,
                                  device=self.device)
         p, nb = self._workspace(M, 1, N)
         _check(_b.load().gspca_ws_predict(ctypes.byref(self.net), X.data_ptr(), X.stride(1), M, N,
-                                          Om.data_ptr(), int(power), T0.data_ptr(), p, nb,
+                                          Om.data_ptr(), int(r), int(power), T0.data_ptr(), p, nb,
                                           _stream(stream, self.device)))
         return T0
 

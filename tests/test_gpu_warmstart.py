@@ -65,12 +65,13 @@ def test_sketch_matches_oracle(orc):
     assert np.all(np.abs(Y.cpu().numpy() - Yo) <= bound + 1e-30)
 
 
-def test_refinement_step_matches_oracle(orc):
+@pytest.mark.parametrize("r", [32, 64])
+def test_refinement_step_matches_oracle(orc, r):
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
-    X = synth.warmstart_instance(4, M=900, N=150)[0]
+    X = synth.warmstart_instance(4, M=900, N=150)[0]  # 150 columns: 3 blocks of 64, ragged
     Xd = _colmajor(X)
-    Z = ws.whiten(ws.sketch(Xd, _dev(synth.sketch_matrix(150, 32))))[0]
+    Z = ws.whiten(ws.sketch(Xd, _dev(synth.sketch_matrix(150, r))))[0]
     W, Y = ws.sketch_refine(Xd, Z)
     torch.cuda.synchronize()
     Zh = Z.cpu().numpy().astype(np.float64)
@@ -84,11 +85,12 @@ def test_refinement_step_matches_oracle(orc):
                   <= N * 2.0 ** -24 * (Xa @ np.abs(Wg)) + 1e-30)
 
 
-def test_whitening_matches_oracle(orc):
+@pytest.mark.parametrize("r", [32, 64])
+def test_whitening_matches_oracle(orc, r):
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
-    X = synth.warmstart_instance(2, M=2048, N=256)[0]
-    Om = synth.sketch_matrix(256, 32)
+    X = synth.warmstart_instance(2, M=2049, N=256)[0]  # a ragged last tile of 64 rows
+    Om = synth.sketch_matrix(256, r)
     Y = ws.sketch(_colmajor(X), _dev(Om))
     Z, g, flag = ws.whiten(Y)
     torch.cuda.synchronize()
@@ -99,11 +101,13 @@ def test_whitening_matches_oracle(orc):
     assert np.abs(g - go).max() <= 1e-10 * go[0]
     Zg = Z.cpu().numpy().astype(np.float64)
     M = Zg.shape[0]
-    ok = go > 1e-12 * go[0]
-    gap = np.ones(32, dtype=bool)
+    # directions resolved in FP64 from the FP32 sketch: eigenvector errors grow
+    # like eps * g_0 / (g_k * gap), so compare where g_k > 1e-8 g_0 with gaps
+    ok = go > 1e-10 * go[0]
+    gap = np.ones(r, dtype=bool)
     gap[:-1] &= (go[:-1] - go[1:]) > 1e-3 * go[:-1]
     gap[1:] &= (go[:-1] - go[1:]) > 1e-3 * go[:-1]
-    sel = ok & gap
+    sel = (go > 1e-8 * go[0]) & gap
     assert sel.sum() >= 16
     assert np.abs(Zg[:, sel] - Zo[:, sel]).max() <= 1e-4
     assert np.abs(Zg[:, ok].T @ Zg[:, ok] / M - np.eye(int(ok.sum()))).max() <= 1e-4
@@ -196,16 +200,17 @@ def test_predict_composes_sketch_whiten_forward(orc):
     M, N = 1500, 128
     X = synth.haar_spectrum(M, N, np.linspace(1.0, 0.3, N), 0.0, seed=(15, 1), centre=False,
                             dtype=np.float32)
-    Om = synth.sketch_matrix(N, 32)
     net = ws.WarmStartNet(K=8, hidden=(64, 64), seed=4, last_zero=False)
     params = _oracle_params(orc, net)
-    for power in (0, 1):
+    for r, power in ((32, 0), (32, 1), (64, 2)):
+        Om = synth.sketch_matrix(N, r)
         T0 = net.predict(_colmajor(X), _dev(Om), power=power)
         torch.cuda.synchronize()
         _, Zo, _ = orc.sketch_whiten(X, Om, power=power)
+        Zo = np.ascontiguousarray(Zo[:, :32])  # the network reads the first 32 directions
         _, _, Oo = orc.mlp_forward(orc.bf16_round(Zo), params, round_bf16=True, skip=Zo)
         assert T0.stride() == (1, M)
-        assert _rel(T0.cpu().numpy(), Oo) <= 5e-3, power
+        assert _rel(T0.cpu().numpy(), Oo) <= 5e-3, (r, power)
 
 
 def test_untrained_network_returns_the_sketch_directions():
