@@ -300,6 +300,111 @@ def bench_batched(args):
     print(json.dumps(res), flush=True)
 
 
+def _events_ms(fn, reps):
+    import torch
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    out = fn()
+    torch.cuda.synchronize()
+    times = []
+    for _ in range(reps):
+        a.record()
+        out = fn()
+        b.record()
+        torch.cuda.synchronize()
+        times.append(a.elapsed_time(b))
+    times.sort()
+    return out, times[len(times) // 2]
+
+
+def bench_small(args):
+    """512 x 128 FP64 (rank-32 signal 2^(-i/4) + 1e-3 noise, centred columns),
+    K = 16, tol 1e-10: GS-PCA and NIPALS, median of 5 fits, parity against
+    the FP64 oracle on the same trajectory (replayed counts and columns)."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    gp.load()
+    X = synth.case_small_f64()
+    Xd = gp.column_major(torch.from_numpy(X).cuda())
+    K, tol = 16, 1e-10
+    res = {"metric": "GS-PCA / NIPALS components/s, FP64 512x128 (cache-resident)",
+           "unit": "components/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "small_f64_512x128_K16", "M": 512, "N": 128, "K": K,
+                      "tol": tol, "max_iter": 1000}}
+    for algo in ("gs", "nipals"):
+        out, ms = _events_ms(lambda: gp.fit(Xd, K, tol=tol, max_iter=1000, algo=algo), 5)
+        its = out["iters"].cpu().numpy()
+        sc = out["start_col"].cpu().numpy()
+        o = oracle.fit(X, K, tol=0.0, max_iter=int(its.max()), algo=algo, replay_iters=its,
+                       replay_start=sc)
+        P = out["P"].cpu().numpy()
+        s = np.sign(np.sum(P * o.P, axis=0))
+        ang = 2 * np.arcsin(np.minimum(np.linalg.norm(P - o.P * s, axis=0) / 2, 1.0))
+        PtP = P.T @ P
+        res[algo] = {"ms_per_fit": ms, "components_per_s": K / ms * 1e3,
+                     "iters_mean": float(its.mean()), "max_loading_angle_vs_oracle": float(ang.max()),
+                     "orth_P": float(np.abs(PtP - np.eye(K)).max())}
+    res["value"] = res["gs"]["components_per_s"]
+    res["ms_per_step"] = res["gs"]["ms_per_fit"]
+    res["steps"], res["warmup"] = 5, 1
+    res["roofline"] = None
+    res["cpu_baseline"] = None
+    if not args.no_cpu_baseline:
+        t0 = time.perf_counter()
+        oracle.fit(X, K, tol=tol, max_iter=1000)
+        dt = time.perf_counter() - t0
+        res["cpu_baseline"] = {"value": K / dt, "unit": "components/s", "cores": 1,
+                               "kind": "oracle", "sample": "one full FP64 oracle fit (%.2f s)" % dt}
+    print(json.dumps(res), flush=True)
+
+
+def bench_collinear(args):
+    """4096 x 512 FP32 full rank (s_i = 0.9^i + 1e-4 noise, centred), K = N =
+    512, tol 1e-6, max_iter 1000: GS-PCA vs NIPALS orthogonality and
+    throughput (cache-resident: the matrix is 8 MiB)."""
+    import numpy as np
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    gp.load()
+    X = synth.case_collinear_f32()
+    Xd = gp.column_major(torch.from_numpy(X).cuda())
+    M, N = X.shape
+    K = N
+    fro2 = float(np.sum(X.astype(np.float64) ** 2))
+    res = {"metric": "GS-PCA components/s and orthogonality, FP32 4096x512 full rank",
+           "unit": "components/s", "n_gpus": 1, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": "collinear_f32_4096x512_K512", "M": M, "N": N, "K": K,
+                      "tol": 1e-6, "max_iter": 1000}}
+    for algo in ("gs", "nipals"):
+        t0 = time.perf_counter()
+        out = gp.fit(Xd, K, tol=1e-6, max_iter=1000, algo=algo, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P = out["P"].double()
+        sig = out["sigma"].double()
+        V = out["T"].double() / torch.where(sig > 0, sig, torch.ones_like(sig))
+        eye = torch.eye(K, dtype=torch.float64, device="cuda")
+        its = out["iters"].cpu().numpy()
+        res[algo] = {"s_per_fit": dt, "components_per_s": K / dt, "status": int(out["status"]),
+                     "iters_mean": float(its.mean()), "iters_max": int(its.max()),
+                     "orth_P": float((P.T @ P - eye).abs().max()),
+                     "orth_V": float((V.T @ V - eye).abs().max()),
+                     "sum_lambda_over_fro2": float(out["lambda"].sum()) / fro2}
+        log("collinear %s: %.2f s, orth_P %.2e orth_V %.2e" % (algo, dt, res[algo]["orth_P"],
+                                                            res[algo]["orth_V"]))
+    res["value"] = res["gs"]["components_per_s"]
+    res["ms_per_step"] = res["gs"]["s_per_fit"] * 1e3
+    res["steps"], res["warmup"] = 1, 0
+    res["roofline"] = None
+    res["cpu_baseline"] = None
+    print(json.dumps(res), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -322,8 +427,10 @@ def main():
     ap.add_argument("--calib-copy", action="store_true",
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
-    ap.add_argument("--workload", default="large", choices=["large", "batched"],
-                    help="large: the 65536 x 8192 fit (default); batched: 2048 uneven problems")
+    ap.add_argument("--workload", default="large",
+                    choices=["large", "batched", "small", "collinear"],
+                    help="large: the 65536 x 8192 fit (default); batched: 2048 uneven "
+                         "problems; small: 512 x 128 FP64; collinear: 4096 x 512 FP32, K = N")
     ap.add_argument("--batch-count", type=int, default=2048)
     args = ap.parse_args()
     if args.gpus != 1:
@@ -332,6 +439,12 @@ def main():
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
+        return
+    if args.workload == "small":
+        bench_small(args)
+        return
+    if args.workload == "collinear":
+        bench_collinear(args)
         return
 
     import numpy as np

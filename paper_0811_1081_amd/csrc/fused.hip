@@ -722,9 +722,10 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
 }
 
 // Gram-Schmidt coefficients of the score, d = V_(k)^T t (FP64), from the
-// complete t of the pass: workgroup b takes `rows` consecutive rows (staged in
-// LDS), one wave per column of V with 8 loads in flight per lane, per-group
-// partials, and the last workgroup adds them in a fixed order.
+// complete t of the pass: workgroup (b, y) takes `rows` consecutive rows
+// (staged in LDS) and columns [16y, 16y + 16) of V, one wave per column with
+// 8 loads in flight per lane; per-row-block partials, added in a fixed order
+// by the last workgroup, which also finishes sigma and the stop test.
 template <typename E>
 __global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t, int64_t M,
                                                    const E *__restrict__ V, int kd, int64_t rows,
@@ -745,7 +746,9 @@ __global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t,
     for (int x = tid; x < n; x += 256)
         ts[x] = t[r0 + x];
     __syncthreads();
-    for (int i = w; i < kd; i += 4) {
+    // columns [16y, 16y + 16) of V for workgroup row y of the grid
+    const int ce = kd < 16 * (int)blockIdx.y + 16 ? kd : 16 * (int)blockIdx.y + 16;
+    for (int i = 16 * (int)blockIdx.y + w; i < ce; i += 4) {
         const E *vc = V + (int64_t)i * M + r0;
         double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         int x = lane;
@@ -942,8 +945,9 @@ void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, const d
                          int32_t limit, int replay, double tiny, int stop, hipStream_t s)
 {
     const int64_t rows = score_rows(M);
-    hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows)), dim3(256), 0, s, t, M, V, kd, rows,
-                       tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
+    const unsigned cols = kd > 0 ? (unsigned)fcdiv(kd, 16) : 1u;
+    hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows), cols), dim3(256), 0, s, t, M, V, kd,
+                       rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
 }
 
 template <int F>

@@ -420,18 +420,17 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
             cs[i] = c[i0 + i];
         __syncthreads();
         if (r < L) {
-            // four independent sums so that the column loads overlap
-            double p1 = 0.0, p2 = 0.0, p3 = 0.0;
+            // eight independent sums so that the column loads overlap
+            double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int i = 0;
-            for (; i + 3 < n; i += 4) {
-                proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
-                p1 += (double)Q[r + (int64_t)(i0 + i + 1) * ldq] * cs[i + 1];
-                p2 += (double)Q[r + (int64_t)(i0 + i + 2) * ldq] * cs[i + 2];
-                p3 += (double)Q[r + (int64_t)(i0 + i + 3) * ldq] * cs[i + 3];
+            for (; i + 7 < n; i += 8) {
+#pragma unroll
+                for (int u = 0; u < 8; ++u)
+                    a[u] += (double)Q[r + (int64_t)(i0 + i + u) * ldq] * cs[i + u];
             }
             for (; i < n; ++i)
-                proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
-            proj = (proj + p1) + (p2 + p3);
+                a[0] += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
+            proj += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
         }
     }
     v -= proj;
