@@ -171,7 +171,8 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5, refine_i
 def measured_traffic(kernel, form, M, N):
     """HBM bytes per launch of the dominant kernel from the committed counter
     summary (profiles/traffic.json), or None when that record is for another
-    configuration or the kernel's source has changed since it was measured."""
+    configuration or the kernel's sources (SHA-256 of each file listed under
+    "kernel_sources") have changed since it was measured."""
     import hashlib
     path = os.path.join(ROOT, "profiles", "traffic.json")
     try:
@@ -179,11 +180,12 @@ def measured_traffic(kernel, form, M, N):
             rec = json.load(f).get("%s %s %dx%d" % (kernel, form, M, N))
         if rec is None:
             return None
-        with open(os.path.join(ROOT, rec["kernel_source"]), "rb") as f:
-            if hashlib.sha256(f.read()).hexdigest() != rec["kernel_source_sha256"]:
-                return None
+        for src, digest in rec["kernel_sources"].items():
+            with open(os.path.join(ROOT, src), "rb") as f:
+                if hashlib.sha256(f.read()).hexdigest() != digest:
+                    return None
         return float(rec["bytes"])
-    except (OSError, ValueError, KeyError):
+    except (OSError, ValueError, KeyError, AttributeError):
         return None
 
 

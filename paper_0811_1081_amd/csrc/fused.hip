@@ -4,122 +4,18 @@
 // E4M3) storage of X with per-column FP32 scales.
 //
 // The data matrix A (the residual R for explicit deflation, X itself for
-// implicit deflation, or the quantised codes Q) is held in row panels: panel b
-// holds rows [b*PR, b*PR + PR) of ldp >= N columns, the PR values of each
-// column contiguous in 16 bytes (PR = 2, 4, 8, 16 for FP64, FP32, BF16, FP8),
-// so a wave reading 64 consecutive columns of a panel reads 1 KiB of
-// contiguous memory.  One persistent workgroup per compute unit walks a
-// contiguous range of panels and, for each panel, computes the PR entries of
-// t = A p (a workgroup reduction), then immediately adds the panel's
-// contribution A_b^T t_b to its private copy of q = A^T t, using the panel
-// values still in registers.  The next panel is loaded while the current one
-// is reduced.  The Gram-Schmidt pass on t (needing all of t) is applied
-// afterwards through W = A^T V_(k):  A^T (t - V d) = q - W d.
+// implicit deflation, or the quantised codes Q) is held in row panels
+// (panel.h); the streaming kernel that reads it once per iteration is in
+// pass.hip.  This file holds the rest of the iteration: the Gram-Schmidt
+// pass on t (needing all of t) is applied afterwards through W = A^T V_(k):
+// A^T (t - V d) = q - W d; the re-tiling, quantisation, deflation, start and
+// end-of-component kernels.
 //
 // Quantised storage: X~_mj = decode(Q_mj) * s_j.  The scale is folded into
 // the vectors: X~ p = Q (s o p) and X~^T t = s o (Q^T t); arithmetic is FP32.
-#include <float.h>
-#include <hip/hip_bf16.h>
-#include <math.h>
-
-#include <type_traits>
-
-#include "internal.h"
+#include "panel.h"
 
 namespace gspca {
-
-typedef float f32x4_t __attribute__((ext_vector_type(4)));
-typedef double f64x2_t __attribute__((ext_vector_type(2)));
-typedef unsigned int u32x4_t __attribute__((ext_vector_type(4)));
-typedef float f32x2_t __attribute__((ext_vector_type(2)));
-
-// Element codecs of a 16-byte panel segment (PR rows of one column).
-struct CodecF64 {
-    using acc = double;
-    using raw = f64x2_t;
-    static constexpr int PR = 2;
-    static constexpr bool scaled = false;
-    __device__ static inline void decode(const raw &v, acc (&o)[PR]) { o[0] = v[0]; o[1] = v[1]; }
-};
-struct CodecF32 {
-    using acc = float;
-    using raw = f32x4_t;
-    static constexpr int PR = 4;
-    static constexpr bool scaled = false;
-    __device__ static inline void decode(const raw &v, acc (&o)[PR])
-    {
-        o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
-    }
-};
-// bfloat16: the upper half of a binary32, so decoding is a shift.
-struct CodecBF16 {
-    using acc = float;
-    using raw = u32x4_t;
-    static constexpr int PR = 8;
-    static constexpr bool scaled = true;
-    __device__ static inline void decode(const raw &v, acc (&o)[PR])
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            o[2 * i] = __uint_as_float(v[i] << 16);
-            o[2 * i + 1] = __uint_as_float(v[i] & 0xFFFF0000u);
-        }
-    }
-    __device__ static inline float decode_one(const unsigned char *seg, int r)
-    {
-        const unsigned short h = reinterpret_cast<const unsigned short *>(seg)[r];
-        return __uint_as_float((unsigned int)h << 16);
-    }
-};
-// OCP E4M3 (gfx950 converts it in hardware, two codes per instruction).
-struct CodecFP8 {
-    using acc = float;
-    using raw = u32x4_t;
-    static constexpr int PR = 16;
-    static constexpr bool scaled = true;
-    __device__ static inline void decode(const raw &v, acc (&o)[PR])
-    {
-#pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const f32x2_t lo = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], false);
-            const f32x2_t hi = __builtin_amdgcn_cvt_pk_f32_fp8((int)v[i], true);
-            o[4 * i] = lo[0];
-            o[4 * i + 1] = lo[1];
-            o[4 * i + 2] = hi[0];
-            o[4 * i + 3] = hi[1];
-        }
-    }
-    __device__ static inline float decode_one(const unsigned char *seg, int r)
-    {
-        const unsigned int word = reinterpret_cast<const unsigned int *>(seg)[r >> 2];
-        const f32x2_t pr = ((r >> 1) & 1) ? __builtin_amdgcn_cvt_pk_f32_fp8((int)word, true)
-                                          : __builtin_amdgcn_cvt_pk_f32_fp8((int)word, false);
-        return (r & 1) ? pr[1] : pr[0];
-    }
-};
-
-template <typename T>
-__device__ inline T fwave_sum(T v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
-
-// Element (m, j) of the panel matrix in the arithmetic type (scaled for codes).
-template <class C>
-__device__ inline typename C::acc panel_elem(const unsigned char *A, int64_t ldp, int64_t m,
-                                             int64_t j, const float *scale)
-{
-    const unsigned char *seg = A + ((m / C::PR) * ldp + j) * 16;
-    const int r = (int)(m % C::PR);
-    if constexpr (C::scaled)
-        return C::decode_one(seg, r) * scale[j];
-    else
-        return reinterpret_cast<const typename C::acc *>(seg)[r];
-}
 
 // ---------------------------------------------------------------------------
 // Re-tile X (column-major, ldx) into row panels of ldp >= N columns; rows >= M
@@ -447,202 +343,6 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
     }
 }
 
-// ---------------------------------------------------------------------------
-// The fused pass.  FIRST: q = A^T t_in only (the start of a component).
-// Otherwise: t = A (p / |p|) (written to t_out in FP64) and q = A^T t.  q is
-// left as per-workgroup partials q_part[g][j].  The pass only streams A: the
-// Gram-Schmidt coefficients d = V_(k)^T t are formed by a separate coalesced
-// reduction over the rows of t_out.
-
-// Variants: PL = false keeps the loading in registers (at most 512 threads,
-// 8 waves per compute unit); PL = true keeps it in LDS, freeing registers for
-// 1024 threads (16 waves per compute unit).  PIPE = true prefetches the next
-// panel into a second register buffer; PIPE = false holds one panel and is
-// meant for two workgroups per compute unit.  `skew` != 0 interleaves the
-// panel assignment (see below).
-template <class C, int CPT, bool FIRST, bool PL, bool PIPE>
-__global__ __launch_bounds__(PL ? 1024 : 512) void k_pass(
-    const unsigned char *__restrict__ A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
-    const float *__restrict__ scale, const double *__restrict__ p,
-    const typename C::acc *__restrict__ t_in, double *__restrict__ t_out,
-    double *__restrict__ tsq, typename C::acc *__restrict__ q_part, LoopState *st, int skew)
-{
-    if (st->done)
-        return;
-    using E = typename C::acc;
-    using RT = typename C::raw;
-    constexpr int PR = C::PR;
-    __shared__ E red[2][16][PR];
-    extern __shared__ unsigned char pass_smem[];
-    E *pl = reinterpret_cast<E *>(pass_smem);
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
-    const int NT = blockDim.x, nw = NT >> 6;
-    const int64_t G = gridDim.x, g = blockIdx.x;
-    // order 0: workgroup g owns the contiguous panels [b0, b1); order 1: it
-    // owns panels g, g + G, g + 2G, ... so that at any moment the grid reads
-    // one contiguous stretch of the matrix.
-    const bool inter = skew != 0;
-    const int64_t b0 = inter ? g : NP * g / G, b1 = inter ? NP : NP * (g + 1) / G;
-    const int64_t cnt = inter ? (g < NP ? (NP - 1 - g) / G + 1 : 0) : b1 - b0;
-    E preg[PL ? 1 : CPT];
-    E q[CPT];
-    double tacc = 0.0; // |t|^2 over this workgroup's rows (threads tid < PR)
-    const double inv = FIRST ? 0.0 : 1.0 / st->pnorm;
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int64_t j = tid + (int64_t)c * NT;
-        double pj = 0.0;
-        if (!FIRST && j < N) {
-            pj = p[j] * inv;
-            if constexpr (C::scaled)
-                pj *= (double)scale[j];
-        }
-        if constexpr (PL)
-            pl[tid + c * NT] = (E)pj;
-        else
-            preg[c] = (E)pj;
-        q[c] = E(0);
-    }
-    if constexpr (PL)
-        __syncthreads();
-    auto pval = [&](int c) -> E {
-        if constexpr (PL)
-            return pl[tid + c * NT];
-        else
-            return preg[c];
-    };
-    // The panel width ldp = NT * CPT covers every lane's columns (columns >= N
-    // are zero), so every lane always loads: no divergent branch around the
-    // loads, and the wait for one panel does not also wait for the prefetched
-    // next one.  Lanes past N carry p = 0 and never store q.
-    RT bufA[CPT], bufB[PIPE ? CPT : 1];
-    const uint32_t lane_off = (uint32_t)tid * 16u;
-    const int64_t col_step = (int64_t)NT * 16;
-    // uniform (scalar) base per panel and column block + one per-lane offset
-    auto load = [&](RT *buf, int64_t b) {
-        const unsigned char *pb = A + b * ldp * 16;
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            const unsigned char *cb = pb + c * col_step;
-#ifdef GSPCA_PLAIN_LOADS
-            buf[c] = *reinterpret_cast<const RT *>(cb + lane_off);
-#else
-            buf[c] = __builtin_nontemporal_load(reinterpret_cast<const RT *>(cb + lane_off));
-#endif
-        }
-    };
-    auto process = [&](const RT *buf, int64_t b, int slot) {
-        E tb[PR];
-        if (FIRST) {
-#pragma unroll
-            for (int r = 0; r < PR; ++r)
-                tb[r] = t_in[b * PR + r];
-        } else {
-            E tp[PR];
-#pragma unroll
-            for (int r = 0; r < PR; ++r)
-                tp[r] = E(0);
-#pragma unroll
-            for (int c = 0; c < CPT; ++c) {
-                E e[PR];
-                C::decode(buf[c], e);
-                const E pc = pval(c);
-#pragma unroll
-                for (int r = 0; r < PR; ++r)
-                    tp[r] += e[r] * pc;
-            }
-#pragma unroll
-            for (int r = 0; r < PR; ++r)
-                tp[r] = fwave_sum(tp[r]);
-            if (lane == 0)
-#pragma unroll
-                for (int r = 0; r < PR; ++r)
-                    red[slot][w][r] = tp[r];
-            __syncthreads();
-#pragma unroll
-            for (int r = 0; r < PR; ++r) {
-                E s = E(0);
-                for (int i = 0; i < nw; ++i)
-                    s += red[slot][i][r];
-                tb[r] = s;
-            }
-            if (tid < PR) {
-                const int64_t m = b * PR + tid;
-                const double tv = (double)tb[tid];
-                t_out[m] = tv;
-                tacc += tv * tv; // rows past M are zero
-            }
-        }
-#pragma unroll
-        for (int c = 0; c < CPT; ++c) {
-            // Decode again rather than keep the decoded values of all CPT
-            // segments alive across the reduction (16 floats per segment for
-            // FP8): the empty asm hides the raw value from common-subexpression
-            // elimination.
-            RT raw = buf[c];
-            if constexpr (C::scaled) {
-#pragma unroll
-                for (int u = 0; u < 4; ++u) {
-                    unsigned int x = raw[u];
-                    asm volatile("" : "+v"(x));
-                    raw[u] = x;
-                }
-            }
-            E e[PR];
-            C::decode(raw, e);
-#pragma unroll
-            for (int r = 0; r < PR; ++r)
-                q[c] += e[r] * tb[r];
-        }
-    };
-
-    // Software pipeline: panel i+1 is in flight while panel i is reduced.  The
-    // steady-state loop issues its prefetches unconditionally; the last one or
-    // two panels are peeled.  Panel i of this workgroup is b0 + (i + off) % cnt.
-    auto pid = [&](int64_t i) -> int64_t { return inter ? g + i * G : b0 + i; };
-    int64_t i = 0;
-    if constexpr (PIPE) {
-        if (i < cnt)
-            load(bufA, pid(i));
-        while (i + 2 < cnt) {
-            load(bufB, pid(i + 1));
-            process(bufA, pid(i), 0);
-            load(bufA, pid(i + 2));
-            process(bufB, pid(i + 1), 1);
-            i += 2;
-        }
-        if (i + 1 < cnt) {
-            load(bufB, pid(i + 1));
-            process(bufA, pid(i), 0);
-            process(bufB, pid(i + 1), 1);
-        } else if (i < cnt) {
-            process(bufA, pid(i), 0);
-        }
-    } else {
-        // one panel in registers; latency is hidden by a second workgroup on
-        // the same compute unit
-        for (; i < cnt; ++i) {
-            load(bufA, pid(i));
-            process(bufA, pid(i), (int)(i & 1));
-        }
-    }
-#pragma unroll
-    for (int c = 0; c < CPT; ++c) {
-        const int64_t j = tid + (int64_t)c * NT;
-        if (j < N) {
-            E v = q[c];
-            if constexpr (C::scaled)
-                v *= scale[j];
-            q_part[g * N + j] = v;
-        }
-    }
-    if (!FIRST && w == 0) {
-        const double tt = fwave_sum(tacc); // lanes >= PR hold 0
-        if (lane == 0)
-            tsq[g] = tt;
-    }
-}
-
 // q = sum_g q_part[g] (FP64, fixed order), q' = q - W d (the Gram-Schmidt
 // correction of t carried to the loading side), then the loading's
 // Gram-Schmidt coefficients c = P_(k)^T q' (Sec. 2.3), finished by the last
@@ -722,64 +422,89 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
 }
 
 // Gram-Schmidt coefficients of the score, d = V_(k)^T t (FP64), from the
-// complete t of the pass: workgroup (b, y) takes `rows` consecutive rows
-// (staged in LDS) and columns [16y, 16y + 16) of V, one wave per column with
-// 8 loads in flight per lane; per-row-block partials, added in a fixed order
-// by the last workgroup, which also finishes sigma and the stop test.
+// complete t of the pass: workgroup (b, y) takes `rows` consecutive rows of t
+// (staged in LDS, zero past M) and columns [32y, 32y + 32) of V, two columns
+// per wave; a lane issues the loads of 16 rows of both its columns before the
+// first use (row and column indices clamped, their weights zero).  Per-row-
+// block partials are added in a fixed order by the last workgroup, which
+// also finishes sigma and the stop test.
+constexpr int kScoreThreads = 1024;
 template <typename E>
-__global__ __launch_bounds__(256) void k_score_dot(const double *__restrict__ t, int64_t M,
-                                                   const E *__restrict__ V, int kd, int64_t rows,
-                                                   const double *__restrict__ tsq, int G,
-                                                   double *__restrict__ cpart,
-                                                   double *__restrict__ d, LoopState *st,
-                                                   double tol, int32_t limit, int replay,
-                                                   double tiny, int stop)
+__global__ __launch_bounds__(kScoreThreads) void k_score_dot(
+    const double *__restrict__ t, int64_t M, const E *__restrict__ V, int kd, int64_t rows,
+    const double *__restrict__ tsq, int G, double *__restrict__ cpart, double *__restrict__ d,
+    LoopState *st, double tol, int32_t limit, int replay, double tiny, int stop)
 {
     if (st->done)
         return;
     __shared__ double ts[kScoreRows];
-    __shared__ double lds[256];
+    __shared__ double lds[kScoreThreads];
     __shared__ int last;
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = kScoreThreads / 64;
     const int64_t r0 = (int64_t)blockIdx.x * rows;
     const int n = (int)(M - r0 < rows ? M - r0 : rows);
-    for (int x = tid; x < n; x += 256)
-        ts[x] = t[r0 + x];
+    for (int x = tid; x < rows; x += kScoreThreads)
+        ts[x] = x < n ? t[r0 + x] : 0.0;
     __syncthreads();
-    // columns [16y, 16y + 16) of V for workgroup row y of the grid
-    const int ce = kd < 16 * (int)blockIdx.y + 16 ? kd : 16 * (int)blockIdx.y + 16;
-    for (int i = 16 * (int)blockIdx.y + w; i < ce; i += 4) {
-        const E *vc = V + (int64_t)i * M + r0;
-        double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-        int x = lane;
-        for (; x + 7 * 64 < n; x += 8 * 64) {
+    if (kd > 0) {
+        const int i0 = 32 * (int)blockIdx.y + w, i1 = i0 + nw;
+        const E *c0 = V + (int64_t)(i0 < kd ? i0 : kd - 1) * M + r0;
+        const E *c1 = V + (int64_t)(i1 < kd ? i1 : kd - 1) * M + r0;
+        double a0 = 0.0, a1 = 0.0;
+        for (int x0 = 0; x0 < n; x0 += 16 * 64) {
+            E v0[16], v1[16];
 #pragma unroll
-            for (int u = 0; u < 8; ++u)
-                a[u] += (double)vc[x + u * 64] * ts[x + u * 64];
+            for (int u = 0; u < 16; ++u) {
+                const int x = x0 + lane + 64 * u, xc = x < n ? x : n - 1;
+                v0[u] = c0[xc];
+                v1[u] = c1[xc];
+            }
+#pragma unroll
+            for (int u = 0; u < 16; ++u) {
+                const double tv = ts[x0 + lane + 64 * u]; // zero past n
+                a0 += (double)v0[u] * tv;
+                a1 += (double)v1[u] * tv;
+            }
         }
-        for (; x < n; x += 64)
-            a[0] += (double)vc[x] * ts[x];
-        const double sum = fwave_sum(((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7])));
-        if (lane == 0)
-            cpart[(int64_t)blockIdx.x * kd + i] = sum;
+        const double s0 = fwave_sum(a0), s1 = fwave_sum(a1);
+        if (lane == 0) {
+            if (i0 < kd && i0 < 32 * (int)blockIdx.y + 32)
+                cpart[(int64_t)blockIdx.x * kd + i0] = s0;
+            if (i1 < kd && i1 < 32 * (int)blockIdx.y + 32)
+                cpart[(int64_t)blockIdx.x * kd + i1] = s1;
+        }
     }
     if (!arrive_last(&st->counter[kCntDotM], &last))
         return;
-    if (kd > 0)
-        reduce_partials(cpart, gridDim.x, kd, d, lds);
-    __shared__ double tt;
-    reduce_partials(tsq, G, 1, &tt, lds);
+    // the |t|^2 partials and the loop state are loaded before the partials of
+    // d are reduced, so that their loads overlap
+    double tq = 0.0;
+    for (int q = tid; q < G; q += kScoreThreads)
+        tq += tsq[q];
+    ScoreState ss{};
+    if (tid == 0)
+        ss = score_state(st);
+    const double ssq = kd > 0 ? reduce_partials<16>(cpart, gridDim.x, kd, d, lds) : 0.0;
+    // |t|^2 and |d|^2 in a fixed order: wave sums, then the waves in order
+    const double tqw = fwave_sum(tq), ssw = fwave_sum(ssq);
+    __syncthreads();
+    if (lane == 0) {
+        lds[w] = tqw;
+        lds[nw + w] = ssw;
+    }
     __syncthreads();
     if (tid != 0)
         return;
+    double tt = 0.0, dd = 0.0;
+    for (int q = 0; q < nw; ++q) {
+        tt += lds[q];
+        dd += lds[nw + q];
+    }
     st->counter[kCntDotM] = 0;
     // sigma = |t - V d| = sqrt(|t|^2 - |d|^2) (V orthonormal; d is at rounding
     // level once t has been formed from a loading orthogonal to P_(k))
-    double dd = 0.0;
-    for (int i = 0; i < kd; ++i)
-        dd += d[i] * d[i];
     const double s2 = tt - dd;
-    score_test(st, s2 > 0.0 ? sqrt(s2) : 0.0, tol, limit, replay, tiny, stop);
+    score_test(st, ss, s2 > 0.0 ? sqrt(s2) : 0.0, tol, limit, replay, tiny, stop);
 }
 
 // Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
@@ -828,14 +553,6 @@ __global__ __launch_bounds__(256) void k_comp_end(const double *__restrict__ td,
 
 // ---------------------------------------------------------------------------
 // Launchers.
-
-static inline unsigned fcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
-
-template <int F> struct CodecOf;
-template <> struct CodecOf<kFmtF64> { using type = CodecF64; };
-template <> struct CodecOf<kFmtF32> { using type = CodecF32; };
-template <> struct CodecOf<kFmtBF16> { using type = CodecBF16; };
-template <> struct CodecOf<kFmtFP8> { using type = CodecFP8; };
 
 template <int F>
 void Fused<F>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP, int64_t ldp,
@@ -895,59 +612,15 @@ void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp,
                        implicit, V, P, sig, cn, T0, a, tiny, t, st);
 }
 
-template <class C, bool FIRST>
-static void launch_pass(int cpt, int G, int NT, int plds, int skew, int pipe,
-                        const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
-                        const float *scale, const double *p, const typename C::acc *t_in,
-                        double *t_out, double *tsq, typename C::acc *q_part, LoopState *st,
-                        hipStream_t s)
-{
-    const size_t lds = plds ? (size_t)cpt * NT * sizeof(typename C::acc) : 0;
-#define GSPCA_PASS(CP, PLV, PIV)                                                               \
-    hipLaunchKernelGGL((k_pass<C, CP, FIRST, PLV, PIV>), dim3(G), dim3(NT), lds, s, A, N, NP,  \
-                       ldp, M, scale, p, t_in, t_out, tsq, q_part, st, skew)
-#define GSPCA_PASS_CPT(PLV, PIV)                                                               \
-    switch (cpt) {                                                                             \
-    case 1: GSPCA_PASS(1, PLV, PIV); break;                                                    \
-    case 2: GSPCA_PASS(2, PLV, PIV); break;                                                    \
-    case 4: GSPCA_PASS(4, PLV, PIV); break;                                                    \
-    case 8: GSPCA_PASS(8, PLV, PIV); break;                                                    \
-    default: GSPCA_PASS(16, PLV, PIV); break;                                                  \
-    }
-    if (plds) {
-        if (pipe) { GSPCA_PASS_CPT(true, true) } else { GSPCA_PASS_CPT(true, false) }
-    } else {
-        if (pipe) { GSPCA_PASS_CPT(false, true) } else { GSPCA_PASS_CPT(false, false) }
-    }
-#undef GSPCA_PASS_CPT
-#undef GSPCA_PASS
-}
-
-template <int F>
-void Fused<F>::pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
-                    const unsigned char *A,
-                    int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
-                    const double *p, const E *t_in, double *t_out, double *tsq, E *q_part,
-                    LoopState *st, hipStream_t s)
-{
-    using C = typename CodecOf<F>::type;
-    if (first)
-        launch_pass<C, true>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                             t_out, tsq, q_part, st, s);
-    else
-        launch_pass<C, false>(cpt, G, NT, plds, skew, pipe, A, N, NP, ldp, M, scale, p, t_in,
-                              t_out, tsq, q_part, st, s);
-}
-
 template <int F>
 void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, const double *tsq,
                          int G, double *cpart, double *d, LoopState *st, double tol,
                          int32_t limit, int replay, double tiny, int stop, hipStream_t s)
 {
     const int64_t rows = score_rows(M);
-    const unsigned cols = kd > 0 ? (unsigned)fcdiv(kd, 16) : 1u;
-    hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows), cols), dim3(256), 0, s, t, M, V, kd,
-                       rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
+    const unsigned cols = kd > 0 ? (unsigned)fcdiv(kd, 32) : 1u;
+    hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows), cols), dim3(kScoreThreads), 0, s, t,
+                       M, V, kd, rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
 }
 
 template <int F>

@@ -59,14 +59,25 @@ __device__ inline bool arrive_last(uint32_t *counter, int *flag_lds)
     return last;
 }
 
+// The loop-state fields the stop test reads, loaded ahead of time.
+struct ScoreState {
+    int32_t iter;
+    double mu, delta, dp;
+};
+__device__ inline ScoreState score_state(const LoopState *st)
+{
+    return ScoreState{st->iter, st->mu, st->delta, st->dp};
+}
+
 // End of an iteration on the score side, by one thread: sigma = |t| after
 // the Gram-Schmidt pass, then the stop test -- the relative sigma test of the
 // host programs (Appendices 1, 3) when stop == 0, the loading change below
-// tol when stop == 1, or the replayed count -- and the loop state.
-__device__ inline void score_test(LoopState *st, double nrm, double tol, int32_t limit,
-                                  int replay, double tiny, int stop)
+// tol when stop == 1, or the replayed count -- and the loop state.  `ss`
+// holds the state as it was before this iteration.
+__device__ inline void score_test(LoopState *st, ScoreState ss, double nrm, double tol,
+                                  int32_t limit, int replay, double tiny, int stop)
 {
-    const int it = st->iter + 1;
+    const int it = ss.iter + 1;
     st->iter = it;
     st->sigma = nrm;
     if (!(nrm >= tiny)) {
@@ -74,15 +85,15 @@ __device__ inline void score_test(LoopState *st, double nrm, double tol, int32_t
         st->done = 1;
         return;
     }
-    const double mu = st->mu;
-    st->delta_prev = st->delta;
-    st->delta = stop == 1 ? st->dp : fabs(nrm - mu) / nrm;
+    const double mu = ss.mu;
+    st->delta_prev = ss.delta;
+    st->delta = stop == 1 ? ss.dp : fabs(nrm - mu) / nrm;
     if (replay) {
         if (it >= limit)
             st->done = 1;
         return;
     }
-    const bool pass_test = stop == 1 ? (st->dp < tol) : (fabs(mu - nrm) < tol * nrm);
+    const bool pass_test = stop == 1 ? (ss.dp < tol) : (fabs(mu - nrm) < tol * nrm);
     if (pass_test) {
         st->converged = 1;
         st->done = 1;
@@ -94,52 +105,78 @@ __device__ inline void score_test(LoopState *st, double nrm, double tol, int32_t
         st->not_converged = 1;
     }
 }
+__device__ inline void score_test(LoopState *st, double nrm, double tol, int32_t limit,
+                                  int replay, double tiny, int stop)
+{
+    score_test(st, score_state(st), nrm, tol, limit, replay, tiny, stop);
+}
 
 // out[i] = sum over b < nb of part[b*k + i], i < k, by one whole workgroup:
 // column i gets S = blockDim / k threads (slice s sums partials b = s, s+S,
-// ...), and the S slice sums are added in slice order, so the result is the
-// same on every run.  `lds` holds blockDim doubles.  All threads must call it.
-__device__ inline void reduce_partials(const double *__restrict__ part, int64_t nb, int k,
-                                       double *__restrict__ out, double *lds)
+// ... with UL loads in flight), and the S slice sums are added in slice
+// order, so the result is the same on every run.  `lds` holds blockDim
+// doubles.  All threads must call it.  Returns, in each thread, the sum of
+// squares of the outputs that thread wrote (0 in the others).
+template <int UL = 8>
+__device__ inline double reduce_partials(const double *__restrict__ part, int64_t nb, int k,
+                                         double *__restrict__ out, double *lds)
 {
     const int nt = blockDim.x, t = threadIdx.x;
+    double ssq = 0.0;
     for (int c0 = 0; c0 < k; c0 += nt) {
         const int kk = k - c0 < nt ? k - c0 : nt;
         const int S = nt / kk;
         const int i = t % kk, sl = t / kk;
-        double a0 = 0.0, a1 = 0.0;
+        double a[UL];
+#pragma unroll
+        for (int u = 0; u < UL; ++u)
+            a[u] = 0.0;
         if (sl < S) {
-            int64_t b = sl;
-            for (; b + S < nb; b += 2 * S) {
-                a0 += part[b * k + c0 + i];
-                a1 += part[(b + S) * k + c0 + i];
+            for (int64_t b = sl; b < nb; b += UL * (int64_t)S) {
+                // unconditional loads (index clamped) so that all UL are in
+                // flight; the ones past nb are dropped afterwards
+                double x[UL];
+#pragma unroll
+                for (int u = 0; u < UL; ++u) {
+                    const int64_t bb = b + (int64_t)u * S;
+                    x[u] = part[(bb < nb ? bb : nb - 1) * k + c0 + i];
+                }
+#pragma unroll
+                for (int u = 0; u < UL; ++u)
+                    a[u] += b + (int64_t)u * S < nb ? x[u] : 0.0;
             }
-            if (b < nb)
-                a0 += part[b * k + c0 + i];
         }
+        // pairwise, in a fixed order
+#pragma unroll
+        for (int h = UL / 2; h > 0; h >>= 1)
+#pragma unroll
+            for (int u = 0; u < h; ++u)
+                a[u] += a[u + h];
         __syncthreads();
-        lds[t] = a0 + a1;
+        lds[t] = a[0];
         __syncthreads();
         if (t < kk) {
             double r = 0.0;
             for (int q = 0; q < S; ++q)
                 r += lds[q * kk + t];
             out[c0 + t] = r;
+            ssq += r * r;
         }
     }
+    return ssq;
 }
 
 // Groups of partial sums per workgroup of the loading-side finish (64
 // columns each; 64 * kFinGroups threads).
 constexpr int kFinGroups = 16;
 
-// Rows per workgroup of the score coefficient reduction: about 128
-// workgroups, whole waves, at most kScoreRows.
-constexpr int64_t kScoreRows = 2048;
+// Rows per workgroup of the score coefficient reduction: whole blocks of
+// 1024, about 96 row blocks, at most kScoreRows (staged in LDS as FP64).
+constexpr int64_t kScoreRows = 4096;
 inline int64_t score_rows(int64_t M)
 {
-    const int64_t r = ((M + 127) / 128 + 63) / 64 * 64;
-    return r < 256 ? 256 : (r > kScoreRows ? kScoreRows : r);
+    const int64_t r = ((M + 95) / 96 + 1023) / 1024 * 1024;
+    return r > kScoreRows ? kScoreRows : r;
 }
 
 struct StartArgs {
