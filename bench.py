@@ -363,6 +363,94 @@ def bench_small(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_paper_sweep(args):
+    """The paper's own timing sweep (Sec. 4, Fig. 1): X uniform on [0, 1) with
+    rows centred, N = M/2, K = 10, tol 1e-7, max_iter 10000, start column k,
+    explicit deflation, FP64, GS-PCA and NIPALS-PCA.  Each size is timed with
+    the matrix resident on the device and, as the paper's programs did, with
+    the host-to-device copy of X and the copy back of T and P inside the
+    timing.  The one-core FP64 oracle is timed on the smaller sizes."""
+    import numpy as np
+    import torch
+    import oracle
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    gp.load()
+    K, tol, max_iter = 10, 1e-7, 10000
+    sizes = [int(x) for x in args.sweep_sizes.split(",")]
+    rows = []
+    for M in sizes:
+        N = M // 2
+        X = synth.uniform_paper(M, N, seed=(6, M))
+        Xh = torch.from_numpy(X).pin_memory()  # column-major (Fortran) view
+        Xd = torch.empty_strided((M, N), (1, M), dtype=torch.float64, device="cuda")
+        Xd.copy_(Xh)
+        Th = torch.empty((K, M), dtype=torch.float64).pin_memory()
+        Ph = torch.empty((K, N), dtype=torch.float64).pin_memory()
+        reps = 3 if M * N <= 32e6 else 2
+        row = {"M": M, "N": N}
+        for algo in ("gs", "nipals"):
+            def run():
+                return gp.fit(Xd, K, tol=tol, max_iter=max_iter, algo=algo, init="column_k",
+                              check=False)
+
+            def run_h2d():
+                Xd.copy_(Xh, non_blocking=True)
+                out = run()
+                Th.copy_(out["T"].t(), non_blocking=True)
+                Ph.copy_(out["P"].t(), non_blocking=True)
+                return out
+            out, ms = _events_ms(run, reps)
+            _, ms_h2d = _events_ms(run_h2d, reps)
+            its = out["iters"].cpu().numpy()
+            P = out["P"].double()
+            sig = out["sigma"].double()
+            V = out["T"].double() / torch.where(sig > 0, sig, torch.ones_like(sig))
+            eye = torch.eye(K, dtype=torch.float64, device="cuda")
+            row[algo] = {"ms": ms, "ms_with_transfer": ms_h2d, "status": int(out["status"]),
+                         "iters_total": int(its.sum()), "us_per_iteration": ms * 1e3 / its.sum(),
+                         "orth_P": float((P.T @ P - eye).abs().max()),
+                         "orth_V": float((V.T @ V - eye).abs().max())}
+            if not args.no_cpu_baseline and M <= args.sweep_cpu_max:
+                t0 = time.perf_counter()
+                o = oracle.fit(X, K, tol=tol, max_iter=max_iter, algo=algo, init="column_k")
+                dt = time.perf_counter() - t0
+                row[algo]["cpu_oracle_ms"] = dt * 1e3
+                row[algo]["cpu_oracle_iters_total"] = int(o.iters.sum())
+                row[algo]["cpu_over_gpu_with_transfer"] = dt * 1e3 / ms_h2d
+            if M == sizes[0]:
+                # parity on the same trajectory (replayed counts and columns)
+                o = oracle.fit(X, K, tol=0.0, max_iter=int(its.max()), algo=algo,
+                               replay_iters=its, replay_start=out["start_col"].cpu().numpy())
+                Pg = out["P"].cpu().numpy()
+                sgn = np.sign(np.sum(Pg * o.P, axis=0))
+                ang = 2 * np.arcsin(np.minimum(np.linalg.norm(Pg - o.P * sgn, axis=0) / 2, 1.0))
+                row[algo]["max_loading_angle_vs_oracle"] = float(ang.max())
+            log("sweep M=%d %s: %.2f ms (%.2f with transfer), %d iterations" % (
+                M, algo, ms, ms_h2d, int(its.sum())))
+        row["gs_over_nipals"] = row["gs"]["ms"] / row["nipals"]["ms"] - 1.0
+        row["gs_over_nipals_per_iteration"] = (row["gs"]["us_per_iteration"] /
+                                               row["nipals"]["us_per_iteration"] - 1.0)
+        rows.append(row)
+        del Xd, Xh
+        torch.cuda.empty_cache()
+    big = rows[-1]
+    res = {"metric": "GS-PCA ms per fit, the paper's FP64 sweep (uniform, N = M/2, K = 10)",
+           "value": big["gs"]["ms"], "unit": "ms", "n_gpus": 1, "steps": 1, "warmup": 1,
+           "ms_per_step": big["gs"]["ms"], "higher_is_better": False, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f64", "data": "synthetic",
+           "config": {"workload": "paper_sweep_f64_uniform_rowcentred", "sizes": sizes, "K": K,
+                      "tol": tol, "max_iter": max_iter, "init": "column_k"},
+           "roofline": None, "cpu_baseline": None, "sweep": rows}
+    cpu_rows = [r for r in rows if "cpu_oracle_ms" in r["gs"]]
+    if cpu_rows:
+        r = cpu_rows[-1]
+        res["cpu_baseline"] = {"value": r["gs"]["cpu_oracle_ms"], "unit": "ms", "cores": 1,
+                               "kind": "oracle",
+                               "sample": "full FP64 oracle GS-PCA fit at M=%d, N=%d" % (r["M"], r["N"])}
+    print(json.dumps(res), flush=True)
+
+
 def bench_collinear(args):
     """4096 x 512 FP32 full rank (s_i = 0.9^i + 1e-4 noise, centred), K = N =
     512, tol 1e-6, max_iter 1000: GS-PCA vs NIPALS orthogonality and
@@ -430,14 +518,19 @@ def main():
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "batched", "small", "collinear"],
+                    choices=["large", "batched", "small", "collinear", "paper_sweep"],
                     help="large: the 65536 x 8192 fit (default); batched: 2048 uneven "
-                         "problems; small: 512 x 128 FP64; collinear: 4096 x 512 FP32, K = N")
+                         "problems; small: 512 x 128 FP64; collinear: 4096 x 512 FP32, K = N; "
+                         "paper_sweep: the paper's FP64 timing sweep (uniform, N = M/2, K = 10)")
     ap.add_argument("--batch-count", type=int, default=2048)
+    ap.add_argument("--sweep-sizes", default="500,1000,2000,4000,8000,15000",
+                    help="row counts M of the paper sweep (N = M/2)")
+    ap.add_argument("--sweep-cpu-max", type=int, default=2000,
+                    help="largest M of the paper sweep at which the oracle is timed")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X and has no "
-              "multi-GPU path (--gpus %d requested)" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
     if args.workload == "batched":
         bench_batched(args)
@@ -447,6 +540,9 @@ def main():
         return
     if args.workload == "collinear":
         bench_collinear(args)
+        return
+    if args.workload == "paper_sweep":
+        bench_paper_sweep(args)
         return
 
     import numpy as np

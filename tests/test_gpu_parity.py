@@ -182,6 +182,37 @@ def test_two_pass_path_wide(orc, algo):
     assert np.abs(g["sigma"] / o.sigma - 1).max() <= 1e-5
 
 
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_paper_sweep_f64_parity(orc, algo):
+    """The paper's timing data (Sec. 4: uniform entries, rows centred,
+    N = M/2, K = 10, tol 1e-7, start column k) on the fused FP64 path, on the
+    oracle's trajectory.  The spectrum is flat (gaps ~1 %), so the angle
+    bound applies to components with a relative gap >= 1 %."""
+    from paper_0811_1081_amd import synth
+    X = synth.uniform_paper(500, 250, seed=(6, 500))
+    K = 10
+    g = _gh().gpu_fit(X, K, tol=1e-7, max_iter=10000, algo=algo, init="column_k")
+    assert np.all(g["start_col"] == np.arange(K))
+    o = _replayed(orc, X, g, K, algo)
+    ok = _gapped(o.sigma, 0.01)
+    assert ok.any()
+    assert col_angles(g["P"], o.P)[ok].max() <= 1e-9
+    assert np.abs(g["sigma"] - o.sigma).max() <= 1e-12 * o.sigma[0]
+
+
+@pytest.mark.parametrize("algo", ["gs", "nipals"])
+def test_two_pass_path_f64(orc, algo):
+    """FP64 with N > 4096 runs the two-pass kernels (the large sizes of the
+    paper's sweep, N = M/2 up to 7500, take this path)."""
+    from paper_0811_1081_amd import synth
+    X = synth.haar_spectrum(600, 4100, 0.8 ** np.arange(30), 1e-6, seed=(11, 1))
+    K = 5
+    g = _gh().gpu_fit(X, K, tol=1e-10, max_iter=3000, algo=algo)
+    o = _replayed(orc, X, g, K, algo)
+    assert col_angles(g["P"], o.P).max() <= 1e-10
+    assert np.abs(g["sigma"] / o.sigma - 1).max() <= 1e-12
+
+
 # --------------------------------------------------------------------------
 # Start-vector modes, replay, determinism.
 

@@ -334,3 +334,33 @@ def test_loading_stop_accuracy_bound(orc):
         b = orc.fit(X, 1, tol=0.0, max_iter=j - 1)
         assert angle(a.P[:, 0], b.P[:, 0]) >= tol * 0.999
         assert angle(b.P[:, 0], f.P[:, 0]) < tol
+
+
+def test_paper_sweep_data_and_bounds(orc):
+    """The paper's timing data (Sec. 4): uniform [0, 1) entries with each row
+    centred.  On it the oracle (start column k, tol 1e-7, the paper's
+    settings) must stop within the power-iteration bound of the exact
+    singular values: after the relative sigma test, the remaining rise of
+    sigma is about tol * rho / (1 - rho) with rho = (s_(k+1) / s_k)^2 the
+    contraction per iteration, and to first order the error an earlier
+    component leaves in the residual adds to the later ones (so the bound of
+    component k is the sum over components <= k); GS-PCA and NIPALS follow
+    the same trajectory (same counts) and GS keeps P orthonormal."""
+    from paper_0811_1081_amd import synth
+    X = synth.uniform_paper(160, 80, seed=(6, 160))
+    raw = synth.uniform_paper(160, 80, seed=(6, 160), centre_rows=False)
+    assert np.array_equal(X, synth.uniform_paper(160, 80, seed=(6, 160)))
+    assert raw.min() >= 0.0 and raw.max() < 1.0 and abs(raw.mean() - 0.5) < 0.01
+    assert np.abs(X.mean(axis=1)).max() <= 1e-15
+    assert np.allclose(X, raw - raw.mean(axis=1, keepdims=True), rtol=0, atol=1e-15)
+    s = np.linalg.svd(X, compute_uv=False)
+    K, tol = 10, 1e-7
+    fits = {a: orc.fit(X, K, tol=tol, max_iter=10000, algo=a, init="column_k")
+            for a in ("gs", "nipals")}
+    assert np.array_equal(fits["gs"].iters, fits["nipals"].iters)
+    rho = (s[1:K + 1] / s[:K]) ** 2
+    bound = np.cumsum(2 * tol / (1 - rho))
+    for a, f in fits.items():
+        assert np.all(np.abs(f.sigma / s[:K] - 1) <= bound), a
+        assert np.all(f.start_col == np.arange(K)), a
+    assert np.abs(fits["gs"].P.T @ fits["gs"].P - np.eye(K)).max() <= 1e-12
