@@ -76,6 +76,21 @@ typedef enum {
 
 typedef enum { GSPCA_GS = 0, GSPCA_NIPALS = 1 } gspca_algo;
 
+/* Form of GS-PCA's two Gram-Schmidt steps per iteration (Sec. 2.3 uses one
+ * classical pass; the other two are re-orthogonalisation variants for
+ * studying the loss of orthogonality, not in the paper):
+ *   CGS:  x <- x - Q (Q^T x), one pass (the paper's; default).
+ *   CGS2: the classical pass applied twice, each with coefficients from the
+ *         vector as it enters that pass.
+ *   MGS:  modified Gram-Schmidt: for i = 0 .. k-1 in order, the coefficient
+ *         of column i is taken from the vector already reduced by columns
+ *         0 .. i-1.
+ * CGS2 and MGS run on the two-pass path (t and p formed explicitly every
+ * iteration) with explicit deflation, FP32/FP64 data; MGS does its k steps
+ * inside one workgroup per side, so it is meant for moderate sizes.  NIPALS
+ * has no Gram-Schmidt step and ignores the field. */
+typedef enum { GSPCA_REORTH_CGS = 0, GSPCA_REORTH_CGS2 = 1, GSPCA_REORTH_MGS = 2 } gspca_reorth;
+
 typedef enum {
     GSPCA_INIT_MAXNORM = 0,  /* largest-norm residual column (default)        */
     GSPCA_INIT_COLUMN_K = 1, /* column k of the residual (the pseudo-code's R^(k)) */
@@ -133,6 +148,9 @@ typedef struct {
     const int32_t *replay_iters;
     const int32_t *replay_start_col;
     gspca_profile *profile; /* host pointer, nullable (see gspca_profile)      */
+    int32_t reorth;     /* gspca_reorth (GS-PCA; 0 = the paper's single pass;
+                           others need explicit deflation and F64/F32 data)   */
+    int32_t reserved;
 } gspca_options;
 
 /* Outputs (device pointers).  T, P and lambda are required. */
@@ -219,7 +237,8 @@ size_t gspca_batched_workspace_bytes(const gspca_batch_problem *probs, int32_t n
 /* Validate the problems (host array of descriptors), write the descriptor
  * table -- sorted by decreasing M*N so that the queue hands out the largest
  * problems first -- into `ws`, and fill `plan` with a default launch shape.
- * Synchronises `stream`.  Not capturable. */
+ * Options: GS-PCA, explicit form, opt->reorth == GSPCA_REORTH_CGS (else
+ * GSPCA_EINVAL).  Synchronises `stream`.  Not capturable. */
 gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t nprob,
                                    const gspca_options *opt, void *ws, size_t ws_bytes,
                                    gspca_batch_plan *plan, void *stream);

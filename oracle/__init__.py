@@ -55,8 +55,10 @@ def lib() -> ctypes.CDLL:
             vp = ctypes.c_void_p
             L.oracle_fit.restype = ctypes.c_int
             L.oracle_fit.argtypes = [ctypes.c_int, ctypes.c_int, vp, i64, i64, i64, i64, dbl, i32,
-                                     ctypes.c_int, vp, vp, vp, dbl, ctypes.c_int, vp, vp, vp, vp,
-                                     vp, vp]
+                                     ctypes.c_int, vp, vp, vp, dbl, ctypes.c_int, ctypes.c_int,
+                                     vp, vp, vp, vp, vp, vp]
+            L.oracle_gs_step.restype = ctypes.c_int
+            L.oracle_gs_step.argtypes = [vp, i64, i64, vp, ctypes.c_int]
             L.oracle_score_step.restype = ctypes.c_int
             L.oracle_score_step.argtypes = [vp, i64, i64, i64, i64, vp, vp, vp, vp, vp, vp]
             L.oracle_jacobi_eig.restype = ctypes.c_int
@@ -114,11 +116,13 @@ class Fit:
 
 def fit(X, K, tol=1e-10, max_iter=1000, algo="gs", implicit=False, init="maxnorm",
         T0=None, replay_iters=None, replay_start=None, tiny=DBL_MIN, want_R=False,
-        stop="sigma") -> Fit:
+        stop="sigma", reorth="cgs") -> Fit:
     """Run NIPALS-PCA (algo='nipals') or GS-PCA (algo='gs') in FP64.
 
     ``stop`` is "sigma" (the relative test of the paper's programs) or
-    "loading" (stop when the unit loading moved less than tol).
+    "loading" (stop when the unit loading moved less than tol).  ``reorth``
+    is the form of GS-PCA's two Gram-Schmidt steps: "cgs" (one classical
+    pass, the paper's), "cgs2" (two classical passes) or "mgs" (modified).
 
     X is widened to float64 (an FP32 input is consumed exactly).  ``replay_iters``
     forces the number of iterations per component and ``replay_start`` the start
@@ -138,10 +142,24 @@ def fit(X, K, tol=1e-10, max_iter=1000, algo="gs", implicit=False, init="maxnorm
     rs = np.ascontiguousarray(replay_start, dtype=np.int32) if replay_start is not None else None
     st = lib().oracle_fit(algo_i, int(bool(implicit)), _ptr(X), M, N, M, K, float(tol),
                           int(max_iter), init_i, _ptr(T0a), _ptr(ri), _ptr(rs), float(tiny),
-                          {"sigma": 0, "loading": 1}[stop],
+                          {"sigma": 0, "loading": 1}[stop], REORTH[reorth],
                           _ptr(T), _ptr(P), _ptr(sigma), _ptr(iters), _ptr(start), _ptr(R))
     return Fit(T=T, P=P, sigma=sigma, lam=sigma ** 2, iters=iters, start_col=start,
                status=st, R=R, algo=algo)
+
+
+REORTH = {"cgs": 0, "cgs2": 1, "mgs": 2}
+
+
+def gs_step(Q, x, reorth="cgs"):
+    """One Gram-Schmidt step of x against the columns of Q in the chosen form
+    (see ``fit``); returns the reduced vector."""
+    Q = _f64_fortran(np.asarray(Q, dtype=np.float64).reshape(len(x), -1))
+    xv = np.array(x, dtype=np.float64)
+    st = lib().oracle_gs_step(_ptr(Q), Q.shape[0], Q.shape[1], _ptr(xv), REORTH[reorth])
+    if st != OK:
+        raise ValueError("oracle_gs_step failed: %d" % st)
+    return xv
 
 
 def score_step(X, k, V, sigma, P, p):

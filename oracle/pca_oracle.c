@@ -43,6 +43,13 @@
  *   - implicit deflation (not in the paper): R is never formed; products use
  *     R p = X p - T (P^T p) and R^T t = X^T t - P (T^T t), identical in exact
  *     arithmetic.
+ *   - re-orthogonalisation (not in the paper, which uses one classical pass;
+ *     optional): the iteration's two Gram-Schmidt steps may instead run two
+ *     classical passes (CGS2, each pass with coefficients from the vector as
+ *     it enters that pass) or the modified process (MGS: for i = 0, 1, ...,
+ *     the coefficient of column i is taken from the vector already reduced
+ *     by columns 0..i-1).  The start-vector test and the degenerate rule
+ *     keep one classical pass.
  *
  * Arithmetic: FP64, sequential loops in increasing index order; build with
  * -O2 -fno-fast-math -ffp-contract=off.  Matrices are column-major:
@@ -67,6 +74,10 @@
 #define OR_INIT_MAXNORM 0
 #define OR_INIT_COLUMN_K 1
 #define OR_INIT_GIVEN 2
+
+#define OR_REORTH_CGS 0
+#define OR_REORTH_CGS2 1
+#define OR_REORTH_MGS 2
 
 /* ------------------------------------------------------------------ */
 /* Level-1 helpers (plain loops).                                      */
@@ -194,6 +205,37 @@ static void cgs_pass(const double *Q, int64_t n, int64_t k, double *x, double *c
     }
 }
 
+/* The iteration's Gram-Schmidt step in the chosen form: one classical pass
+ * (the paper's), two classical passes, or the modified process. */
+static void gs_step(const double *Q, int64_t n, int64_t k, double *x, double *coef, int reorth)
+{
+    if (reorth == OR_REORTH_MGS) {
+        for (int64_t i = 0; i < k; ++i) {
+            const double c = dot(Q + i * n, x, n);
+            for (int64_t m = 0; m < n; ++m)
+                x[m] -= Q[m + i * n] * c;
+        }
+        return;
+    }
+    cgs_pass(Q, n, k, x, coef);
+    if (reorth == OR_REORTH_CGS2)
+        cgs_pass(Q, n, k, x, coef);
+}
+
+/* One Gram-Schmidt step of the vector x (n) against the k columns of Q (n x
+ * k, leading dimension n), in place, in the chosen form (for the tests). */
+int oracle_gs_step(const double *Q, int64_t n, int64_t k, double *x, int reorth)
+{
+    if (!Q || !x || n < 1 || k < 0 || reorth < OR_REORTH_CGS || reorth > OR_REORTH_MGS)
+        return OR_EINVAL;
+    double *coef = malloc((size_t)(k + 1) * sizeof(double));
+    if (!coef)
+        return OR_EINVAL;
+    gs_step(Q, n, k, x, coef, reorth);
+    free(coef);
+    return OR_OK;
+}
+
 /* Loading for a degenerate component: first e_i whose residual against P_(k)
  * has squared norm >= (N-k)/(2N), after one Gram-Schmidt pass, normalised. */
 static void degenerate_loading(const double *P, int64_t N, int64_t k, double *p, double *coef)
@@ -224,7 +266,7 @@ int oracle_fit(int algo, int implicit,
                const double *X, int64_t M, int64_t N, int64_t ldx, int64_t K,
                double tol, int32_t max_iter, int init, const double *T0,
                const int32_t *replay_iters, const int32_t *replay_start,
-               double tiny, int stop,
+               double tiny, int stop, int reorth,
                double *T, double *P, double *sigma, int32_t *iters, int32_t *start_col,
                double *R_out)
 {
@@ -235,6 +277,8 @@ int oracle_fit(int algo, int implicit,
     if (algo != OR_ALGO_GS && algo != OR_ALGO_NIPALS)
         return OR_EINVAL;
     if (stop != OR_STOP_SIGMA && stop != OR_STOP_LOADING)
+        return OR_EINVAL;
+    if (reorth < OR_REORTH_CGS || reorth > OR_REORTH_MGS)
         return OR_EINVAL;
     if (init == OR_INIT_GIVEN && !T0)
         return OR_EINVAL;
@@ -325,7 +369,7 @@ int oracle_fit(int algo, int implicit,
             resid_t_mul(&op, t, p);
             /* GS-PCA: A <- U_(k)^T U^(k); U^(k) <- U^(k) - U_(k) A */
             if (gs && k > 0)
-                cgs_pass(P, N, k, p, coef);
+                gs_step(P, N, k, p, coef, reorth);
             /* normalise the loading */
             const double pn = nrm2(p, N);
             if (!(pn >= tiny)) { degenerate = 1; break; }
@@ -346,7 +390,7 @@ int oracle_fit(int algo, int implicit,
             resid_mul(&op, p, t);
             /* GS-PCA: B <- V_(k)^T V^(k); V^(k) <- V^(k) - V_(k) B */
             if (gs && k > 0)
-                cgs_pass(T, M, k, t, coef);
+                gs_step(T, M, k, t, coef, reorth);
             /* eigenvalue estimate = score norm */
             s = nrm2(t, M);
             if (!(s >= tiny)) { degenerate = 1; break; }

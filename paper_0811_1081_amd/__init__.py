@@ -25,6 +25,7 @@ __all__ = ["fit", "quantize", "Quantized", "Batch", "workspace_bytes", "column_m
 _ALGOS = {"gs": GS, "nipals": NIPALS}
 _INITS = {"maxnorm": INIT_MAXNORM, "column_k": INIT_COLUMN_K, "given": INIT_GIVEN}
 _STOPS = {"sigma": STOP_SIGMA_REL, "loading": STOP_LOADING}
+_REORTHS = {"cgs": 0, "cgs2": 1, "mgs": 2}
 _FMTS = {"bf16": BF16, "e4m3": FP8_E4M3}
 
 
@@ -97,8 +98,9 @@ def _problem(X, K):
 
 
 def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start=None,
-             implicit=False, stop="sigma"):
+             implicit=False, stop="sigma", reorth="cgs"):
     o = _b.Options()
+    o.reorth = _REORTHS[reorth]
     o.algo = _ALGOS[algo]
     o.init = _INITS[init]
     o.implicit_deflation = 1 if implicit else 0
@@ -112,11 +114,11 @@ def _options(algo, init, tol, max_iter, T0=None, replay_iters=None, replay_start
 
 
 def workspace_bytes(X, K, algo="gs", init="maxnorm", tol=1e-7, max_iter=10000,
-                    implicit=False, stop="sigma") -> int:
+                    implicit=False, stop="sigma", reorth="cgs") -> int:
     L = _b.load()
     pr = _problem(X, K)
     op = _options(algo, init, tol, max_iter, implicit=implicit or isinstance(X, Quantized),
-                  stop=stop)
+                  stop=stop, reorth=reorth)
     return int(L.gspca_workspace_bytes(pr, op))
 
 
@@ -129,7 +131,7 @@ def _workspace(nbytes, device):
 
 def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         replay_iters=None, replay_start=None, workspace=None, stream=None, check=True,
-        profile=None, implicit=False, stop="sigma"):
+        profile=None, implicit=False, stop="sigma", reorth="cgs"):
     """Fit K components of the column-major device matrix X (M x N).
 
     Returns a dict of device tensors: T (M x K), P (N x K) (column-major, dtype
@@ -139,8 +141,10 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
     column.  ``implicit`` selects implicit deflation (X is never modified,
     GS-PCA only; always on for a Quantized X, whose outputs are float32).
     ``stop`` is "sigma" (the paper's relative test) or "loading" (the unit
-    loading moved less than tol).  Raises GspcaError on a negative status when
-    ``check``."""
+    loading moved less than tol).  ``reorth`` is the form of GS-PCA's
+    Gram-Schmidt steps: "cgs" (one classical pass, the paper's), "cgs2" (two
+    passes) or "mgs" (modified); the last two need explicit deflation and
+    F32/F64 data.  Raises GspcaError on a negative status when ``check``."""
     import torch
     L = _b.load()
     quant = isinstance(X, Quantized)
@@ -159,7 +163,8 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
                               or not a.is_contiguous()):
             raise ValueError(name + " must be a contiguous int32 device tensor of length K")
     pr = _problem(X, K)
-    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start, implicit, stop)
+    op = _options(algo, init, tol, max_iter, T0, replay_iters, replay_start, implicit, stop,
+                  reorth)
     if profile is not None:
         op.profile = ctypes.addressof(profile)
     T = torch.empty_strided((M, K), (1, M), dtype=out_dtype, device=dev)

@@ -50,7 +50,8 @@ class Options(ctypes.Structure):
                 ("T0", ctypes.c_void_p),
                 ("tol", ctypes.c_double), ("max_iter", ctypes.c_int32),
                 ("replay_iters", ctypes.c_void_p), ("replay_start_col", ctypes.c_void_p),
-                ("profile", ctypes.c_void_p)]
+                ("profile", ctypes.c_void_p), ("reorth", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
 
 
 class Profile(ctypes.Structure):

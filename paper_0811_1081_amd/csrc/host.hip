@@ -120,6 +120,13 @@ gspca_status validate(const gspca_problem *pr, const gspca_options *op)
     if (op->implicit_deflation &&
         (op->algo != GSPCA_GS || pr->N > (pr->dtype == GSPCA_F64 ? 4096 : 8192)))
         return GSPCA_EINVAL;
+    if (op->reorth != GSPCA_REORTH_CGS && op->reorth != GSPCA_REORTH_CGS2 &&
+        op->reorth != GSPCA_REORTH_MGS)
+        return GSPCA_EINVAL;
+    // the re-orthogonalisation variants run on the two-pass path
+    if (op->reorth != GSPCA_REORTH_CGS && op->algo == GSPCA_GS &&
+        (op->implicit_deflation || is_quantised(pr->dtype)))
+        return GSPCA_EINVAL;
     return GSPCA_OK;
 }
 
@@ -210,6 +217,28 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
         return hipStreamSynchronize(s) == hipSuccess;
     };
 
+    // Gram-Schmidt coefficients of one side (the vector y = sum of the
+    // partials against the k columns of Q).  CGS: c = Q^T y.  CGS2: the first
+    // pass y <- y - Q (Q^T y) in place, then c = Q^T y for the second pass.
+    // MGS: y fully reduced in place by the modified process (the final apply
+    // then runs with no columns).  The apply kernel finishes the step.
+    const int reorth = gs ? op->reorth : GSPCA_REORTH_CGS;
+    auto gs_side = [&](const double *part, int nsplit, int64_t ldpart, int64_t Lv, double *y,
+                       const E *Q, int64_t ldq, int kq, double *cp, double *cv, int counter,
+                       hipStream_t st_) {
+        if (kq == 0)
+            return;
+        if (reorth == GSPCA_REORTH_MGS) {
+            L::mgs(part, nsplit, ldpart, Lv, Q, ldq, kq, y, st, st_);
+            return;
+        }
+        L::gs_dot(part, nsplit, ldpart, Lv, Q, ldq, kq, y, cp, cv, st, counter, st_);
+        if (reorth == GSPCA_REORTH_CGS2) {
+            L::gs_project(y, Lv, Q, ldq, kq, cv, st, st_);
+            L::gs_dot(y, 1, Lv, Lv, Q, ldq, kq, nullptr, cp, cv, st, counter, st_);
+        }
+    };
+
     if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
         return GSPCA_EDEVICE;
     L::copy_pad(X, pr->ldx, R, pl.ldr, M, N, st, s);
@@ -237,19 +266,28 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
                 L::gemv_t(R, pl.ldr, N, t, pl.rows_per_split, pl.nsplit_t, pl.ncolblk, qpart, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[4 * i + 1], s);
-                if (kk > 0)
-                    L::gs_dot(qpart, pl.nsplit_t, N, N, P, N, kk, qy, cpart, c, st, kCntDotN, s);
-                L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, pprev, nullptr, sq, st, 0,
-                            tol, limit, replay, tiny, op->stop, s);
+                // GS on the loading: p <- q - P_(k) c (one pass, two passes or
+                // the modified process), then |p| and the loading stop
+                gs_side(qpart, pl.nsplit_t, N, N, qy, P, N, kk, cpart, c, kCntDotN, s);
+                if (kk > 0 && reorth != GSPCA_REORTH_CGS)
+                    L::gs_apply(qy, 1, N, N, qy, P, N, reorth == GSPCA_REORTH_MGS ? 0 : kk, c, p,
+                                pprev, nullptr, sq, st, 0, tol, limit, replay, tiny, op->stop, s);
+                else
+                    L::gs_apply(qpart, pl.nsplit_t, N, N, qy, P, N, kk, c, p, pprev, nullptr, sq,
+                                st, 0, tol, limit, replay, tiny, op->stop, s);
                 if (prof)
                     (void)hipEventRecord(ev[4 * i + 2], s);
                 L::gemv_n(R, pl.ldr, N, p, pl.cols_per_split, pl.nsplit_n, tpart, st, s);
                 if (prof)
                     (void)hipEventRecord(ev[4 * i + 3], s);
-                if (kk > 0)
-                    L::gs_dot(tpart, pl.nsplit_n, pl.ldr, M, T, M, kk, ty, cpart, c, st, kCntDotM, s);
-                L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, nullptr, t, sq,
-                            st, 1, tol, limit, replay, tiny, op->stop, s);
+                gs_side(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, cpart, c, kCntDotM, s);
+                if (kk > 0 && reorth != GSPCA_REORTH_CGS)
+                    L::gs_apply(ty, 1, M, M, ty, T, M, reorth == GSPCA_REORTH_MGS ? 0 : kk, c,
+                                nullptr, nullptr, t, sq, st, 1, tol, limit, replay, tiny, op->stop,
+                                s);
+                else
+                    L::gs_apply(tpart, pl.nsplit_n, pl.ldr, M, ty, T, M, kk, c, nullptr, nullptr, t,
+                                sq, st, 1, tol, limit, replay, tiny, op->stop, s);
             }
             enq += n;
             if (!read_state())
@@ -396,8 +434,10 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
 // FP64 panels hold 2 rows per 16 bytes, so twice the registers per column:
 // the single-pass path takes N <= 8192 (N <= 4096 for FP64).  Quantised data
 // always runs it.
-bool use_fused(const gspca_problem *pr)
+bool use_fused(const gspca_problem *pr, const gspca_options *op)
 {
+    if (op->algo == GSPCA_GS && op->reorth != GSPCA_REORTH_CGS)
+        return false; // t and p are formed explicitly on the two-pass path
     return pr->N <= (pr->dtype == GSPCA_F64 ? kFusedMaxN / 2 : kFusedMaxN);
 }
 
@@ -571,9 +611,9 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     return h.not_converged ? GSPCA_NOT_CONVERGED : GSPCA_OK;
 }
 
-size_t workspace_for(const gspca_problem *pr)
+size_t workspace_for(const gspca_problem *pr, const gspca_options *op)
 {
-    if (use_fused(pr))
+    if (use_fused(pr, op))
         return make_fused_plan(pr->M, pr->N, pr->K, fmt_of(pr->dtype), device_cu_count()).total;
     return make_plan(pr->M, pr->N, pr->K, dtype_size(pr->dtype)).total;
 }
@@ -597,7 +637,7 @@ size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt
 {
     if (validate(prob, opt) != GSPCA_OK)
         return 0;
-    return workspace_for(prob);
+    return workspace_for(prob, opt);
 }
 
 gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
@@ -609,7 +649,7 @@ gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
     if (!res || !res->T || !res->P || !res->lambda)
         return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
-    if (use_fused(prob)) {
+    if (use_fused(prob, opt)) {
         switch (prob->dtype) {
         case GSPCA_F64: return fit_fused<kFmtF64>(prob, opt, res, ws, ws_bytes, s);
         case GSPCA_F32: return fit_fused<kFmtF32>(prob, opt, res, ws, ws_bytes, s);

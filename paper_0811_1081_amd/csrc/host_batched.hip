@@ -162,6 +162,8 @@ gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t npr
     if (!(opt->tol >= 0.0) || !isfinite(opt->tol) || opt->max_iter < 1 ||
         (opt->stop != GSPCA_STOP_SIGMA_REL && opt->stop != GSPCA_STOP_LOADING))
         return GSPCA_EINVAL;
+    if (opt->reorth != GSPCA_REORTH_CGS) // one classical pass only
+        return GSPCA_EINVAL;
     for (int32_t i = 0; i < nprob; ++i)
         if (!valid_problem(probs[i]))
             return GSPCA_EINVAL;

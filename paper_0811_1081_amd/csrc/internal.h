@@ -206,6 +206,13 @@ struct Launch {
                          double *ydst, double *yprev, E *edst, double *sqpart, LoopState *st,
                          int side, double tol, int32_t limit, int replay, double tiny, int stop,
                          hipStream_t s);
+    // y <- y - Q c (FP64, in place; the first pass of CGS2)
+    static void gs_project(double *y, int64_t L, const E *Q, int64_t ldq, int k, const double *c,
+                           LoopState *st, hipStream_t s);
+    // y <- sum of the partials, reduced by the modified Gram-Schmidt process
+    // against the k columns of Q (one workgroup)
+    static void mgs(const double *part, int nsplit, int64_t ldpart, int64_t L, const E *Q,
+                    int64_t ldq, int k, double *y, LoopState *st, hipStream_t s);
     static void degenerate_p(const E *P, int64_t N, int k, double *p, LoopState *st, hipStream_t s);
     static void finalize_comp(const E *t, int64_t M, int64_t N, const double *p, int k, int gs,
                               E *T, E *P, double *sigma, int32_t *iters, int32_t *start_col,

@@ -493,6 +493,82 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
     score_test(st, nrm, tol, limit, replay, tiny, stop);
 }
 
+// First pass of the doubled classical form (CGS2): y <- y - Q c in place
+// (FP64), c = Q^T y from gs_dot; the second pass is gs_dot + gs_apply on y.
+template <typename E>
+__global__ __launch_bounds__(kBlock) void k_gs_project(double *__restrict__ y, int64_t L,
+                                                       const E *__restrict__ Q, int64_t ldq,
+                                                       int k, const double *__restrict__ c,
+                                                       const LoopState *st)
+{
+    if (st->done)
+        return;
+    __shared__ double cs[1024];
+    const int64_t r = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    double proj = 0.0;
+    for (int i0 = 0; i0 < k; i0 += 1024) {
+        const int n = min(1024, k - i0);
+        __syncthreads();
+        for (int i = threadIdx.x; i < n; i += kBlock)
+            cs[i] = c[i0 + i];
+        __syncthreads();
+        if (r < L)
+            for (int i = 0; i < n; ++i)
+                proj += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
+    }
+    if (r < L)
+        y[r] -= proj;
+}
+
+// Modified Gram-Schmidt (the MGS form of the step), one workgroup: y = sum of
+// the nsplit partial vectors, then for i = 0 .. k-1 in order c_i = q_i^T y
+// and y <- y - c_i q_i, each coefficient from the vector already reduced by
+// the earlier columns.  Every thread owns the entries r = tid + 1024 j, so y
+// needs no barrier; each coefficient is a fixed-order workgroup sum (wave
+// butterflies, then the 16 waves in order), and the update by column i is
+// fused with the dot product for column i + 1.
+constexpr int kMgsThreads = 1024;
+template <typename E>
+__global__ __launch_bounds__(kMgsThreads) void k_mgs(const double *__restrict__ part, int nsplit,
+                                                     int64_t ldpart, int64_t L,
+                                                     const E *__restrict__ Q, int64_t ldq, int k,
+                                                     double *__restrict__ y, const LoopState *st)
+{
+    if (st->done)
+        return;
+    constexpr int NW = kMgsThreads / 64;
+    __shared__ double red[NW];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    double acc = 0.0;
+    for (int64_t r = tid; r < L; r += kMgsThreads) {
+        double v = 0.0;
+        for (int s = 0; s < nsplit; ++s)
+            v += part[(int64_t)s * ldpart + r];
+        y[r] = v;
+        acc += (double)Q[r] * v; // column 0
+    }
+    for (int i = 0; i < k; ++i) {
+        const double ws = wave_sum(acc);
+        __syncthreads(); // the previous coefficient has been read by every thread
+        if (lane == 0)
+            red[w] = ws;
+        __syncthreads();
+        double ci = 0.0;
+        for (int q = 0; q < NW; ++q)
+            ci += red[q];
+        const E *qi = Q + (int64_t)i * ldq;
+        const E *qn = Q + (int64_t)(i + 1 < k ? i + 1 : i) * ldq;
+        const bool more = i + 1 < k;
+        acc = 0.0;
+        for (int64_t r = tid; r < L; r += kMgsThreads) {
+            const double v = y[r] - (double)qi[r] * ci;
+            y[r] = v;
+            if (more)
+                acc += (double)qn[r] * v;
+        }
+    }
+}
+
 // Degenerate component: the first unit vector whose Gram-Schmidt residual
 // against P_(k) has squared norm >= (N-k)/(2N), normalised, into p (FP64).
 // Rare path: one workgroup, candidates tried in ascending order.
@@ -668,6 +744,22 @@ void Launch<E>::gs_apply(const double *part, int nsplit, int64_t ldpart, int64_t
     hipLaunchKernelGGL(k_gs_apply<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, part, nsplit,
                        ldpart, L, y, Q, ldq, k, c, ydst, yprev, edst, sqpart, st, side, tol, limit,
                        replay, tiny, stop);
+}
+
+template <typename E>
+void Launch<E>::gs_project(double *y, int64_t L, const E *Q, int64_t ldq, int k, const double *c,
+                           LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_gs_project<E>, dim3(ceil_div(L, kBlock)), dim3(kBlock), 0, s, y, L, Q,
+                       ldq, k, c, st);
+}
+
+template <typename E>
+void Launch<E>::mgs(const double *part, int nsplit, int64_t ldpart, int64_t L, const E *Q,
+                    int64_t ldq, int k, double *y, LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_mgs<E>, dim3(1), dim3(kMgsThreads), 0, s, part, nsplit, ldpart, L, Q, ldq,
+                       k, y, st);
 }
 
 template <typename E>
