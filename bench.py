@@ -451,6 +451,54 @@ def bench_paper_sweep(args):
     print(json.dumps(res), flush=True)
 
 
+def bench_orthogonality(args):
+    """Loss of orthogonality against the component index (the paper's claim
+    about NIPALS, Secs. 2.2-2.3, with the re-orthogonalisation variants as
+    the comparison): 4096 x 512 FP32 full-rank collinear data (s_i = 0.9^i,
+    1e-4 noise, centred), tol 1e-6, max_iter 1000, NIPALS and GS-PCA with one
+    classical pass (the paper's), two passes and modified Gram-Schmidt;
+    max |P_k^T P_k - I| and max |V_k^T V_k - I| over the first k components."""
+    import numpy as np
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    gp.load()
+    X = synth.case_collinear_f32()
+    Xd = gp.column_major(torch.from_numpy(X).cuda())
+    M, N = X.shape
+    K = args.ortho_k
+    ks = [k for k in (8, 16, 32, 64, 128, 256, 512) if k <= K]
+    forms = [("nipals", "cgs"), ("gs", "cgs"), ("gs", "cgs2"), ("gs", "mgs")]
+    out = {}
+    for algo, reorth in forms:
+        name = algo if algo == "nipals" else "gs_" + reorth
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        r = gp.fit(Xd, K, tol=1e-6, max_iter=1000, algo=algo, reorth=reorth, check=False)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        P = r["P"].double()
+        sig = r["sigma"].double()
+        V = r["T"].double() / torch.where(sig > 0, sig, torch.ones_like(sig))
+        GP, GV = P.T @ P, V.T @ V
+        eye = torch.eye(K, dtype=torch.float64, device="cuda")
+        its = r["iters"].cpu().numpy()
+        out[name] = {"s_per_fit": dt, "status": int(r["status"]), "iters_total": int(its.sum()),
+                     "orth_P": {str(k): float((GP[:k, :k] - eye[:k, :k]).abs().max()) for k in ks},
+                     "orth_V": {str(k): float((GV[:k, :k] - eye[:k, :k]).abs().max()) for k in ks}}
+        log("orthogonality %s: %.2f s, |V^T V - I| at K: %.2e" % (name, dt,
+                                                                 out[name]["orth_V"][str(ks[-1])]))
+    res = {"metric": "max |V_K^T V_K - I| of GS-PCA (one classical pass), FP32 4096x512 full rank",
+           "value": out["gs_cgs"]["orth_V"][str(ks[-1])], "unit": "abs", "n_gpus": 1,
+           "steps": 1, "warmup": 0, "ms_per_step": out["gs_cgs"]["s_per_fit"] * 1e3,
+           "higher_is_better": False, "scaling": "weak", "vs_baseline": None, "dtype": "f32",
+           "data": "synthetic",
+           "config": {"workload": "orthogonality_f32_4096x512", "M": M, "N": N, "K": K,
+                      "tol": 1e-6, "max_iter": 1000},
+           "roofline": None, "cpu_baseline": None, "forms": out}
+    print(json.dumps(res), flush=True)
+
+
 def bench_collinear(args):
     """4096 x 512 FP32 full rank (s_i = 0.9^i + 1e-4 noise, centred), K = N =
     512, tol 1e-6, max_iter 1000: GS-PCA vs NIPALS orthogonality and
@@ -518,10 +566,14 @@ def main():
                     help="run one device-to-device copy of 1 GiB first (calibrates HBM byte "
                          "counters of a profiler run against a kernel of known traffic)")
     ap.add_argument("--workload", default="large",
-                    choices=["large", "batched", "small", "collinear", "paper_sweep"],
+                    choices=["large", "batched", "small", "collinear", "paper_sweep",
+                             "orthogonality"],
                     help="large: the 65536 x 8192 fit (default); batched: 2048 uneven "
                          "problems; small: 512 x 128 FP64; collinear: 4096 x 512 FP32, K = N; "
-                         "paper_sweep: the paper's FP64 timing sweep (uniform, N = M/2, K = 10)")
+                         "paper_sweep: the paper's FP64 timing sweep (uniform, N = M/2, K = 10); "
+                         "orthogonality: NIPALS vs the Gram-Schmidt forms on the collinear case")
+    ap.add_argument("--ortho-k", type=int, default=128,
+                    help="components of the orthogonality study")
     ap.add_argument("--batch-count", type=int, default=2048)
     ap.add_argument("--sweep-sizes", default="500,1000,2000,4000,8000,15000",
                     help="row counts M of the paper sweep (N = M/2)")
@@ -543,6 +595,9 @@ def main():
         return
     if args.workload == "paper_sweep":
         bench_paper_sweep(args)
+        return
+    if args.workload == "orthogonality":
+        bench_orthogonality(args)
         return
 
     import numpy as np
