@@ -230,6 +230,37 @@ def whiten(Y):
     return (Y @ Q) * scale, g
 
 
+def block_fit(X, K, Omega=None, Z0=None, tol=0.0, max_iter=10):
+    """Block iteration with Rayleigh-Ritz (not in the paper; Halko, Martinsson
+    & Tropp 2011, Alg. 4.4, orthonormalised by whitening), FP64, in the
+    library's order of steps: V_0 from the whitened X Omega (or Z0); each
+    iteration Y = X (X^T V), whitened (Ritz order; g the Ritz values of
+    (X X^T)^2); stop when every s_i = g_i^(1/4), i < K, moved less than tol
+    relatively (never for tol = 0).  Then w_i = X^T v_i, sigma_i = |w_i|,
+    P = w / sigma, T = sigma v.  Returns (T, P, sigma, iterations, converged)."""
+    X = np.asarray(X, dtype=np.float64)
+    M = X.shape[0]
+    if Z0 is not None:
+        Z, g = whiten(Z0)
+    else:
+        Z, g = whiten(X @ np.asarray(Omega, dtype=np.float64))
+    prev = np.zeros(K)
+    it, conv = 0, False
+    while it < max_iter:
+        it += 1
+        Z, g = whiten(sketch_refine(X, Z)[1])
+        s = np.where(g[:K] > 0, g[:K], 0.0) ** 0.25
+        passed = bool(np.all(np.abs(s - prev) < tol * s))
+        prev = s
+        if tol > 0 and passed:
+            conv = True
+            break
+    V = Z[:, :K] / np.sqrt(M)
+    W = X.T @ V
+    sig = np.linalg.norm(W, axis=0)
+    return V * sig, W / sig, sig, it, conv
+
+
 def bf16_round(a):
     """Element-wise value of a stored as FP32 then bfloat16 (float64 array)."""
     a = np.ascontiguousarray(np.asarray(a, dtype=np.float64))

@@ -19,7 +19,7 @@ from ._binding import (BF16, EDEVICE, EINVAL, ENOMEM, ENONFINITE, EWORKSPACE, F3
                        NOT_CONVERGED, OK, STOP_LOADING, STOP_SIGMA_REL, GspcaError,
                        LibraryMissing, Profile, status_string)
 
-__all__ = ["fit", "quantize", "Quantized", "Batch", "workspace_bytes", "column_major",
+__all__ = ["fit", "fit_block", "quantize", "Quantized", "Batch", "workspace_bytes", "column_major",
            "status_string", "GspcaError", "LibraryMissing", "Profile", "load"]
 
 _ALGOS = {"gs": GS, "nipals": NIPALS}
@@ -191,6 +191,51 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         raise GspcaError(st)
     return {"T": T, "P": P, "lambda": lam, "sigma": sig, "iters": iters, "start_col": start,
             "status": st}
+
+
+def fit_block(X, K, r=64, Omega=None, Z0=None, tol=1e-6, max_iter=50, stream=None,
+              check=True):
+    """Block iteration with Rayleigh-Ritz for the K leading components of the
+    column-major FP32 device matrix X (gspca_block.h; not in the paper).
+
+    ``r`` (32 or 64) is the block width; the start block is X @ Omega (Omega
+    N x r, row-major float32 device tensor) or the given M x r row-major Z0.
+    Returns T, P (column-major float32), lambda, sigma (float64), the
+    iteration count and the status."""
+    import torch
+    L = _b.load()
+    if not X.is_cuda or X.dtype != torch.float32 or X.stride(0) != 1:
+        raise ValueError("X must be a column-major float32 device matrix")
+    M, N = X.shape
+    K, r = int(K), int(r)
+    for name, a, shape in (("Omega", Omega, (N, r)), ("Z0", Z0, (M, r))):
+        if a is not None and (a.dtype != torch.float32 or not a.is_cuda or
+                              tuple(a.shape) != shape or not a.is_contiguous()):
+            raise ValueError("%s must be a contiguous (row-major) float32 device tensor %s"
+                             % (name, shape))
+    if Omega is None and Z0 is None:
+        raise ValueError("give Omega or Z0")
+    op = _b.BlockOptions(r, int(max_iter), float(tol),
+                         Omega.data_ptr() if Omega is not None else None,
+                         Z0.data_ptr() if Z0 is not None else None)
+    dev = X.device
+    T = torch.empty_strided((M, K), (1, M), dtype=torch.float32, device=dev)
+    P = torch.empty_strided((N, K), (1, N), dtype=torch.float32, device=dev)
+    lam = torch.empty(K, dtype=torch.float64, device=dev)
+    sig = torch.empty(K, dtype=torch.float64, device=dev)
+    nbytes = int(L.gspca_block_workspace_bytes(M, N, r))
+    if nbytes == 0:
+        raise GspcaError(EINVAL)
+    _keep, wptr = _workspace(nbytes, dev)
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    its = ctypes.c_int32(0)
+    st = int(L.gspca_fit_block(X.data_ptr(), X.stride(1), M, N, K, op, T.data_ptr(),
+                               P.data_ptr(), lam.data_ptr(), sig.data_ptr(), ctypes.byref(its),
+                               wptr, nbytes, ctypes_stream(stream)))
+    if check and st < 0:
+        raise GspcaError(st)
+    return {"T": T, "P": P, "lambda": lam, "sigma": sig, "iters": int(its.value), "status": st}
 
 
 def ctypes_stream(stream):

@@ -32,6 +32,8 @@ EXPORTS = (
     "gspca_whiten_sketch",
     "gspca_mlp_sync", "gspca_mlp_forward", "gspca_mlp_loss_grad", "gspca_mlp_adam",
     "gspca_ws_predict",
+    # gspca_block.h (block iteration)
+    "gspca_block_workspace_bytes", "gspca_fit_block",
 )
 
 WS_RANK = 32  # GSPCA_WS_RANK (network input width)
@@ -80,6 +82,11 @@ class Mlp(ctypes.Structure):
                 ("d3", ctypes.c_int32), ("theta", ctypes.c_void_p), ("theta_bf16", ctypes.c_void_p),
                 ("grad", ctypes.c_void_p), ("adam_m", ctypes.c_void_p), ("adam_v", ctypes.c_void_p),
                 ("step", ctypes.c_int32), ("pad", ctypes.c_int32)]
+
+
+class BlockOptions(ctypes.Structure):
+    _fields_ = [("r", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+                ("Omega", ctypes.c_void_p), ("Z0", ctypes.c_void_p)]
 
 
 class Result(ctypes.Structure):
@@ -151,7 +158,11 @@ def load() -> ctypes.CDLL:
                 ("gspca_mlp_loss_grad", ctypes.c_int, [mlp, vp, vp, i32, i64, vp, vp, sz, vp]),
                 ("gspca_mlp_adam", ctypes.c_int, [mlp, flt, flt, flt, flt, vp]),
                 ("gspca_ws_predict", ctypes.c_int,
-                 [mlp, vp, i64, i64, i64, vp, i32, i32, vp, vp, sz, vp])):
+                 [mlp, vp, i64, i64, i64, vp, i32, i32, vp, vp, sz, vp]),
+                ("gspca_block_workspace_bytes", sz, [i64, i64, i32]),
+                ("gspca_fit_block", ctypes.c_int,
+                 [vp, i64, i64, i64, i64, ctypes.POINTER(BlockOptions), vp, vp, vp, vp,
+                  ctypes.POINTER(i32), vp, sz, vp])):
             f = getattr(L, name)
             f.restype = res
             f.argtypes = args

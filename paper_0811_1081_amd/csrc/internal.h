@@ -265,6 +265,26 @@ struct Fused {
                          int32_t *start_col, LoopState *st, hipStream_t s);
 };
 
+// Sketch products and whitening (mlp.hip), shared by the warm start and the
+// block iteration (block.hip).  Row slices of the refinement's X^T Z (about
+// 2048 workgroups) and of the Gram matrix (at most 256), and the workspace
+// they use (the whitening alone needs off_wpart bytes).
+struct SketchPlan {
+    int64_t st, rows_t, sg, rows_g;
+    size_t off_gpart, off_qs, off_wpart, total;
+};
+SketchPlan sketch_plan(int64_t M, int64_t N, int r);
+bool valid_rank(int32_t r); // sketch widths: 32 or 64
+// Y = X Om (X column-major, Om row-major N x r, Y row-major M x r)
+void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
+                   float *Y, hipStream_t s);
+// W = X^T Z / sqrt(M) (Z row-major M x r, W row-major N x r)
+void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Z, int r,
+                     float *W, unsigned char *ws, hipStream_t s);
+// Z = sqrt(M) Y Q diag(g)^(-1/2), g the eigenvalues of Y^T Y (decreasing)
+void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_t *flag,
+                   unsigned char *ws, hipStream_t s);
+
 // Batched path (batched.hip): one workgroup per problem, persistent queue.
 struct BatchItem {
     const float *X;

@@ -608,33 +608,6 @@ bool valid_net(const gspca_mlp *n)
 // splits.
 constexpr int kMaxSplit = 64;
 
-// Row slices of the refinement's X^T Z (about 2048 workgroups) and of the Gram
-// matrix (at most 256 workgroups), and the workspace they use.
-struct SketchPlan {
-    int64_t st, rows_t, sg, rows_g;
-    size_t off_gpart, off_qs, off_wpart, total; // whitening needs off_wpart bytes
-};
-SketchPlan sketch_plan(int64_t M, int64_t N, int r)
-{
-    SketchPlan P{};
-    const int64_t cb = (N + 63) / 64;
-    P.st = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 2048 / cb));
-    P.rows_t = ((M + P.st - 1) / P.st + 31) / 32 * 32;
-    P.st = (M + P.rows_t - 1) / P.rows_t;
-    P.sg = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 256));
-    P.rows_g = ((M + P.sg - 1) / P.sg + 63) / 64 * 64;
-    P.sg = (M + P.rows_g - 1) / P.rows_g;
-    size_t o = 0; // Gram part first: its offsets do not depend on N
-    P.off_gpart = o;
-    o = align256(o + (size_t)P.sg * r * r * 8);
-    P.off_qs = o;
-    o = align256(o + (size_t)r * r * 8);
-    P.off_wpart = o;
-    o = align256(o + (size_t)P.st * N * r * 4);
-    P.total = o;
-    return P;
-}
-
 struct Layout {
     size_t H1, H2, O, dO, G2, G1, lossp, part, Y, Z, W, SK, total;
 };
@@ -724,6 +697,32 @@ gspca_status launched()
     return hipGetLastError() == hipSuccess ? GSPCA_OK : GSPCA_EDEVICE;
 }
 
+} // namespace
+
+// Sketch products and whitening, shared with the block iteration (block.hip).
+// Row slices of the refinement's X^T Z (about 2048 workgroups) and of the Gram
+// matrix (at most 256 workgroups), and the workspace they use.
+SketchPlan sketch_plan(int64_t M, int64_t N, int r)
+{
+    SketchPlan P{};
+    const int64_t cb = (N + 63) / 64;
+    P.st = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 2048 / cb));
+    P.rows_t = ((M + P.st - 1) / P.st + 31) / 32 * 32;
+    P.st = (M + P.rows_t - 1) / P.rows_t;
+    P.sg = std::max<int64_t>(1, std::min<int64_t>((M + 255) / 256, 256));
+    P.rows_g = ((M + P.sg - 1) / P.sg + 63) / 64 * 64;
+    P.sg = (M + P.rows_g - 1) / P.rows_g;
+    size_t o = 0; // Gram part first: its offsets do not depend on N
+    P.off_gpart = o;
+    o = align256(o + (size_t)P.sg * r * r * 8);
+    P.off_qs = o;
+    o = align256(o + (size_t)r * r * 8);
+    P.off_wpart = o;
+    o = align256(o + (size_t)P.st * N * r * 4);
+    P.total = o;
+    return P;
+}
+
 bool valid_rank(int32_t r) { return r == 32 || r == GSPCA_WS_RMAX; }
 
 void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
@@ -770,7 +769,6 @@ void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_
     }
 }
 
-} // namespace
 } // namespace gspca
 
 using namespace gspca;

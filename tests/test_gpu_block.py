@@ -1,0 +1,110 @@
+"""GPU block iteration (gspca_block.h; not in the paper) against the FP64
+oracle of the same steps and against the library SVD.
+
+Tolerances: FP32 data and FP32-accumulated products (relative rounding
+~1e-7 per product, amplified by 1 / gap in the vectors): sigma within 1e-5
+relative, loading angles <= 1e-4 for components whose relative gap to both
+neighbours is >= 2 %."""
+import numpy as np
+import pytest
+
+from metrics import col_angles
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _lib():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_0811_1081_amd as gp
+    gp.load()
+
+
+def _gapped(s, rel=0.02):
+    ok = np.ones(len(s), dtype=bool)
+    for k in range(len(s)):
+        if k > 0 and s[k] > (1 - rel) * s[k - 1]:
+            ok[k] = False
+        if k + 1 < len(s) and s[k + 1] > (1 - rel) * s[k]:
+            ok[k] = False
+    return ok
+
+
+def _case(M=2000, N=300, r=32, seed=4):
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    X = synth.haar_spectrum(M, N, 0.9 ** np.arange(80), 1e-4, seed=(11, seed), dtype=np.float32)
+    Om = synth.sketch_matrix(N, r)
+    Xd = gp.column_major(torch.from_numpy(X).cuda())
+    Omd = torch.from_numpy(np.ascontiguousarray(Om, dtype=np.float32)).cuda()
+    return X, Om, Xd, Omd
+
+
+@pytest.mark.parametrize("r", [32, 64])
+def test_fixed_iterations_match_oracle(orc, r):
+    import paper_0811_1081_amd as gp
+    X, Om, Xd, Omd = _case(r=r)
+    K = 16
+    g = gp.fit_block(Xd, K, r=r, Omega=Omd, tol=0.0, max_iter=3)
+    assert g["status"] == 0 and g["iters"] == 3
+    T, P, s, it, _ = orc.block_fit(X, K, Omega=Om, tol=0.0, max_iter=3)
+    sg = g["sigma"].cpu().numpy()
+    assert np.abs(sg / s - 1).max() <= 1e-5
+    ok = _gapped(s)
+    assert ok.any()
+    assert col_angles(g["P"].cpu().numpy(), P)[ok].max() <= 1e-4
+    assert col_angles(g["T"].cpu().numpy(), T)[ok].max() <= 1e-4
+    assert np.abs(g["lambda"].cpu().numpy() / s ** 2 - 1).max() <= 2e-5
+
+
+def test_converged_matches_svd():
+    import paper_0811_1081_amd as gp
+    X, Om, Xd, Omd = _case(r=64)
+    K = 24
+    g = gp.fit_block(Xd, K, r=64, Omega=Omd, tol=1e-7, max_iter=100)
+    assert g["status"] == 0 and g["iters"] < 100
+    U, sv, Vt = np.linalg.svd(X.astype(np.float64), full_matrices=False)
+    sg = g["sigma"].cpu().numpy()
+    assert np.abs(sg / sv[:K] - 1).max() <= 1e-5
+    ok = _gapped(sv[:K + 1])[:K]
+    P = g["P"].cpu().numpy().astype(np.float64)
+    assert col_angles(P, Vt[:K].T)[ok].max() <= 1e-4
+    assert np.abs(P.T @ P - np.eye(K)).max() <= 1e-5
+
+
+def test_given_start_saves_iterations():
+    """Starting from vectors already close to the singular vectors (the
+    scores of an earlier, lower-precision fit) converges in fewer iterations
+    than the random sketch."""
+    import torch
+    import paper_0811_1081_amd as gp
+    X, Om, Xd, Omd = _case(r=32)
+    K = 16
+    U = np.linalg.svd(X.astype(np.float64), full_matrices=False)[0][:, :32]
+    rng = np.random.default_rng(1)
+    Z0 = (U + 1e-3 * rng.standard_normal(U.shape)).astype(np.float32)
+    Z0d = torch.from_numpy(np.ascontiguousarray(Z0)).cuda()
+    a = gp.fit_block(Xd, K, r=32, Omega=Omd, tol=1e-7, max_iter=100)
+    b = gp.fit_block(Xd, K, r=32, Z0=Z0d, tol=1e-7, max_iter=100)
+    assert a["status"] == 0 and b["status"] == 0
+    assert b["iters"] < a["iters"]
+    assert np.abs(b["sigma"].cpu().numpy() / a["sigma"].cpu().numpy() - 1).max() <= 1e-5
+
+
+def test_errors_and_status():
+    import torch
+    import paper_0811_1081_amd as gp
+    X, Om, Xd, Omd = _case(M=400, N=100, r=32)
+    with pytest.raises(gp.GspcaError):
+        gp.fit_block(Xd, 40, r=32, Omega=Omd)  # K > r
+    # a zero matrix: the Ritz values are 0, none of the K is positive
+    Ld = gp.column_major(torch.zeros((400, 100), dtype=torch.float32, device="cuda"))
+    with pytest.raises(gp.GspcaError):
+        gp.fit_block(Ld, 4, r=32, Omega=Omd, tol=0.0, max_iter=2)
+    # max_iter reached with tol > 0: NOT_CONVERGED, outputs still written
+    r = gp.fit_block(Xd, 16, r=32, Omega=Omd, tol=1e-14, max_iter=2)
+    assert r["status"] == 1 and r["iters"] == 2
+    assert np.all(np.isfinite(r["P"].cpu().numpy()))
