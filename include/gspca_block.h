@@ -14,9 +14,14 @@
  *   V_(j+1) = Y Q diag(g)^(-1/2)           orthonormal, in Ritz order
  *
  * g holds the Ritz values of (X X^T)^2 on the block, so s_i = g_i^(1/4)
- * estimates sigma_i; iteration j passes when |s_i^(j) - s_i^(j-1)| <
- * tol * s_i^(j) for every i < K (the paper's relative test, applied to the
- * K leading estimates at once; s^(0) = 0).  At the end
+ * estimates sigma_i.  Stop tests, for every i < K at once:
+ *   GSPCA_STOP_SIGMA_REL: |s_i^(j) - s_i^(j-1)| < tol * s_i^(j) (the paper's
+ *     relative test on the K leading estimates; s^(0) = 0).  The estimates
+ *     settle quadratically faster than the vectors, so in FP32 this test
+ *     suits tolerances down to ~1e-7, i.e. vectors to ~3e-4.
+ *   GSPCA_STOP_LOADING: |v_i^(j) - s v_i^(j-1)| < tol, s = +-1 aligning the
+ *     signs: the unit Ritz vectors moved less than tol (FP64 dot products).
+ * At the end
  *   w_i = X^T v_i,  sigma_i = |w_i|,  P[:, i] = w_i / sigma_i,
  *   T[:, i] = sigma_i v_i,  lambda_i = sigma_i^2          (i < K)
  * -- the same output conventions as gspca_fit_ex (T = V Lambda, unit
@@ -40,6 +45,8 @@ extern "C" {
 typedef struct {
     int32_t r;          /* block width: 32 or 64, K <= r <= M                  */
     int32_t max_iter;   /* >= 1 block iterations                               */
+    int32_t stop;       /* gspca_stop (see above)                              */
+    int32_t reserved;
     double tol;         /* >= 0; 0 runs exactly max_iter iterations            */
     const float *Omega; /* N x r row-major start sketch (used when Z0 is NULL) */
     const float *Z0;    /* M x r row-major start vectors (nullable); whitened

@@ -230,13 +230,15 @@ def whiten(Y):
     return (Y @ Q) * scale, g
 
 
-def block_fit(X, K, Omega=None, Z0=None, tol=0.0, max_iter=10):
+def block_fit(X, K, Omega=None, Z0=None, tol=0.0, max_iter=10, stop="sigma"):
     """Block iteration with Rayleigh-Ritz (not in the paper; Halko, Martinsson
     & Tropp 2011, Alg. 4.4, orthonormalised by whitening), FP64, in the
     library's order of steps: V_0 from the whitened X Omega (or Z0); each
     iteration Y = X (X^T V), whitened (Ritz order; g the Ritz values of
     (X X^T)^2); stop when every s_i = g_i^(1/4), i < K, moved less than tol
-    relatively (never for tol = 0).  Then w_i = X^T v_i, sigma_i = |w_i|,
+    relatively, or (stop="loading") every unit Ritz vector v_i moved less
+    than tol (|v_i - s v_i_prev|, s = +-1 aligning the signs); never for
+    tol = 0.  Then w_i = X^T v_i, sigma_i = |w_i|,
     P = w / sigma, T = sigma v.  Returns (T, P, sigma, iterations, converged)."""
     X = np.asarray(X, dtype=np.float64)
     M = X.shape[0]
@@ -248,9 +250,14 @@ def block_fit(X, K, Omega=None, Z0=None, tol=0.0, max_iter=10):
     it, conv = 0, False
     while it < max_iter:
         it += 1
+        Zp = Z
         Z, g = whiten(sketch_refine(X, Z)[1])
         s = np.where(g[:K] > 0, g[:K], 0.0) ** 0.25
-        passed = bool(np.all(np.abs(s - prev) < tol * s))
+        if stop == "loading":
+            c = np.abs(np.sum(Z[:, :K] * Zp[:, :K], axis=0)) / M
+            passed = bool(np.all(np.sqrt(np.maximum(0.0, 2 - 2 * c)) < tol))
+        else:
+            passed = bool(np.all(np.abs(s - prev) < tol * s))
         prev = s
         if tol > 0 and passed:
             conv = True

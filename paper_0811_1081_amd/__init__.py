@@ -193,13 +193,15 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
             "status": st}
 
 
-def fit_block(X, K, r=64, Omega=None, Z0=None, tol=1e-6, max_iter=50, stream=None,
-              check=True):
+def fit_block(X, K, r=64, Omega=None, Z0=None, tol=1e-6, max_iter=50, stop="sigma",
+              stream=None, check=True):
     """Block iteration with Rayleigh-Ritz for the K leading components of the
     column-major FP32 device matrix X (gspca_block.h; not in the paper).
 
     ``r`` (32 or 64) is the block width; the start block is X @ Omega (Omega
     N x r, row-major float32 device tensor) or the given M x r row-major Z0.
+    ``stop``: "sigma" (relative change of the K leading estimates) or
+    "loading" (the unit Ritz vectors moved less than tol).
     Returns T, P (column-major float32), lambda, sigma (float64), the
     iteration count and the status."""
     import torch
@@ -215,7 +217,7 @@ def fit_block(X, K, r=64, Omega=None, Z0=None, tol=1e-6, max_iter=50, stream=Non
                              % (name, shape))
     if Omega is None and Z0 is None:
         raise ValueError("give Omega or Z0")
-    op = _b.BlockOptions(r, int(max_iter), float(tol),
+    op = _b.BlockOptions(r, int(max_iter), _STOPS[stop], 0, float(tol),
                          Omega.data_ptr() if Omega is not None else None,
                          Z0.data_ptr() if Z0 is not None else None)
     dev = X.device

@@ -85,7 +85,8 @@ class Mlp(ctypes.Structure):
 
 
 class BlockOptions(ctypes.Structure):
-    _fields_ = [("r", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("tol", ctypes.c_double),
+    _fields_ = [("r", ctypes.c_int32), ("max_iter", ctypes.c_int32), ("stop", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("Omega", ctypes.c_void_p), ("Z0", ctypes.c_void_p)]
 
 

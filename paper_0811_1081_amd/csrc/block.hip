@@ -5,6 +5,7 @@
 // the output kernels.
 #include <math.h>
 
+#include <utility>
 #include <vector>
 
 #include "../../include/gspca_block.h"
@@ -17,7 +18,7 @@ inline unsigned bcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b)
 inline size_t balign(size_t x) { return (x + 255) & ~(size_t)255; }
 
 struct BlockLayout {
-    size_t Y, Z, W, g, flag, norms, sk, total;
+    size_t Y, Z, Z2, W, g, flag, norms, sk, total;
 };
 BlockLayout block_layout(int64_t M, int64_t N, int r)
 {
@@ -29,8 +30,9 @@ BlockLayout block_layout(int64_t M, int64_t N, int r)
     };
     put(L.Y, (size_t)M * r * 4);
     put(L.Z, (size_t)M * r * 4);
+    put(L.Z2, (size_t)M * r * 4);
     put(L.W, (size_t)N * r * 4);
-    put(L.g, (size_t)r * 8);
+    put(L.g, (size_t)2 * r * 8);
     put(L.flag, 8);
     put(L.norms, (size_t)r * 8);
     put(L.sk, sketch_plan(M, N, r).total);
@@ -58,6 +60,30 @@ __global__ __launch_bounds__(256) void k_block_norms(const float *__restrict__ W
     __syncthreads();
     if (tid == 0)
         sig[i] = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
+}
+
+// Change of the unit Ritz vector i = blockIdx.x between two whitened blocks
+// (columns of norm sqrt(M)): d_i = |v - s u| = sqrt(2 - 2 |u . v|), s the
+// sign of u . v, from an FP64 sum over the rows in a fixed order.
+__global__ __launch_bounds__(256) void k_block_change(const float *__restrict__ Zn,
+                                                      const float *__restrict__ Zo, int64_t M,
+                                                      int r, double *__restrict__ d)
+{
+    __shared__ double red[4];
+    const int i = blockIdx.x, tid = threadIdx.x;
+    double a = 0.0;
+    for (int64_t m = tid; m < M; m += 256)
+        a += (double)Zn[m * r + i] * (double)Zo[m * r + i];
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1)
+        a += __shfl_xor(a, o, 64);
+    if ((tid & 63) == 0)
+        red[tid >> 6] = a;
+    __syncthreads();
+    if (tid == 0) {
+        const double c = fabs(((red[0] + red[1]) + red[2]) + red[3]) / (double)M;
+        d[i] = sqrt(fmax(0.0, 2.0 - 2.0 * c));
+    }
 }
 
 // Outputs of component i = blockIdx.y: T[:, i] = sigma_i Z[:, i] / sqrt(M)
@@ -107,7 +133,8 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
     const int r = opt->r;
     if (!valid_rank(r) || M < r || N < 1 || ldx < M || K < 1 || K > r || K > N ||
         opt->max_iter < 1 || !(opt->tol >= 0.0) || !isfinite(opt->tol) ||
-        (!opt->Omega && !opt->Z0))
+        (!opt->Omega && !opt->Z0) ||
+        (opt->stop != GSPCA_STOP_SIGMA_REL && opt->stop != GSPCA_STOP_LOADING))
         return GSPCA_EINVAL;
     if (((uintptr_t)ws) % 256)
         return GSPCA_EINVAL;
@@ -118,8 +145,10 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
     unsigned char *base = static_cast<unsigned char *>(ws);
     float *Y = reinterpret_cast<float *>(base + L.Y);
     float *Z = reinterpret_cast<float *>(base + L.Z);
+    float *Zo = reinterpret_cast<float *>(base + L.Z2); // the previous block
     float *W = reinterpret_cast<float *>(base + L.W);
     double *gd = reinterpret_cast<double *>(base + L.g);
+    double *dd = gd + r; // vector changes (loading stop)
     int32_t *flag = reinterpret_cast<int32_t *>(base + L.flag);
     double *norms = reinterpret_cast<double *>(base + L.norms);
     unsigned char *sk = base + L.sk;
@@ -134,7 +163,8 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
     }
     launch_whiten(Y, M, r, Z, gd, flag, sk, s);
 
-    std::vector<double> g(r), prev(K, 0.0);
+    std::vector<double> g(2 * r), prev(K, 0.0);
+    const bool vstop = opt->stop == GSPCA_STOP_LOADING;
     int32_t it = 0;
     bool conv = false;
     while (it < opt->max_iter) {
@@ -142,18 +172,24 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
         // Y = X (X^T V), V = Z / sqrt(M); then V <- whitened Y (Ritz order)
         launch_sketch_t(X, ldx, M, N, Z, r, W, sk, s);
         launch_sketch(X, ldx, M, N, W, r, Y, s);
+        std::swap(Z, Zo);
         launch_whiten(Y, M, r, Z, gd, flag, sk, s);
-        if (hipMemcpyAsync(g.data(), gd, (size_t)r * 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        if (vstop)
+            hipLaunchKernelGGL(k_block_change, dim3((unsigned)K), dim3(256), 0, s, Z, Zo, M, r,
+                               dd);
+        if (hipMemcpyAsync(g.data(), gd, (size_t)(vstop ? 2 * r : r) * 8, hipMemcpyDeviceToHost,
+                           s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
             return GSPCA_EDEVICE;
         for (int64_t i = 0; i < K; ++i)
             if (!(g[i] > 0.0) || !isfinite(g[i]))
                 return GSPCA_EINVAL; // X has rank below K (or non-finite entries)
-        // estimates s_i = g_i^(1/4) (g: Ritz values of (X X^T)^2), relative test
+        // estimates s_i = g_i^(1/4) (g: Ritz values of (X X^T)^2), relative
+        // test; or the change of the unit Ritz vectors
         bool pass = true;
         for (int64_t i = 0; i < K; ++i) {
             const double si = pow(g[i], 0.25);
-            if (!(fabs(si - prev[i]) < opt->tol * si))
+            if (vstop ? !(g[r + i] < opt->tol) : !(fabs(si - prev[i]) < opt->tol * si))
                 pass = false;
             prev[i] = si;
         }

@@ -94,6 +94,21 @@ def test_given_start_saves_iterations():
     assert np.abs(b["sigma"].cpu().numpy() / a["sigma"].cpu().numpy() - 1).max() <= 1e-5
 
 
+def test_vector_change_stop():
+    """stop="loading": the fit ends when the unit Ritz vectors move less than
+    tol; the same count replayed in the oracle (tol = 0) gives the same
+    result, and the vectors are then well inside tol of the SVD's."""
+    import paper_0811_1081_amd as gp
+    X, Om, Xd, Omd = _case(r=64)
+    K = 24
+    g = gp.fit_block(Xd, K, r=64, Omega=Omd, tol=1e-4, max_iter=100, stop="loading")
+    assert g["status"] == 0 and 1 < g["iters"] < 100
+    U, sv, Vt = np.linalg.svd(X.astype(np.float64), full_matrices=False)
+    ok = _gapped(sv[:K + 1])[:K]
+    P = g["P"].cpu().numpy()
+    assert col_angles(P, Vt[:K].T)[ok].max() <= 1e-4
+
+
 def test_errors_and_status():
     import torch
     import paper_0811_1081_amd as gp

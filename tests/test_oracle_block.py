@@ -64,3 +64,21 @@ def test_given_start_equals_sketch_start(orc):
     a = orc.block_fit(X, 8, Omega=Om, tol=0.0, max_iter=3)
     b = orc.block_fit(X, 8, Z0=X @ Om, tol=0.0, max_iter=3)
     assert np.array_equal(a[2], b[2]) and np.array_equal(a[1], b[1])
+
+
+def test_vector_change_stop(orc):
+    """stop="loading": the iteration ends once every unit Ritz vector moved
+    less than tol; the error left is then below tol times the contraction
+    (sigma_(r+1) / sigma_K)^2 / (1 - that), far below tol for this gap."""
+    X, Om = _gapped_case()
+    K = 12
+    T, P, s, it, conv = orc.block_fit(X, K, Omega=Om, tol=1e-6, max_iter=200, stop="loading")
+    U, sv, Vt = np.linalg.svd(X, full_matrices=False)
+    assert conv
+    rho = (sv[32] / sv[K - 1]) ** 2
+    assert col_angles(T / s, U[:, :K]).max() <= 1e-6 * rho / (1 - rho) * 4
+    # one iteration fewer has not yet met the test
+    T2, _, s2, _, _ = orc.block_fit(X, K, Omega=Om, tol=0.0, max_iter=it - 1)
+    T3, _, s3, _, _ = orc.block_fit(X, K, Omega=Om, tol=0.0, max_iter=it - 2) if it > 2 else (T2, 0, s2, 0, 0)
+    if it > 2:
+        assert col_angles(T2 / s2, T3 / s3).max() >= 1e-6
