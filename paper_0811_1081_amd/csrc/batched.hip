@@ -49,6 +49,28 @@ __device__ inline double bblock_sum(double v, double *red)
     return r;
 }
 
+// This lane's share of col . v over n rows (lanes over rows, eight rows per
+// lane in flight; the wave sum finishes the product).
+__device__ inline double lane_dot(const float *__restrict__ col, const double *__restrict__ v,
+                                  int n, int lane)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int m = lane;
+    for (; m + 7 * 64 < n; m += 8 * 64) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            x[u] = col[m + 64 * u];
+        s0 += (double)x[0] * v[m] + (double)x[4] * v[m + 256];
+        s1 += (double)x[1] * v[m + 64] + (double)x[5] * v[m + 320];
+        s2 += (double)x[2] * v[m + 128] + (double)x[6] * v[m + 384];
+        s3 += (double)x[3] * v[m + 192] + (double)x[7] * v[m + 448];
+    }
+    for (; m < n; m += 64)
+        s0 += (double)col[m] * v[m];
+    return (s0 + s1) + (s2 + s3);
+}
+
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
 
 __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ items, int nprob,
@@ -203,21 +225,13 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             auto loading = [&](int first) -> bool {
                 __syncthreads();
                 for (int j = w; j < N; j += nw) {
-                    const float *col = X + (int64_t)j * ldx;
-                    double s = 0.0;
-                    for (int m = lane; m < M; m += 64)
-                        s += (double)col[m] * t[m];
-                    s = bwave_sum(s);
+                    const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
                     if (lane == 0)
                         q[j] = s;
                 }
                 __syncthreads();
                 for (int i = w; i < k; i += nw) {
-                    const float *pc = P + (int64_t)i * N;
-                    double s = 0.0;
-                    for (int j = lane; j < N; j += 64)
-                        s += (double)pc[j] * q[j];
-                    s = bwave_sum(s);
+                    const double s = bwave_sum(lane_dot(P + (int64_t)i * N, q, N, lane));
                     if (lane == 0)
                         dc[i] = s;
                 }
@@ -266,14 +280,22 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                     pf[j] = (float)(p[j] / pn);
                 __syncthreads();
                 for (int m = tid; m < M; m += NT) {
+                    // sixteen columns per step, all loads issued before use
                     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
                     const float *xr = X + m;
                     int j = 0;
-                    for (; j + 4 <= N; j += 4) {
-                        a0 += xr[(int64_t)j * ldx] * pf[j];
-                        a1 += xr[(int64_t)(j + 1) * ldx] * pf[j + 1];
-                        a2 += xr[(int64_t)(j + 2) * ldx] * pf[j + 2];
-                        a3 += xr[(int64_t)(j + 3) * ldx] * pf[j + 3];
+                    for (; j + 16 <= N; j += 16) {
+                        float x[16];
+#pragma unroll
+                        for (int u = 0; u < 16; ++u)
+                            x[u] = xr[(int64_t)(j + u) * ldx];
+#pragma unroll
+                        for (int u = 0; u < 16; u += 4) {
+                            a0 += x[u] * pf[j + u];
+                            a1 += x[u + 1] * pf[j + u + 1];
+                            a2 += x[u + 2] * pf[j + u + 2];
+                            a3 += x[u + 3] * pf[j + u + 3];
+                        }
                     }
                     for (; j < N; ++j)
                         a0 += xr[(int64_t)j * ldx] * pf[j];
@@ -282,11 +304,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 __syncthreads();
                 // d = V^T t, t <- t - V d, sigma
                 for (int i = w; i < k; i += nw) {
-                    const float *vc = T + (int64_t)i * M;
-                    double s = 0.0;
-                    for (int m = lane; m < M; m += 64)
-                        s += (double)vc[m] * t[m];
-                    s = bwave_sum(s);
+                    const double s = bwave_sum(lane_dot(T + (int64_t)i * M, t, M, lane));
                     if (lane == 0)
                         dc[i] = s;
                 }
