@@ -439,10 +439,10 @@ __global__ __launch_bounds__(256) void k_whiten_apply(const float *__restrict__ 
 // Eigen-decomposition of the sketch's Gram matrix by one workgroup of 1024
 // threads (R = 32 or 64): G = sum of the nslice partials from k_gram (fixed
 // order, FP64), parallel cyclic Jacobi (round-robin pairing: R/2 disjoint
-// rotations per round, R-1 rounds per sweep; rotation of Golub & Van Loan's
-// symmetric Schur step) until the off-diagonal mass is below 1e-28 of
-// |G|_F^2; eigenpairs by decreasing g, each eigenvector's largest entry made
-// positive.  Writes QS = sqrt(M) Q[:, perm] diag(g)^(-1/2) (R x R, row-major;
+// rotations per round, applied to both sides of G in one step, R-1 rounds per
+// sweep; rotation of Golub & Van Loan's symmetric Schur step) until the
+// off-diagonal mass is below 1e-28 of |G|_F^2; eigenpairs by decreasing g,
+// each eigenvector's largest entry made positive.  Writes QS = sqrt(M) Q[:, perm] diag(g)^(-1/2) (R x R, row-major;
 // zero columns where g is not positive and finite), g, and the flag.
 template <int R>
 __global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ part, int nslice,
@@ -459,7 +459,8 @@ __global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ 
     __shared__ int perm[R];
     __shared__ double scale[R];
     __shared__ double offsum[2];
-    const int tid = threadIdx.x;
+    __shared__ double red[2][NT / 64];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int idx = tid + e * NT, a = idx / R, b = idx % R;
@@ -471,16 +472,35 @@ __global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ 
     }
     __syncthreads();
     for (int sweep = 0; sweep < 60; ++sweep) {
-        if (tid == 0) {
+        {   // off-diagonal and total mass: per-thread entries, wave sums, the
+            // waves in order (the same on every run)
             double off = 0.0, fro = 0.0;
-            for (int i = 0; i < R; ++i)
-                for (int j = 0; j < R; ++j) {
-                    fro += G[i][j] * G[i][j];
-                    if (i != j)
-                        off += G[i][j] * G[i][j];
+#pragma unroll
+            for (int e = 0; e < EPT; ++e) {
+                const int idx = tid + e * NT, a = idx / R, b = idx % R;
+                const double v = G[a][b];
+                fro += v * v;
+                off += a != b ? v * v : 0.0;
+            }
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                off += __shfl_xor(off, o, 64);
+                fro += __shfl_xor(fro, o, 64);
+            }
+            if (lane == 0) {
+                red[0][w] = off;
+                red[1][w] = fro;
+            }
+            __syncthreads();
+            if (tid == 0) {
+                double so = 0.0, sf = 0.0;
+                for (int i = 0; i < NT / 64; ++i) {
+                    so += red[0][i];
+                    sf += red[1][i];
                 }
-            offsum[0] = off;
-            offsum[1] = fro;
+                offsum[0] = so;
+                offsum[1] = sf;
+            }
         }
         __syncthreads();
         if (!(offsum[0] > 1e-28 * offsum[1]))
@@ -512,61 +532,68 @@ __global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ 
                 sn[i] = sv;
             }
             __syncthreads();
-            for (int e = tid; e < R * (R / 2); e += NT) { // G <- G J, Q <- Q J (row a, pair b)
+            // G <- J^T G J in one step: the pairs are disjoint, so the 2 x 2
+            // block of row pair b1 and column pair b2 depends on rotations b1
+            // and b2 only (columns first, then rows, as two sweeps would)
+            for (int e = tid; e < (R / 2) * (R / 2); e += NT) {
+                const int b1 = e / (R / 2), b2 = e % (R / 2);
+                const int p1 = pa[b1], q1 = pb[b1], p2 = pa[b2], q2 = pb[b2];
+                const double c1 = cs[b1], s1 = sn[b1], c2 = cs[b2], s2 = sn[b2];
+                const double g00 = G[p1][p2], g01 = G[p1][q2], g10 = G[q1][p2], g11 = G[q1][q2];
+                const double h00 = c2 * g00 - s2 * g01, h01 = s2 * g00 + c2 * g01;
+                const double h10 = c2 * g10 - s2 * g11, h11 = s2 * g10 + c2 * g11;
+                G[p1][p2] = c1 * h00 - s1 * h10;
+                G[q1][p2] = s1 * h00 + c1 * h10;
+                G[p1][q2] = c1 * h01 - s1 * h11;
+                G[q1][q2] = s1 * h01 + c1 * h11;
+            }
+            for (int e = tid; e < R * (R / 2); e += NT) { // Q <- Q J (row a, pair b)
                 const int a = e / (R / 2), b = e % (R / 2);
                 const int p = pa[b], q = pb[b];
                 const double c = cs[b], sv = sn[b];
-                const double gp = G[a][p], gq = G[a][q];
-                G[a][p] = c * gp - sv * gq;
-                G[a][q] = sv * gp + c * gq;
                 const double qp = Q[a][p], qq = Q[a][q];
                 Q[a][p] = c * qp - sv * qq;
                 Q[a][q] = sv * qp + c * qq;
             }
             __syncthreads();
-            for (int e = tid; e < R * (R / 2); e += NT) { // G <- J^T G (column a, pair b)
-                const int a = e / (R / 2), b = e % (R / 2);
-                const int p = pa[b], q = pb[b];
-                const double c = cs[b], sv = sn[b];
-                const double gp = G[p][a], gq = G[q][a];
-                G[p][a] = c * gp - sv * gq;
-                G[q][a] = sv * gp + c * gq;
+        }
+    }
+    // eigenvalues by decreasing g (rank of each, ties by index), then per
+    // column the sign that makes its largest entry positive (first maximum in
+    // row order) and the whitening scale
+    __shared__ int badf;
+    if (tid < R)
+        eig[tid] = G[tid][tid];
+    if (tid == 0)
+        badf = 0;
+    __syncthreads();
+    if (tid < R) {
+        const double gi = eig[tid];
+        int rank = 0;
+        for (int j = 0; j < R; ++j)
+            rank += (eig[j] > gi || (eig[j] == gi && j < tid)) ? 1 : 0;
+        perm[rank] = tid;
+    }
+    __syncthreads();
+    if (tid < R) {
+        const int i = tid, c = perm[i];
+        double amax = -1.0, sgn = 1.0;
+        for (int r = 0; r < R; ++r)
+            if (fabs(Q[r][c]) > amax) {
+                amax = fabs(Q[r][c]);
+                sgn = Q[r][c] >= 0.0 ? 1.0 : -1.0;
             }
-            __syncthreads();
-        }
+        const double g = eig[c];
+        const bool ok = g > 0.0 && isfinite(g);
+        if (!ok)
+            badf = 1;
+        scale[i] = ok ? sqrt((double)M) / sqrt(g) * sgn : 0.0;
+        if (gout)
+            gout[i] = g;
     }
-    if (tid == 0) {
-        for (int i = 0; i < R; ++i) {
-            eig[i] = G[i][i];
-            perm[i] = i;
-        }
-        for (int i = 0; i < R; ++i) // selection sort, decreasing
-            for (int j = i + 1; j < R; ++j)
-                if (eig[perm[j]] > eig[perm[i]]) {
-                    const int t = perm[i];
-                    perm[i] = perm[j];
-                    perm[j] = t;
-                }
-        int bad = 0;
-        const double rm = sqrt((double)M);
-        for (int i = 0; i < R; ++i) {
-            const int c = perm[i];
-            double amax = -1.0, sgn = 1.0;
-            for (int r = 0; r < R; ++r)
-                if (fabs(Q[r][c]) > amax) {
-                    amax = fabs(Q[r][c]);
-                    sgn = Q[r][c] >= 0.0 ? 1.0 : -1.0;
-                }
-            const double g = eig[c];
-            const bool ok = g > 0.0 && isfinite(g);
-            bad |= !ok;
-            scale[i] = ok ? rm / sqrt(g) * sgn : 0.0;
-            if (gout)
-                gout[i] = g;
-        }
-        if (flag)
-            *flag = bad;
-    }
+    __syncthreads();
+    if (tid == 0 && flag)
+        *flag = badf;
     __syncthreads();
     for (int e = tid; e < R * R; e += NT) {
         const int r = e / R, b = e % R;
