@@ -421,6 +421,128 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
         st->counter[kCntDotN] = 0;
 }
 
+// The loading side of an iteration in one workgroup when N <= 1024 (no
+// cross-workgroup reduction, one launch instead of two): q = sum_g q_part[g]
+// (fixed order), q' = q - W d, c = P_(k)^T q', p = q' - P_(k) c (Sec. 2.3),
+// |p| and the loading change -- the steps and state updates of k_fin_q
+// followed by k_gs_apply on the loading side.  Column j belongs to thread j;
+// the partials are summed by NT / N' groups of threads (N' = N rounded up to
+// whole waves), eight loads in flight, groups added in order.
+constexpr int kFinApplyThreads = 1024;
+static_assert(kFinApplyMaxN == kFinApplyThreads, "one column per thread");
+template <typename E>
+__global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
+    const E *__restrict__ q_part, int64_t G, int64_t N, const double *__restrict__ W, int kd,
+    const double *__restrict__ d, const E *__restrict__ P, int kg, double *__restrict__ qy,
+    double *__restrict__ p, double *__restrict__ pprev, LoopState *st, int it, int stop,
+    double tiny)
+{
+    if (st->degenerate)
+        return;
+    const int done = st->done;
+    // the state this iteration started from, read before thread 0 updates it
+    const int iter0 = st->iter;
+    const double pn_old = st->pnorm;
+    if (done && iter0 != it)
+        return;
+    constexpr int NT = kFinApplyThreads, NW = NT / 64;
+    __shared__ double part[NT];
+    __shared__ double qs[NT];
+    __shared__ double cs[NT];
+    __shared__ double red[3][NW];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int Np = (int)((N + 63) / 64) * 64;
+    const int NGr = NT / Np;
+    const int j = tid % Np, gr = tid / Np;
+    const int64_t jc = j < N ? j : N - 1;
+    double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    if (gr < NGr) {
+        for (int64_t g0 = gr; g0 < G; g0 += 8 * (int64_t)NGr) {
+            E x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                const int64_t g = g0 + (int64_t)u * NGr;
+                x[u] = q_part[(g < G ? g : G - 1) * N + jc];
+            }
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                a[u] += g0 + (int64_t)u * NGr < G ? (double)x[u] : 0.0;
+        }
+    }
+    part[tid] = ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
+    __syncthreads();
+    double qv = 0.0;
+    if (tid < N) {
+        double q = 0.0;
+        for (int r = 0; r < NGr; ++r)
+            q += part[r * Np + tid];
+        double wd = 0.0;
+        for (int i = 0; i < kd; ++i)
+            wd += W[tid + (int64_t)i * N] * d[i];
+        qv = q - wd;
+        qy[tid] = qv;
+        qs[tid] = qv;
+    }
+    if (done) // stopped in this iteration: q' only feeds W
+        return;
+    __syncthreads();
+    for (int i = w; i < kg; i += NW) { // c = P^T q': wave per coefficient
+        double sacc = 0.0;
+        for (int jj = lane; jj < N; jj += 64)
+            sacc += (double)P[jj + (int64_t)i * N] * qs[jj];
+        sacc = fwave_sum(sacc);
+        if (lane == 0)
+            cs[i] = sacc;
+    }
+    __syncthreads();
+    double v = 0.0, o = 0.0;
+    if (tid < N) {
+        double pr = 0.0;
+        for (int i = 0; i < kg; ++i)
+            pr += (double)P[tid + (int64_t)i * N] * cs[i];
+        v = qv - pr;
+        o = p[tid];
+        pprev[tid] = o;
+        p[tid] = v;
+    }
+    // |p|^2 and p . p_old: wave sums, then the waves in order
+    double s2 = fwave_sum(v * v), dt = fwave_sum(tid < N ? v * o : 0.0);
+    if (lane == 0) {
+        red[0][w] = s2;
+        red[1][w] = dt;
+    }
+    __syncthreads();
+    double tot = 0.0, dtot = 0.0;
+    for (int q = 0; q < NW; ++q) {
+        tot += red[0][q];
+        dtot += red[1][q];
+    }
+    const double nrm = sqrt(tot);
+    double dp = INFINITY;
+    if (stop == 1 && iter0 > 0 && nrm > 0.0 && pn_old > 0.0) {
+        // |p/|p| - s p_old/|p_old|| (s aligning the signs), fixed order
+        const double ia = 1.0 / nrm, ib = (dtot >= 0.0 ? 1.0 : -1.0) / pn_old;
+        const double e = tid < N ? v * ia - o * ib : 0.0;
+        const double ss = fwave_sum(e * e);
+        if (lane == 0)
+            red[2][w] = ss;
+        __syncthreads();
+        double sst = 0.0;
+        for (int q = 0; q < NW; ++q)
+            sst += red[2][q];
+        dp = sqrt(sst);
+    }
+    if (tid != 0)
+        return;
+    st->dp = dp;
+    st->pnorm = nrm;
+    if (!(nrm >= tiny)) { // counts as the iteration in which it happened
+        st->iter = iter0 + 1;
+        st->degenerate = 1;
+        st->done = 1;
+    }
+}
+
 // Gram-Schmidt coefficients of the score, d = V_(k)^T t (FP64), from the
 // complete t of the pass: workgroup (b, y) takes `rows` consecutive rows of t
 // (staged in LDS, zero past M) and columns [32y, 32y + 32) of V, two columns
@@ -631,6 +753,16 @@ void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int
     hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 64)), dim3(64 * kFinGroups), 0, s, q_part, G, N,
                        W, kd, d, P,
                        kg, qy, cpart, c, st, it);
+}
+
+template <int F>
+void Fused<F>::fin_apply(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
+                         const double *d, const E *P, int kg, double *qy, double *p,
+                         double *pprev, LoopState *st, int it, int stop, double tiny,
+                         hipStream_t s)
+{
+    hipLaunchKernelGGL(k_fin_apply<E>, dim3(1), dim3(kFinApplyThreads), 0, s, q_part, G, N, W, kd,
+                       d, P, kg, qy, p, pprev, st, it, stop, tiny);
 }
 
 template <int F>

@@ -541,9 +541,24 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
         F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE,
                 td, tsq, qpart, st, s);
-        F::fin_q(qpart, f.G, N, W, 0, dvec, P, kg, qy, cpart, cvec, st, 0, s);
-        L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol, limit,
-                    replay, tiny, stop, s);
+        // the loading side: one workgroup when N and the partials are small
+        // (no cross-workgroup reductions; at most 256 KiB of partials, which
+        // one workgroup reads in a few microseconds -- 512 x 256 FP64: 122 ->
+        // 95 ms per fit, while 2 MiB at 2000 x 1000 made it slower), else the
+        // column-parallel reduction and apply kernels
+        const bool one_wg =
+            N <= kFinApplyMaxN && (int64_t)f.G * N * (int64_t)sizeof(E) <= (int64_t)256 * 1024;
+        auto loading_side = [&](int kdv, int it) {
+            if (one_wg) {
+                F::fin_apply(qpart, f.G, N, W, kdv, dvec, P, kg, qy, p, pprev, st, it, stop, tiny,
+                             s);
+            } else {
+                F::fin_q(qpart, f.G, N, W, kdv, dvec, P, kg, qy, cpart, cvec, st, it, s);
+                L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol,
+                            limit, replay, tiny, stop, s);
+            }
+        };
+        loading_side(0, 0);
         int32_t enq = 0;
         int batch = 4;
         bool have = false;
@@ -563,9 +578,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 // itself is formed once, when the component ends
                 F::score_dot(td, M, T, kg, tsq, f.G, cpart, dvec, st, tol, limit, replay, tiny,
                              stop, s);
-                F::fin_q(qpart, f.G, N, W, gs ? kg : 0, dvec, P, kg, qy, cpart, cvec, st, it, s);
-                L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol,
-                            limit, replay, tiny, stop, s);
+                loading_side(gs ? kg : 0, it);
             }
             enq += n;
             if (!read_state())

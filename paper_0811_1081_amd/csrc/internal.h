@@ -166,6 +166,9 @@ __device__ inline double reduce_partials(const double *__restrict__ part, int64_
     return ssq;
 }
 
+// Largest N whose loading side runs in one workgroup (k_fin_apply).
+constexpr int64_t kFinApplyMaxN = 1024;
+
 // Groups of partial sums per workgroup of the loading-side finish (64
 // columns each; 64 * kFinGroups threads).
 constexpr int kFinGroups = 16;
@@ -259,6 +262,11 @@ struct Fused {
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);
+    // fin_q and the loading-side gs_apply in one workgroup (N <= 1024)
+    static void fin_apply(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
+                          const double *d, const E *P, int kg, double *qy, double *p,
+                          double *pprev, LoopState *st, int it, int stop, double tiny,
+                          hipStream_t s);
     static void comp_end(const double *td, const double *d, int kd, E *tE, int64_t M, int64_t N,
                          const double *p, const double *qy, int k, int gs, int explicit_defl,
                          E *T, E *P, double *W, double *sigma, int32_t *iters,

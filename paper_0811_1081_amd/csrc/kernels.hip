@@ -467,9 +467,15 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
         dtot = block_sum(dtot, red);
     const double nrm = sqrt(tot);
     double dp = INFINITY;
-    if (side == 0 && stop == 1 && st->iter > 0 && nrm > 0.0 && st->pnorm > 0.0) {
+    // every thread reads the state before thread 0 updates it (the barrier
+    // below orders the reads of all waves before that update), so the branch
+    // is taken by all threads or by none
+    const int iter0 = st->iter;
+    const double pn_old = st->pnorm;
+    __syncthreads();
+    if (side == 0 && stop == 1 && iter0 > 0 && nrm > 0.0 && pn_old > 0.0) {
         // |p/|p| - s q/|q||^2 over the whole vector (fixed order, this workgroup)
-        const double a = 1.0 / nrm, bq = (dtot >= 0.0 ? 1.0 : -1.0) / st->pnorm;
+        const double a = 1.0 / nrm, bq = (dtot >= 0.0 ? 1.0 : -1.0) / pn_old;
         double ss = 0.0;
         for (int64_t i = threadIdx.x; i < L; i += kBlock) {
             const double dd = ydst[i] * a - yprev[i] * bq;
