@@ -292,6 +292,107 @@ __global__ __launch_bounds__(256) void k_sketch(const float *__restrict__ X, int
     }
 }
 
+// The same product when X's columns are 16-byte aligned (ldx a multiple of
+// 4): workgroup b owns rows [64b, 64b + 64) (1024 workgroups at M = 65536);
+// 16-column chunks of X and the matching 16 rows of Omega are staged in LDS
+// with 16-byte loads, the next chunk's loads in flight while the current one
+// is multiplied (two LDS buffers, one barrier per chunk); each of the 256
+// threads accumulates a 4 x (R/16) block of Y in FP32, over j in the same
+// order as k_sketch.
+typedef float sf32x2_t __attribute__((ext_vector_type(2)));
+template <int R>
+__global__ __launch_bounds__(256) void k_sketch_v(const float *__restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t N,
+                                                  const float *__restrict__ Om,
+                                                  float *__restrict__ Y)
+{
+    constexpr int BM = 64, BK = 16, RB = R / 16, OQ = BK * R / 4;
+    __shared__ __align__(16) float xs[2][BK][BM];
+    __shared__ __align__(16) float os[2][BK][R];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4; // rows 4tx..4tx+3, sketch columns RB*ty..
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    mf32x4_t xr, orr = {0.f, 0.f, 0.f, 0.f};
+    auto gload = [&](int64_t j0) {
+        { // column c, rows 4q..4q+3 of the tile
+            const int c = tid >> 4, q = tid & 15;
+            const int64_t m = m0 + 4 * q, j = j0 + c;
+            if (j < N && m + 3 < M) {
+                xr = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    xr[u] = (j < N && m + u < M) ? X[m + u + j * ldx] : 0.0f;
+            }
+        }
+        if (tid < OQ) { // Omega row c, columns 4u..4u+3
+            const int c = tid / (R / 4), u = tid % (R / 4);
+            const int64_t j = j0 + c;
+            if (j < N)
+                orr = *reinterpret_cast<const mf32x4_t *>(Om + j * R + 4 * u);
+            else
+                orr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto sstore = [&](int b) {
+        const int c = tid >> 4, q = tid & 15;
+        *reinterpret_cast<mf32x4_t *>(&xs[b][c][4 * q]) = xr;
+        if (tid < OQ) {
+            const int c2 = tid / (R / 4), u = tid % (R / 4);
+            *reinterpret_cast<mf32x4_t *>(&os[b][c2][4 * u]) = orr;
+        }
+    };
+    float acc[4][RB];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            acc[a][b] = 0.0f;
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = 0; j0 < N; j0 += BK) {
+        const bool more = j0 + BK < N;
+        if (more)
+            gload(j0 + BK); // in flight while this chunk is multiplied
+#pragma unroll 4
+        for (int c = 0; c < BK; ++c) {
+            const mf32x4_t x0 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][c][4 * tx]);
+            float ov[RB];
+            if constexpr (RB == 4) {
+                const mf32x4_t o = *reinterpret_cast<const mf32x4_t *>(&os[buf][c][RB * ty]);
+                ov[0] = o[0]; ov[1] = o[1]; ov[2] = o[2]; ov[3] = o[3];
+            } else {
+                const sf32x2_t o = *reinterpret_cast<const sf32x2_t *>(&os[buf][c][RB * ty]);
+                ov[0] = o[0]; ov[1] = o[1];
+            }
+            const float xv[4] = {x0[0], x0[1], x0[2], x0[3]};
+#pragma unroll
+            for (int a = 0; a < 4; ++a)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[a][b] += xv[a] * ov[b];
+        }
+        if (more)
+            sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t m = m0 + 4 * tx + a;
+        if (m < M) {
+            float *yr = Y + m * R + RB * ty;
+            if constexpr (RB == 4)
+                *reinterpret_cast<mf32x4_t *>(yr) =
+                    mf32x4_t{acc[a][0], acc[a][1], acc[a][2], acc[a][3]};
+            else
+                *reinterpret_cast<sf32x2_t *>(yr) = sf32x2_t{acc[a][0], acc[a][1]};
+        }
+    }
+}
+
 // W = s X^T Z (N x R, row-major) for a row-major M x R sketch Z, as partial
 // sums over row slices.  Workgroup (b, y) owns columns [64b, 64b + 64) of X
 // over row slice y: 32-row tiles of X (64 columns, read along the rows) and
@@ -355,6 +456,117 @@ __global__ __launch_bounds__(256) void k_sketch_t(const float *__restrict__ X, i
 #pragma unroll
             for (int b = 0; b < RB; ++b)
                 W[j * R + RB * ty + b] = acc[a][b] * s;
+    }
+}
+
+// The same product when X's columns are 16-byte aligned (ldx a multiple of
+// 4): workgroup (b, y) owns columns [128b, 128b + 128) of X over row slice y;
+// 16-row chunks of X (16-byte loads along the rows, transposed into LDS) and
+// of Z are staged in two LDS buffers with the next chunk's loads in flight;
+// each thread accumulates an 8 x (R/16) block of W in FP32, over the rows in
+// the same order as k_sketch_t.
+template <int R>
+__global__ __launch_bounds__(256) void k_sketch_t_v(const float *__restrict__ X, int64_t ldx,
+                                                    int64_t M, int64_t N,
+                                                    const float *__restrict__ Z, float s,
+                                                    int64_t rows, float *__restrict__ W)
+{
+    constexpr int BN = 128, BK = 16, RB = R / 16, ZQ = BK * R / 4;
+    __shared__ __align__(16) float xs[2][BK][BN];
+    __shared__ __align__(16) float zs[2][BK][R];
+    const int tid = threadIdx.x;
+    const int tx = tid & 15, ty = tid >> 4; // X columns 8tx..8tx+7, sketch columns RB*ty..
+    const int64_t j0 = (int64_t)blockIdx.x * BN;
+    const int64_t rb = (int64_t)blockIdx.y * rows;
+    const int64_t re = M < rb + rows ? M : rb + rows;
+    W += (int64_t)blockIdx.y * N * R;
+    mf32x4_t xr[2], zr = {0.f, 0.f, 0.f, 0.f};
+    auto gload = [&](int64_t r0) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) { // column c, rows 4q..4q+3 of the chunk
+            const int e = tid + 256 * h, c = e >> 2, q = e & 3;
+            const int64_t m = r0 + 4 * q, j = j0 + c;
+            if (j < N && m + 3 < re) {
+                xr[h] = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    xr[h][u] = (j < N && m + u < re) ? X[m + u + j * ldx] : 0.0f;
+            }
+        }
+        if (tid < ZQ) { // Z row c, columns 4u..4u+3
+            const int c = tid / (R / 4), u = tid % (R / 4);
+            const int64_t m = r0 + c;
+            if (m < re)
+                zr = *reinterpret_cast<const mf32x4_t *>(Z + m * R + 4 * u);
+            else
+                zr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto sstore = [&](int b) {
+#pragma unroll
+        for (int h = 0; h < 2; ++h) {
+            const int e = tid + 256 * h, c = e >> 2, q = e & 3;
+#pragma unroll
+            for (int u = 0; u < 4; ++u)
+                xs[b][4 * q + u][c] = xr[h][u];
+        }
+        if (tid < ZQ) {
+            const int c = tid / (R / 4), u = tid % (R / 4);
+            *reinterpret_cast<mf32x4_t *>(&zs[b][c][4 * u]) = zr;
+        }
+    };
+    float acc[8][RB];
+#pragma unroll
+    for (int a = 0; a < 8; ++a)
+#pragma unroll
+        for (int b = 0; b < RB; ++b)
+            acc[a][b] = 0.0f;
+    if (rb < re) {
+        gload(rb);
+        sstore(0);
+    }
+    __syncthreads();
+    int buf = 0;
+    for (int64_t r0 = rb; r0 < re; r0 += BK) {
+        const bool more = r0 + BK < re;
+        if (more)
+            gload(r0 + BK); // in flight while this chunk is multiplied
+#pragma unroll 2
+        for (int i = 0; i < BK; ++i) {
+            const mf32x4_t x0 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][i][8 * tx]);
+            const mf32x4_t x1 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][i][8 * tx + 4]);
+            float zv[RB];
+            if constexpr (RB == 4) {
+                const mf32x4_t z = *reinterpret_cast<const mf32x4_t *>(&zs[buf][i][RB * ty]);
+                zv[0] = z[0]; zv[1] = z[1]; zv[2] = z[2]; zv[3] = z[3];
+            } else {
+                const sf32x2_t z = *reinterpret_cast<const sf32x2_t *>(&zs[buf][i][RB * ty]);
+                zv[0] = z[0]; zv[1] = z[1];
+            }
+            const float xv[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
+#pragma unroll
+            for (int a = 0; a < 8; ++a)
+#pragma unroll
+                for (int b = 0; b < RB; ++b)
+                    acc[a][b] += xv[a] * zv[b];
+        }
+        if (more)
+            sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+        const int64_t j = j0 + 8 * tx + a;
+        if (j < N) {
+            float *wr = W + j * R + RB * ty;
+            if constexpr (RB == 4)
+                *reinterpret_cast<mf32x4_t *>(wr) =
+                    mf32x4_t{acc[a][0] * s, acc[a][1] * s, acc[a][2] * s, acc[a][3] * s};
+            else
+                *reinterpret_cast<sf32x2_t *>(wr) = sf32x2_t{acc[a][0] * s, acc[a][1] * s};
+        }
     }
 }
 
@@ -755,6 +967,17 @@ bool valid_rank(int32_t r) { return r == 32 || r == GSPCA_WS_RMAX; }
 void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
                    float *Y, hipStream_t s)
 {
+    const bool aligned = ldx % 4 == 0 && ((uintptr_t)X) % 16 == 0 && ((uintptr_t)Om) % 16 == 0 &&
+                         ((uintptr_t)Y) % 16 == 0;
+    if (aligned) {
+        if (r == 32)
+            hipLaunchKernelGGL(k_sketch_v<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
+                               Om, Y);
+        else
+            hipLaunchKernelGGL(k_sketch_v<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
+                               Om, Y);
+        return;
+    }
     if (r == 32)
         hipLaunchKernelGGL(k_sketch<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N, Om, Y);
     else
@@ -767,11 +990,25 @@ void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const fl
     const SketchPlan P = sketch_plan(M, N, r);
     const float sc = (float)(1.0 / sqrt((double)M));
     float *dst = P.st == 1 ? W : reinterpret_cast<float *>(ws + P.off_wpart);
-    const dim3 g(ucdiv(N, 64), (unsigned)P.st);
-    if (r == 32)
-        hipLaunchKernelGGL(k_sketch_t<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t, dst);
-    else
-        hipLaunchKernelGGL(k_sketch_t<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t, dst);
+    const bool aligned = ldx % 4 == 0 && ((uintptr_t)X) % 16 == 0 && ((uintptr_t)Z) % 16 == 0 &&
+                         ((uintptr_t)dst) % 16 == 0 && P.rows_t % 16 == 0;
+    if (aligned) {
+        const dim3 g(ucdiv(N, 128), (unsigned)P.st);
+        if (r == 32)
+            hipLaunchKernelGGL(k_sketch_t_v<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+                               dst);
+        else
+            hipLaunchKernelGGL(k_sketch_t_v<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+                               dst);
+    } else {
+        const dim3 g(ucdiv(N, 64), (unsigned)P.st);
+        if (r == 32)
+            hipLaunchKernelGGL(k_sketch_t<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+                               dst);
+        else
+            hipLaunchKernelGGL(k_sketch_t<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+                               dst);
+    }
     if (P.st > 1) // slice partials added in slice order
         hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(N * r, 256)), dim3(256), 0, s, dst,
                            (int)P.st, N, (int64_t)r, W, (int64_t)r, (int64_t)1);
