@@ -52,10 +52,11 @@ def _oracle_params(orc, net):
     return [orc.bf16_round(x) if i % 2 == 0 else x for i, x in enumerate(p)]
 
 
-def test_sketch_matches_oracle(orc):
+@pytest.mark.parametrize("M", [1000, 1001])  # 16-byte aligned columns, and not
+def test_sketch_matches_oracle(orc, M):
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
-    X = synth.warmstart_instance(1, M=1000, N=200)[0]
+    X = synth.warmstart_instance(1, M=M, N=200)[0]
     Om = synth.sketch_matrix(200, 32)
     Y = ws.sketch(_colmajor(X), _dev(Om))
     torch.cuda.synchronize()
@@ -65,11 +66,11 @@ def test_sketch_matches_oracle(orc):
     assert np.all(np.abs(Y.cpu().numpy() - Yo) <= bound + 1e-30)
 
 
-@pytest.mark.parametrize("r", [32, 64])
-def test_refinement_step_matches_oracle(orc, r):
+@pytest.mark.parametrize("r,M", [(32, 900), (64, 900), (64, 903)])  # aligned columns, and not
+def test_refinement_step_matches_oracle(orc, r, M):
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
-    X = synth.warmstart_instance(4, M=900, N=150)[0]  # 150 columns: 3 blocks of 64, ragged
+    X = synth.warmstart_instance(4, M=M, N=150)[0]  # 150 columns: ragged blocks
     Xd = _colmajor(X)
     Z = ws.whiten(ws.sketch(Xd, _dev(synth.sketch_matrix(150, r))))[0]
     W, Y = ws.sketch_refine(Xd, Z)
