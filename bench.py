@@ -273,7 +273,15 @@ def bench_batched(args):
     mn = np.array([m * n for m, n, _ in shapes], dtype=np.float64)
     it_sum = np.array([int(x.sum()) for x in its], dtype=np.float64)
     compulsory = float(mn.sum() * 4)              # every matrix read from HBM once
-    streamed = float((2.0 * mn * 4 * it_sum).sum())  # X read for t and for q every iteration
+    # reads of each matrix: its column norms, per component the first loading
+    # (q = X^T t0) and one read per iteration (t and q from one pass; two when
+    # a problem has more than 32 columns per wave), and W's column X^T v for
+    # every component but the last
+    nwaves = threads // 64
+    per_iter = np.array([1.0 if n <= 32 * nwaves else 2.0 for _, n, _ in shapes])
+    kk = np.array([k for _, _, k in shapes], dtype=np.float64)
+    reads = 1.0 + kk + per_iter * it_sum + (kk - 1.0)
+    streamed = float((mn * 4 * reads).sum())
     res = {
         "metric": "batched GS-PCA components/s (2048 uneven problems, one persistent launch)",
         "value": comps * args.steps / elapsed, "unit": "components/s", "n_gpus": 1,
@@ -288,9 +296,10 @@ def bench_batched(args):
                      "frac": streamed / ms / 1e6 / HBM_PEAK_GBPS, "traffic": None,
                      "bytes_per_launch": streamed, "avg_launch_us": ms * 1e3,
                      "compulsory_bytes": compulsory,
-                     "note": "algorithmic bytes: every iteration reads each problem's matrix "
-                             "twice (t = X p, q = X^T t), summed over the iterations run; part "
-                             "of the re-reads are served by L2/MALL"},
+                     "note": "algorithmic bytes: each problem's matrix is read once per "
+                             "iteration (t = X p and q = X^T t from one pass), once per "
+                             "component for its first loading and for W, and once for the "
+                             "column norms; part of the re-reads are served by L2/MALL"},
         "cache_stream_GBps": streamed / ms / 1e6,
         "iters_mean": float(it_sum.sum() / comps),
         "status_ok": int((st == 0).sum()), "status_not_converged": int((st == 1).sum()),

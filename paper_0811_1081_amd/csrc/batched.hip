@@ -12,16 +12,21 @@
 //
 // Per iteration (FP32 data, FP64 Gram-Schmidt and norms, implicit deflation
 // R = X - T P^T on Gram-Schmidt-projected vectors):
-//   t = X p                 threads over rows (coalesced columns of X)
+//   t = X p, q = X^T t      one read of X (batch_pass): a tile of rows is
+//                           held in registers while its t is summed across
+//                           the waves, then multiplied back into q
 //   d = V_(k)^T t           waves over components, lanes over rows
 //   t <- t - V d, sigma = |t|, stop test (relative sigma, loading, replay)
-//   q = X^T t               waves over columns, lanes over rows
+//   q <- q - W d            W = X^T V_(k), so q = X^T (t - V d)
 //   c = P_(k)^T q, p = q - P c, p / |p|
-// t, q, p, the column norms and the coefficient vectors live in LDS.
+// t, q, p, the column norms and the coefficient vectors live in LDS.  A
+// problem with more than 32 columns per wave reads X twice instead (t = X p
+// with threads over rows, then q = X^T t with waves over columns).
 #include <float.h>
 #include <math.h>
 
 #include "internal.h"
+#include "panel.h"
 
 namespace gspca {
 
@@ -71,6 +76,103 @@ __device__ inline double lane_dot(const float *__restrict__ col, const double *_
     return (s0 + s1) + (s2 + s3);
 }
 
+// LDS floats (at the start of the dynamic LDS) for the cross-wave sums of
+// batch_pass: two buffers of one value per thread of a 1024-thread workgroup.
+constexpr int kPassLdsFloats = 2 * 1024;
+
+// Column split of the single pass: CW waves share the columns of a row tile,
+// CPW (a power of two, 4..32) columns per wave; 0 when N needs more than 32
+// columns per wave or X's element offsets do not fit 32 bits.
+__device__ inline void pass_split(int N, int64_t ldx, int nw, int &CW, int &CPW)
+{
+    int cw = 1;
+    while (cw * 32 < N)
+        cw <<= 1;
+    if (cw > nw || ldx * (int64_t)N >= ((int64_t)1 << 31)) {
+        CW = 0;
+        CPW = 0;
+        return;
+    }
+    const int per = (N + cw - 1) / cw;
+    int c = 4;
+    while (c < per)
+        c <<= 1;
+    CW = cw;
+    CPW = c;
+}
+
+// t = X p and q = X^T t from one read of X (Sec. 2.3's two products).  The
+// waves form CW column groups x RS row groups; a tile is 64 RS rows: lane l
+// of row group r takes row 64 r + l and CPW consecutive columns of its column
+// group (coalesced 256-byte loads down each column), forms its share of t in
+// FP32, the CW shares of a row are added in FP64 through LDS (fixed order),
+// and the same registers then give the row's terms of q = X^T t, summed over
+// the wave's 64 rows with a reduce-scatter; each lane keeps the FP64 running
+// sum of one column.  Rows past M are read clamped and weigh 0; columns past
+// N are read clamped with p = 0 and dropped.  t and q are written to LDS.
+template <int CPW>
+__device__ void batch_pass(const float *__restrict__ X, int64_t ldx, int M, int N, int CW,
+                           const float *pf, float *xr, double *t, double *q)
+{
+    const int tid = threadIdx.x, lane = tid & 63, NT = blockDim.x;
+    const int nw = NT >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int cw = w % CW, rs = w / CW, RS = nw / CW;
+    // a wave's columns may lie wholly past N (then it contributes zeros)
+    const int cbase = cw * CPW;
+    const int ld = (int)ldx, navail = N - cbase;
+    // the wave's p values are re-read from LDS (one broadcast read each) in
+    // every tile rather than held in registers
+    const int tile = 64 * RS;
+    double qacc = 0.0;
+    int slot = 0;
+    int buf = 0;
+    for (int m0 = 0; m0 < M; m0 += tile) {
+        const int row = m0 + rs * 64 + lane;
+        const int rowc = row < M ? row : M - 1;
+        float x[CPW];
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            x[c] = X[(c < navail ? cbase + c : N - 1) * ld + rowc];
+        float ta = 0.f, tb = 0.f;
+#pragma unroll
+        for (int c = 0; c < CPW; c += 2) {
+            ta += x[c] * (c < navail ? pf[cbase + c] : 0.f);
+            tb += x[c + 1] * (c + 1 < navail ? pf[cbase + c + 1] : 0.f);
+        }
+        float *red = xr + buf * 1024;
+        red[cw * tile + rs * 64 + lane] = ta + tb;
+        __syncthreads();
+        double tv = 0.0;
+        for (int g = 0; g < CW; ++g)
+            tv += (double)red[g * tile + rs * 64 + lane];
+        if (row >= M)
+            tv = 0.0;
+        else if (cw == 0)
+            t[row] = tv;
+        const float tf = (float)tv;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c)
+            x[c] *= tf;
+        qacc += (double)wave_scatter_sum<float, CPW>(x, lane, slot);
+        buf ^= 1;
+    }
+    // q: the row groups' sums of each column, in order (the buffers are free
+    // once every wave has passed this barrier)
+    __syncthreads();
+    double *qr = reinterpret_cast<double *>(xr);
+    const int width = CW * CPW;
+    if ((lane & (64 / CPW - 1)) == 0 && cbase + slot < N)
+        qr[rs * width + cbase + slot] = qacc;
+    __syncthreads();
+    for (int j = tid; j < N; j += NT) {
+        double v = 0.0;
+        for (int r = 0; r < RS; ++r)
+            v += qr[r * width + j];
+        q[j] = v;
+    }
+}
+
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
 
 __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ items, int nprob,
@@ -92,7 +194,8 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             cur = i < (uint32_t)nprob ? order[i] : -1;
         }
         __syncthreads();
-        const int pi = cur;
+        // uniform values read from LDS go to scalar registers
+        const int pi = __builtin_amdgcn_readfirstlane(cur);
         __syncthreads();
         if (pi < 0)
             return;
@@ -102,8 +205,10 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
         const float *X = it.X;
         float *T = it.T, *P = it.P;
         double *W = it.W; // N x K: X^T v_i of finished components
-        // LDS: t[M] | q[N] | p[N] | pprev[N] | cn0[N] | sig[K] | dc[K] | pf[N] (float)
-        double *t = lds;
+        // LDS: pass buffers | t[M] | q[N] | p[N] | pprev[N] | cn0[N] | sig[K] | dc[K]
+        //      | pf[N] (float)
+        float *xr = reinterpret_cast<float *>(lds);
+        double *t = lds + kPassLdsFloats / 2;
         double *q = t + M;
         double *p = q + N;
         double *pprev = p + N;
@@ -136,6 +241,8 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             continue;
         }
         int not_conv = 0;
+        int CW = 0, CPW = 0;
+        pass_split(N, ldx, nw, CW, CPW);
 
         for (int k = 0; k < K; ++k) {
             const int32_t limit = it.replay_iters ? it.replay_iters[k] : a.max_iter;
@@ -200,7 +307,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                     sel = selmax;
                 __syncthreads();
             }
-            const int64_t c0 = sel;
+            const int64_t c0 = (int64_t)__builtin_amdgcn_readfirstlane((int)sel);
             // t0 = X_c - sum_i s_i v_i P_ci, or the given vector
             double ss = 0.0;
             for (int m = tid; m < M; m += NT) {
@@ -221,13 +328,24 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             double s_cur = 0.0, mu = 0.0, pn = 1.0, dp = INFINITY;
             int iters = 0, conv = 0;
 
-            // loading from t: q = X^T t, one GS pass, norm (Sec. 2.3)
-            auto loading = [&](int first) -> bool {
+            // loading from t: q = X^T t, one GS pass, norm (Sec. 2.3).  After
+            // a single pass q holds X^T t for the t before its Gram-Schmidt
+            // step, and q - W d is X^T of the projected t.
+            auto loading = [&](int first, int from_pass) -> bool {
                 __syncthreads();
-                for (int j = w; j < N; j += nw) {
-                    const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
-                    if (lane == 0)
-                        q[j] = s;
+                if (!from_pass) {
+                    for (int j = w; j < N; j += nw) {
+                        const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
+                        if (lane == 0)
+                            q[j] = s;
+                    }
+                } else if (k > 0) {
+                    for (int j = tid; j < N; j += NT) {
+                        double wd = 0.0;
+                        for (int i = 0; i < k; ++i)
+                            wd += W[j + (int64_t)i * N] * dc[i];
+                        q[j] -= wd;
+                    }
                 }
                 __syncthreads();
                 for (int i = w; i < k; i += nw) {
@@ -267,7 +385,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             };
 
             if (!degenerate) {
-                if (!loading(1)) {
+                if (!loading(1, 0)) {
                     degenerate = 1;
                     iters = 1;
                 }
@@ -279,7 +397,14 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 for (int j = tid; j < N; j += NT)
                     pf[j] = (float)(p[j] / pn);
                 __syncthreads();
-                for (int m = tid; m < M; m += NT) {
+                switch (CPW) {
+                case 4: batch_pass<4>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 8: batch_pass<8>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 16: batch_pass<16>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 32: batch_pass<32>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                default: break;
+                }
+                for (int m = CPW ? M : tid; m < M; m += NT) {
                     // sixteen columns per step, all loads issued before use
                     float a0 = 0.f, a1 = 0.f, a2 = 0.f, a3 = 0.f;
                     const float *xr = X + m;
@@ -335,7 +460,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 }
                 if (iters >= limit)
                     break;
-                if (!loading(0)) {
+                if (!loading(0, CPW != 0)) {
                     degenerate = 1;
                     ++iters;
                     break;

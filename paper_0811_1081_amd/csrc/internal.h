@@ -314,7 +314,8 @@ void batched_launch(const BatchItem *items, int nprob, const int32_t *order, uin
                     BatchArgs a, int grid, int threads, size_t lds_bytes, hipStream_t s);
 inline size_t batched_lds_bytes(int64_t M, int64_t N, int64_t K)
 {
-    return (size_t)(M + 4 * N + 2 * K) * 8 + (size_t)N * 4;
+    // 8 KiB of cross-wave sums for the single pass, then the vectors
+    return (size_t)8192 + (size_t)(M + 4 * N + 2 * K) * 8 + (size_t)N * 4;
 }
 
 }  // namespace gspca
