@@ -547,9 +547,11 @@ __global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
 // complete t of the pass: workgroup (b, y) takes `rows` consecutive rows of t
 // (staged in LDS, zero past M) and columns [32y, 32y + 32) of V, two columns
 // per wave; a lane issues the loads of 16 rows of both its columns before the
-// first use (row and column indices clamped, their weights zero).  Per-row-
-// block partials are added in a fixed order by the last workgroup, which
-// also finishes sigma and the stop test.
+// first use (row and column indices clamped, their weights zero; the first
+// chunk's loads are issued before the barrier that publishes the rows of t).
+// Per-row-block partials are added in a fixed order by the last workgroup,
+// which also finishes sigma and the stop test; a grid of one workgroup keeps
+// its partials in LDS and needs no arrival counter.
 constexpr int kScoreThreads = 1024;
 template <typename E>
 __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
@@ -561,26 +563,34 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
         return;
     __shared__ double ts[kScoreRows];
     __shared__ double lds[kScoreThreads];
+    __shared__ double dsh[32];
     __shared__ int last;
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, nw = kScoreThreads / 64;
+    const bool single = gridDim.x == 1 && gridDim.y == 1;
     const int64_t r0 = (int64_t)blockIdx.x * rows;
     const int n = (int)(M - r0 < rows ? M - r0 : rows);
+    const int i0 = 32 * (int)blockIdx.y + w, i1 = i0 + nw;
+    const E *c0 = V + (int64_t)(i0 < kd ? i0 : (kd > 0 ? kd - 1 : 0)) * M + r0;
+    const E *c1 = V + (int64_t)(i1 < kd ? i1 : (kd > 0 ? kd - 1 : 0)) * M + r0;
+    E v0[16], v1[16];
+    auto load_chunk = [&](int x0) {
+#pragma unroll
+        for (int u = 0; u < 16; ++u) {
+            const int x = x0 + lane + 64 * u, xc = x < n ? x : n - 1;
+            v0[u] = c0[xc];
+            v1[u] = c1[xc];
+        }
+    };
+    if (kd > 0)
+        load_chunk(0);
     for (int x = tid; x < rows; x += kScoreThreads)
         ts[x] = x < n ? t[r0 + x] : 0.0;
     __syncthreads();
     if (kd > 0) {
-        const int i0 = 32 * (int)blockIdx.y + w, i1 = i0 + nw;
-        const E *c0 = V + (int64_t)(i0 < kd ? i0 : kd - 1) * M + r0;
-        const E *c1 = V + (int64_t)(i1 < kd ? i1 : kd - 1) * M + r0;
         double a0 = 0.0, a1 = 0.0;
         for (int x0 = 0; x0 < n; x0 += 16 * 64) {
-            E v0[16], v1[16];
-#pragma unroll
-            for (int u = 0; u < 16; ++u) {
-                const int x = x0 + lane + 64 * u, xc = x < n ? x : n - 1;
-                v0[u] = c0[xc];
-                v1[u] = c1[xc];
-            }
+            if (x0 > 0)
+                load_chunk(x0);
 #pragma unroll
             for (int u = 0; u < 16; ++u) {
                 const double tv = ts[x0 + lane + 64 * u]; // zero past n
@@ -590,13 +600,20 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
         }
         const double s0 = fwave_sum(a0), s1 = fwave_sum(a1);
         if (lane == 0) {
-            if (i0 < kd && i0 < 32 * (int)blockIdx.y + 32)
-                cpart[(int64_t)blockIdx.x * kd + i0] = s0;
-            if (i1 < kd && i1 < 32 * (int)blockIdx.y + 32)
-                cpart[(int64_t)blockIdx.x * kd + i1] = s1;
+            if (single) {
+                if (i0 < kd)
+                    dsh[i0] = s0;
+                if (i1 < kd)
+                    dsh[i1] = s1;
+            } else {
+                if (i0 < kd && i0 < 32 * (int)blockIdx.y + 32)
+                    cpart[(int64_t)blockIdx.x * kd + i0] = s0;
+                if (i1 < kd && i1 < 32 * (int)blockIdx.y + 32)
+                    cpart[(int64_t)blockIdx.x * kd + i1] = s1;
+            }
         }
     }
-    if (!arrive_last(&st->counter[kCntDotM], &last))
+    if (!single && !arrive_last(&st->counter[kCntDotM], &last))
         return;
     // the |t|^2 partials and the loop state are loaded before the partials of
     // d are reduced, so that their loads overlap
@@ -606,7 +623,17 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
     ScoreState ss{};
     if (tid == 0)
         ss = score_state(st);
-    const double ssq = kd > 0 ? reduce_partials<16>(cpart, gridDim.x, kd, d, lds) : 0.0;
+    double ssq = 0.0;
+    if (single) {
+        __syncthreads();
+        if (tid < kd) {
+            const double dv = dsh[tid];
+            d[tid] = dv;
+            ssq = dv * dv;
+        }
+    } else if (kd > 0) {
+        ssq = reduce_partials<16>(cpart, gridDim.x, kd, d, lds);
+    }
     // |t|^2 and |d|^2 in a fixed order: wave sums, then the waves in order
     const double tqw = fwave_sum(tq), ssw = fwave_sum(ssq);
     __syncthreads();
@@ -622,7 +649,8 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
         tt += lds[q];
         dd += lds[nw + q];
     }
-    st->counter[kCntDotM] = 0;
+    if (!single)
+        st->counter[kCntDotM] = 0;
     // sigma = |t - V d| = sqrt(|t|^2 - |d|^2) (V orthonormal; d is at rounding
     // level once t has been formed from a loading orthogonal to P_(k))
     const double s2 = tt - dd;
