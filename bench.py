@@ -109,6 +109,9 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5, refine_i
                   FP8 representation error is larger).
       block_fp32: not GS-PCA: the block iteration with Rayleigh-Ritz
                   (gspca_fit_block) from the same sketch, all K at once.
+      block_warm_fp32: the block iteration's scores as the given starts of
+                  the FP32 GS-PCA fit (which then ends at its own loading
+                  stop, usually after two iterations per component).
     Times are HIP-event totals with the input resident in HBM."""
     import torch
     from paper_0811_1081_amd import synth, warmstart as ws
@@ -178,6 +181,17 @@ def precision_form(gp, Xd, K, tol_loading, max_iter, log, low_tol=1e-5, refine_i
                          "max_loading_err": float(loading_angles(blk["P"], Pref).max()),
                          "status": int(blk["status"])}
     log("precision form: block_fp32 %.1f ms, %d iterations" % (ms_blk, blk["iters"]))
+    fin, ms_fin = timed(lambda: gp.fit(Xd, K, tol=tol_loading, max_iter=max_iter, init="given",
+                                       T0=blk["T"], stop="loading", check=False,
+                                       implicit=refine_implicit))
+    total = ms_blk + ms_fin
+    out["block_warm_fp32"] = {"ms": total, "speedup_vs_plain": ms_plain / total,
+                              "block_ms": ms_blk, "fp32_refine_ms": ms_fin,
+                              "refine_iters_mean": float(fin["iters"].double().mean()),
+                              "max_loading_err": float(loading_angles(fin["P"], Pref).max()),
+                              "status": int(fin["status"])}
+    log("precision form: block_warm_fp32 %.1f ms (GS-PCA %.1f ms, %.2f iterations per "
+        "component)" % (total, ms_fin, out["block_warm_fp32"]["refine_iters_mean"]))
     return out
 
 
