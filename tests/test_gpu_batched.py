@@ -214,3 +214,41 @@ def test_batched_given_start(orc):
             assert col_angles(b.P[i].cpu().numpy(), o.P)[ok].max() <= 1e-5
     with pytest.raises(ValueError):
         gp.Batch(Xs, [k for _, k in probs], init="given")
+
+
+@pytest.mark.parametrize("threads", [256, 512, 1024])
+def test_batched_single_pass_column_splits(orc, tmp_path, threads):
+    """Every workgroup size on shapes at the edges of the single pass's column
+    split (one column group, 32 columns per wave, groups past N, more than 32
+    columns per wave -> two reads) and of its row tiles (M below, at and past
+    multiples of 64): parity with the FP64 oracle on the same trajectory."""
+    import torch
+    import paper_0811_1081_amd as gp
+    from paper_0811_1081_amd import synth
+    shapes = [(5, 4), (63, 16), (64, 31), (65, 32), (200, 33), (130, 64), (300, 65),
+              (129, 128), (700, 129), (257, 256), (1000, 257), (333, 300), (1100, 512)]
+    probs = []
+    for i, (M, N) in enumerate(shapes):
+        r = min(M, N, 12)
+        X = synth.haar_spectrum(M, N, 0.75 ** np.arange(r), 1e-3, seed=(14, 50_000 + i),
+                                dtype=np.float32)
+        probs.append((X, min(4, M, N)))
+    Xs = [_gh().to_device(X) for X, _ in probs]
+    Ks = [k for _, k in probs]
+    cache = tmp_path / "tune.jsonl"
+    os.environ["GSPCA_TUNE_CACHE"] = str(cache)
+    try:
+        gp.Batch(Xs, Ks, tol=1e-6).tune()
+        line = cache.read_text().strip().splitlines()[0]
+        key = line.split('"key":"')[1].split('"')[0]
+        cache.write_text('{"key":"%s","threads":%d,"occ":1,"ms":1.0}\n' % (key, threads))
+        b = gp.Batch(Xs, Ks, tol=1e-6, max_iter=1000)
+        assert b.shape() == (threads, 1)
+        b.launch()
+        torch.cuda.synchronize()
+    finally:
+        del os.environ["GSPCA_TUNE_CACHE"]
+    assert np.all(b.status.cpu().numpy() == 0)
+    for i, (X, K) in enumerate(probs):
+        _check(orc, X, K, b.T[i].cpu().numpy(), b.P[i].cpu().numpy(), b.sigma[i].cpu().numpy(),
+               b.iters[i].cpu().numpy(), b.start_col[i].cpu().numpy())
