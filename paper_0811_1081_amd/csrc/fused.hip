@@ -767,7 +767,7 @@ void Fused<F>::score_dot(const double *t, int64_t M, const E *V, int kd, const d
                          int G, double *cpart, double *d, LoopState *st, double tol,
                          int32_t limit, int replay, double tiny, int stop, hipStream_t s)
 {
-    const int64_t rows = score_rows(M);
+    const int64_t rows = score_rows(M, kd);
     const unsigned cols = kd > 0 ? (unsigned)fcdiv(kd, 32) : 1u;
     hipLaunchKernelGGL(k_score_dot<E>, dim3(fcdiv(M, rows), cols), dim3(kScoreThreads), 0, s, t,
                        M, V, kd, rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);

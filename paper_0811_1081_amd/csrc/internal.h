@@ -175,9 +175,16 @@ constexpr int kFinGroups = 16;
 
 // Rows per workgroup of the score coefficient reduction: whole blocks of
 // 1024, about 96 row blocks, at most kScoreRows (staged in LDS as FP64).
+// A single workgroup takes everything (no arrival counter) when t fits it
+// and it has at most two 1024-row chunks of V to read (kd <= 32), or none:
+// FP64 sweep at M = 2000, 264 -> 237 ms per GS fit; at M = 4000 the four
+// chunks in one workgroup cost more than the counter (493 -> 518 ms), while
+// NIPALS (no V) still gained (331 -> 307 ms).
 constexpr int64_t kScoreRows = 4096;
-inline int64_t score_rows(int64_t M)
+inline int64_t score_rows(int64_t M, int kd)
 {
+    if ((kd == 0 && M <= kScoreRows) || (kd <= 32 && M <= 2048))
+        return (M + 1023) / 1024 * 1024;
     const int64_t r = ((M + 95) / 96 + 1023) / 1024 * 1024;
     return r > kScoreRows ? kScoreRows : r;
 }
