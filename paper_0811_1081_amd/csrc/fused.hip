@@ -213,6 +213,36 @@ __global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict
     cn[j] = s;
 }
 
+// Dot products of a given start vector g = T0[:, k], for the test in
+// k_start_panel: part[b][0] = g . g and part[b][1 + i] = v_i . g over the
+// 1024 rows of workgroup b (waves over the products, lanes over rows).
+constexpr int kStartRows = 1024;
+template <typename E>
+__global__ __launch_bounds__(1024) void k_start_dots(const E *__restrict__ T0,
+                                                     const E *__restrict__ V, int64_t M, int k,
+                                                     int nd, double *__restrict__ part)
+{
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * kStartRows;
+    const int64_t r1 = M - r0 < kStartRows ? M : r0 + kStartRows;
+    const E *g = T0 + (int64_t)k * M;
+    for (int i = w - 1; i < nd; i += 16) {
+        const E *v = i < 0 ? g : V + (int64_t)i * M;
+        double a0 = 0.0, a1 = 0.0;
+        int64_t m = r0 + lane;
+        for (; m + 64 < r1; m += 128) {
+            a0 += (double)v[m] * (double)g[m];
+            a1 += (double)v[m + 64] * (double)g[m + 64];
+        }
+        if (m < r1)
+            a0 += (double)v[m] * (double)g[m];
+        const double sum = fwave_sum(a0 + a1);
+        if (lane == 0)
+            part[(int64_t)blockIdx.x * (nd + 1) + (i + 1)] = sum;
+    }
+}
+
+
 // Start vector of component k (the pseudo-code's T^(k) <- R^(k)): explicit
 // deflation takes the residual column from the panel copy; implicit forms
 // A_j - sum_i sigma_i v_i P_ji.  Selection: replayed column, column k, the
@@ -229,12 +259,11 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
                                                       const double *__restrict__ cn,
                                                       const typename C::acc *__restrict__ T0,
                                                       StartArgs a, double tiny,
-                                                      typename C::acc *__restrict__ t,
+                                                      const double *__restrict__ part, int nb,
                                                       LoopState *st)
 {
-    using E = typename C::acc;
-    constexpr int PR = C::PR;
     __shared__ double sv[16];
+    __shared__ double buf[1024];
     __shared__ int64_t si[16];
     __shared__ int64_t col_sel;
     __shared__ int use_given, degenerate;
@@ -257,26 +286,28 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
         // earlier normalised scores (|g|^2 - sum_i (v_i . g)^2, V orthonormal).
         // Fall back to the max-norm column if the norm is tiny or not finite,
         // or if less than a tenth of it lies outside span(V_(k)).
-        const E *g = T0 + (int64_t)a.k * M;
+        // (the products come as per-row-block partials from k_start_dots,
+        // added here in block order)
         const int nd = a.gs ? a.k : 0;
         double tot = 0.0, dd = 0.0;
-        for (int i = -1; i < nd; ++i) {
-            const E *v = i < 0 ? g : V + (int64_t)i * M;
-            double s = 0.0;
-            for (int64_t m = tid; m < M; m += 1024)
-                s += (double)v[m] * (double)g[m];
-            s = fwave_sum(s);
-            if (lane == 0)
-                sv[w] = s;
-            __syncthreads();
+        for (int c0 = 0; c0 < nd + 1; c0 += 1024) {
+            const int j = c0 + tid;
             double r = 0.0;
-            for (int j = 0; j < 16; ++j)
-                r += sv[j];
+            if (j < nd + 1)
+                for (int b = 0; b < nb; ++b)
+                    r += part[(int64_t)b * (nd + 1) + j];
+            buf[tid] = r;
             __syncthreads();
-            if (i < 0)
-                tot = r;
-            else
-                dd += r * r;
+            if (tid == 0) {
+                const int cnt = nd + 1 - c0 < 1024 ? nd + 1 - c0 : 1024;
+                for (int q = 0; q < cnt; ++q) {
+                    if (c0 + q == 0)
+                        tot = buf[q];
+                    else
+                        dd += buf[q] * buf[q];
+                }
+            }
+            __syncthreads();
         }
         if (tid == 0) {
             const double nrm = sqrt(tot);
@@ -312,22 +343,6 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
         degenerate = 1;
     __syncthreads();
     const int64_t c = col_sel;
-    const int64_t len = NP * PR;
-    for (int64_t m = tid; m < len; m += 1024) {
-        E v = E(0);
-        if (m < M) {
-            if (c < 0) {
-                v = T0[m + (int64_t)a.k * M];
-            } else {
-                double s = (double)panel_elem<C>(A, ldp, m, c, scale);
-                if (implicit)
-                    for (int i = 0; i < a.k; ++i)
-                        s -= sig[i] * (double)V[m + (int64_t)i * M] * (double)P[c + (int64_t)i * N];
-                v = (E)s;
-            }
-        }
-        t[m] = v;
-    }
     if (tid == 0) {
         st->start_col = (int32_t)c;
         st->iter = 0;
@@ -341,6 +356,41 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
         st->degenerate = degenerate;
         st->done = degenerate;
     }
+}
+
+// t = the chosen start (st->start_col, set by k_start_panel): the given
+// vector (-1) or column c of the residual -- of A itself, or of
+// X - T P^T formed from the finished components in implicit mode --
+// zero-padded to NP*PR rows; one thread per row.
+template <class C>
+__global__ __launch_bounds__(256) void k_start_fill(const unsigned char *__restrict__ A, int64_t N,
+                                                    int64_t NP, int64_t ldp, int64_t M,
+                                                    const float *__restrict__ scale, int implicit,
+                                                    const typename C::acc *__restrict__ V,
+                                                    const typename C::acc *__restrict__ P,
+                                                    const double *__restrict__ sig,
+                                                    const typename C::acc *__restrict__ T0, int k,
+                                                    typename C::acc *__restrict__ t,
+                                                    const LoopState *st)
+{
+    using E = typename C::acc;
+    const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (m >= NP * C::PR)
+        return;
+    const int64_t c = st->start_col;
+    E v = E(0);
+    if (m < M) {
+        if (c < 0) {
+            v = T0[m + (int64_t)k * M];
+        } else {
+            double s = (double)panel_elem<C>(A, ldp, m, c, scale);
+            if (implicit)
+                for (int i = 0; i < k; ++i)
+                    s -= sig[i] * (double)V[m + (int64_t)i * M] * (double)P[c + (int64_t)i * N];
+            v = (E)s;
+        }
+    }
+    t[m] = v;
 }
 
 // q = sum_g q_part[g] (FP64, fixed order), q' = q - W d (the Gram-Schmidt
@@ -754,12 +804,20 @@ void Fused<F>::colnorm_finish(const double *cnpart, int nsplit, int64_t N, doubl
 template <int F>
 void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                      const float *scale, int implicit, const E *V, const E *P, const double *sig,
-                     const double *cn, const E *T0, StartArgs a, double tiny, E *t, LoopState *st,
-                     hipStream_t s)
+                     const double *cn, const E *T0, StartArgs a, double tiny, E *t,
+                     double *part, LoopState *st, hipStream_t s)
 {
     using C = typename CodecOf<F>::type;
+    const int nb = (int)fcdiv(M, kStartRows);
+    if (a.init == 2 && T0) {
+        const int nd = a.gs ? a.k : 0;
+        hipLaunchKernelGGL(k_start_dots<E>, dim3((unsigned)nb), dim3(1024), 0, s, T0, V, M, a.k,
+                           nd, part);
+    }
     hipLaunchKernelGGL(k_start_panel<C>, dim3(1), dim3(1024), 0, s, A, N, NP, ldp, M, scale,
-                       implicit, V, P, sig, cn, T0, a, tiny, t, st);
+                       implicit, V, P, sig, cn, T0, a, tiny, part, nb, st);
+    hipLaunchKernelGGL(k_start_fill<C>, dim3(fcdiv(NP * C::PR, 256)), dim3(256), 0, s, A, N, NP,
+                       ldp, M, scale, implicit, V, P, sig, T0, a.k, t, st);
 }
 
 template <int F>

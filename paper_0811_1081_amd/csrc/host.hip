@@ -537,7 +537,9 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         const int kg = gs ? (int)k : 0;
         StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, gs ? 1 : 0,
                     op->replay_start_col};
-        F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, st, s);
+        // the start's scratch (given-start products) shares cpart, idle here
+        F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, cpart, st,
+                 s);
         // first loading of the component: p = R^T t0, Gram-Schmidt, norm
         F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE,
                 td, tsq, qpart, st, s);

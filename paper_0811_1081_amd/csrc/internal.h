@@ -257,7 +257,7 @@ struct Fused {
     static void start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                       const float *scale, int implicit, const E *V, const E *P, const double *sig,
                       const double *cn, const E *T0, StartArgs a, double tiny, E *t,
-                      LoopState *st, hipStream_t s);
+                      double *part, LoopState *st, hipStream_t s);
     static void pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                      const unsigned char *A,
                      int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
