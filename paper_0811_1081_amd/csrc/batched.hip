@@ -173,6 +173,26 @@ __device__ void batch_pass(const float *__restrict__ X, int64_t ldx, int M, int 
     }
 }
 
+// This lane's share of |col|^2 over n rows, in the same shape as lane_dot.
+__device__ inline double lane_sq(const float *__restrict__ col, int n, int lane)
+{
+    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+    int m = lane;
+    for (; m + 7 * 64 < n; m += 8 * 64) {
+        float x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            x[u] = col[m + 64 * u];
+        s0 += (double)x[0] * (double)x[0] + (double)x[4] * (double)x[4];
+        s1 += (double)x[1] * (double)x[1] + (double)x[5] * (double)x[5];
+        s2 += (double)x[2] * (double)x[2] + (double)x[6] * (double)x[6];
+        s3 += (double)x[3] * (double)x[3] + (double)x[7] * (double)x[7];
+    }
+    for (; m < n; m += 64)
+        s0 += (double)col[m] * (double)col[m];
+    return (s0 + s1) + (s2 + s3);
+}
+
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
 
 __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ items, int nprob,
@@ -222,11 +242,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             bad = 0;
         __syncthreads();
         for (int j = w; j < N; j += nw) {
-            const float *col = X + (int64_t)j * ldx;
-            double s = 0.0;
-            for (int m = lane; m < M; m += 64)
-                s += (double)col[m] * (double)col[m];
-            s = bwave_sum(s);
+            const double s = bwave_sum(lane_sq(X + (int64_t)j * ldx, M, lane));
             if (lane == 0) {
                 cn0[j] = s;
                 if (!isfinite(s))
@@ -511,11 +527,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             __syncthreads();
             if (k + 1 < K) {
                 for (int j = w; j < N; j += nw) {
-                    const float *col = X + (int64_t)j * ldx;
-                    double s = 0.0;
-                    for (int m = lane; m < M; m += 64)
-                        s += (double)col[m] * t[m];
-                    s = bwave_sum(s);
+                    const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
                     if (lane == 0)
                         W[j + (int64_t)k * N] = degenerate ? 0.0 : s;
                 }
