@@ -194,8 +194,19 @@ __global__ __launch_bounds__(256) void k_colnorm_finish(const double *__restrict
         return;
     double s;
     if (cnpart) {
+        // in split order, eight loads issued before their adds
         s = 0.0;
-        for (int i = 0; i < nsplit; ++i)
+        int i = 0;
+        for (; i + 8 <= nsplit; i += 8) {
+            double x[8];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                x[u] = cnpart[(int64_t)(i + u) * N + j];
+#pragma unroll
+            for (int u = 0; u < 8; ++u)
+                s += x[u];
+        }
+        for (; i < nsplit; ++i)
             s += cnpart[(int64_t)i * N + j];
         if (cn0)
             cn0[j] = s;
