@@ -456,8 +456,9 @@ def bench_paper_sweep(args):
                 row[algo]["cpu_oracle_ms"] = dt * 1e3
                 row[algo]["cpu_oracle_iters_total"] = int(o.iters.sum())
                 row[algo]["cpu_over_gpu_with_transfer"] = dt * 1e3 / ms_h2d
-            if M == sizes[0]:
-                # parity on the same trajectory (replayed counts and columns)
+            if M == sizes[0] and M <= args.sweep_cpu_max:
+                # parity on the same trajectory (replayed counts and columns);
+                # the oracle only runs on the sizes it is timed on
                 o = oracle.fit(X, K, tol=0.0, max_iter=int(its.max()), algo=algo,
                                replay_iters=its, replay_start=out["start_col"].cpu().numpy())
                 Pg = out["P"].cpu().numpy()

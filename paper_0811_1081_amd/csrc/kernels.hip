@@ -22,6 +22,27 @@
 
 namespace gspca {
 
+// Sum of the nsplit partials part[s * ldpart + r] in split order, eight
+// loads issued before their adds.
+__device__ inline double sum_parts(const double *__restrict__ part, int nsplit, int64_t ldpart,
+                                   int64_t r)
+{
+    double v = 0.0;
+    int s = 0;
+    for (; s + 8 <= nsplit; s += 8) {
+        double x[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            x[u] = part[(int64_t)(s + u) * ldpart + r];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            v += x[u];
+    }
+    for (; s < nsplit; ++s)
+        v += part[(int64_t)s * ldpart + r];
+    return v;
+}
+
 // 16-byte native vectors (one global_load_dwordx4 per lane).
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef double f64x2 __attribute__((ext_vector_type(2)));
@@ -348,8 +369,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_dot(const double *__restrict__ pa
     const int64_t r = r0 + threadIdx.x;
     double v = 0.0;
     if (r < L) {
-        for (int s = 0; s < nsplit; ++s)
-            v += part[(int64_t)s * ldpart + r];
+        v = sum_parts(part, nsplit, ldpart, r);
         if (y)
             y[r] = v;
     }
@@ -408,8 +428,7 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
         if (k > 0) {
             v = y[r];
         } else {
-            for (int s = 0; s < nsplit; ++s)
-                v += part[(int64_t)s * ldpart + r];
+            v = sum_parts(part, nsplit, ldpart, r);
         }
     }
     double proj = 0.0;
@@ -548,8 +567,7 @@ __global__ __launch_bounds__(kMgsThreads) void k_mgs(const double *__restrict__ 
     double acc = 0.0;
     for (int64_t r = tid; r < L; r += kMgsThreads) {
         double v = 0.0;
-        for (int s = 0; s < nsplit; ++s)
-            v += part[(int64_t)s * ldpart + r];
+        v = sum_parts(part, nsplit, ldpart, r);
         y[r] = v;
         acc += (double)Q[r] * v; // column 0
     }
