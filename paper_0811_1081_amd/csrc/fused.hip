@@ -304,9 +304,20 @@ __global__ __launch_bounds__(1024) void k_start_panel(const unsigned char *__res
         for (int c0 = 0; c0 < nd + 1; c0 += 1024) {
             const int j = c0 + tid;
             double r = 0.0;
-            if (j < nd + 1)
-                for (int b = 0; b < nb; ++b)
+            if (j < nd + 1) {
+                int b = 0;
+                for (; b + 8 <= nb; b += 8) { // in block order, eight loads ahead
+                    double x[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        x[u] = part[(int64_t)(b + u) * (nd + 1) + j];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u)
+                        r += x[u];
+                }
+                for (; b < nb; ++b)
                     r += part[(int64_t)b * (nd + 1) + j];
+            }
             buf[tid] = r;
             __syncthreads();
             if (tid == 0) {
