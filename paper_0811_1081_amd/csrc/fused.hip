@@ -19,33 +19,47 @@ namespace gspca {
 
 // ---------------------------------------------------------------------------
 // Re-tile X (column-major, ldx) into row panels of ldp >= N columns; rows >= M
-// and columns >= N are zero.  Flags NaN/Inf.  Thread: one 16-byte panel
-// segment (PR rows of one column).
-
+// and columns >= N are zero.  Flags NaN/Inf.  Workgroup: a tile of 64 rows x
+// 64 columns, read down the columns (256 contiguous bytes per column for
+// FP32), transposed through LDS, and written as the 16-byte segments of its
+// 64 / PR panels (64 consecutive segments per panel row, contiguous).
+constexpr int kRetileTile = 64;
 template <typename E>
 __global__ __launch_bounds__(256) void k_retile(const E *__restrict__ X, int64_t ldx, int64_t M,
                                                 int64_t N, int64_t NP, int64_t ldp,
                                                 E *__restrict__ A, LoopState *st)
 {
     constexpr int PR = 16 / sizeof(E);
+    constexpr int T = kRetileTile;
+    __shared__ E tile[T][T + 1]; // [column][row]
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t r0 = (int64_t)blockIdx.x * T, j0 = (int64_t)blockIdx.y * T;
     int bad = 0;
-    const int64_t total = NP * ldp;
-    for (int64_t s = (int64_t)blockIdx.x * 256 + threadIdx.x; s < total;
-         s += (int64_t)gridDim.x * 256) {
-        const int64_t b = s / ldp, j = s - b * ldp;
-        E v[PR];
-#pragma unroll
-        for (int r = 0; r < PR; ++r) {
-            const int64_t m = b * PR + r;
-            const E x = (m < M && j < N) ? X[m + j * ldx] : E(0);
-            bad |= !isfinite(x);
-            v[r] = x;
-        }
-#pragma unroll
-        for (int r = 0; r < PR; ++r)
-            A[s * PR + r] = v[r];
+    const int64_t m = r0 + lane;
+#pragma unroll 4
+    for (int c = w; c < T; c += 4) {
+        const int64_t j = j0 + c;
+        const E x = (m < M && j < N) ? X[m + j * ldx] : E(0);
+        bad |= !isfinite(x);
+        tile[c][lane] = x;
     }
-    if (__any(bad) && (threadIdx.x & 63) == 0)
+    __syncthreads();
+    // segment (panel b0 + pb, column j0 + c): thread -> c = lane, pb = w, w + 4, ...
+    const int64_t b0 = r0 / PR;
+    for (int pb = w; pb < T / PR; pb += 4) {
+        const int64_t b = b0 + pb, j = j0 + lane;
+        if (b < NP && j < ldp) {
+            E v[PR];
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                v[r] = tile[lane][pb * PR + r];
+            E *dst = A + (b * ldp + j) * PR;
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                dst[r] = v[r];
+        }
+    }
+    if (__any(bad) && lane == 0)
         atomicOr(&st->nonfinite, 1);
 }
 
@@ -781,9 +795,9 @@ void Fused<F>::retile(const E *X, int64_t ldx, int64_t M, int64_t N, int64_t NP,
                       unsigned char *A, LoopState *st, hipStream_t s)
 {
     if constexpr (F == kFmtF64 || F == kFmtF32) {
-        const int64_t total = NP * ldp;
-        const unsigned g = (unsigned)std::min<int64_t>(fcdiv(total, 256), 8192);
-        hipLaunchKernelGGL(k_retile<E>, dim3(g), dim3(256), 0, s, X, ldx, M, N, NP, ldp,
+        const dim3 grid(fcdiv(NP * (16 / (int64_t)sizeof(E)), kRetileTile),
+                        fcdiv(ldp, kRetileTile));
+        hipLaunchKernelGGL(k_retile<E>, grid, dim3(256), 0, s, X, ldx, M, N, NP, ldp,
                            reinterpret_cast<E *>(A), st);
     }
 }
