@@ -69,7 +69,8 @@ int64_t gspca_mlp_param_count(int32_t d0, int32_t d1, int32_t d2, int32_t d3);
 
 /* Workspace of gspca_mlp_forward / gspca_mlp_loss_grad over `rows` rows in
  * `ninst` matrices (cols = 0), and of gspca_ws_predict for an M x N matrix
- * (rows = M, ninst = 1, cols = N). */
+ * (rows = M, ninst = 1, cols = N).  0 when the sizes or the network widths
+ * are invalid (d0 = 32, d1 and d2 in [16, 1024], d3 in [1, 32]). */
 size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t ninst,
                                  int64_t cols);
 

@@ -87,12 +87,15 @@ int oracle_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int fmt,
     const float qmax = fmt == 1 ? 448.0f : 1.0f;
     for (int64_t n = 0; n < N; ++n) {
         float amax = 0.0f;
+        int bad = 0;
         for (int64_t m = 0; m < M; ++m) {
             const float a = fabsf(X[m + n * ldx]);
-            if (!(a <= amax))
-                amax = a; /* propagates NaN */
+            if (!isfinite(a))
+                bad = 1; /* NaN or Inf anywhere in the column */
+            else if (a > amax)
+                amax = a;
         }
-        if (!isfinite(amax))
+        if (bad)
             return -4;
         const float s = amax > 0.0f ? amax / qmax : 1.0f;
         scale[n] = s;

@@ -1051,6 +1051,10 @@ size_t gspca_mlp_workspace_bytes(const gspca_mlp *net, int64_t rows, int32_t nin
 {
     if (!net || rows < 1 || ninst < 1 || cols < 0)
         return 0;
+    // the widths the kernels accept (valid_net without the parameter pointers)
+    if (net->d0 != GSPCA_WS_RANK || net->d1 < 16 || net->d1 > 1024 || net->d2 < 16 ||
+        net->d2 > 1024 || net->d3 < 1 || net->d3 > net->d0)
+        return 0;
     return layout(net, rows, ninst, cols).total;
 }
 
