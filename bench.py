@@ -223,23 +223,11 @@ def _batched_instance(args):
 
 
 def generate_batched(shapes, workers=8):
-    """Host matrices of the batched workload (a spawn pool with one BLAS
-    thread per worker; call before the process touches the GPU)."""
-    import multiprocessing as mp
-    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
-    saved = {k: os.environ.get(k) for k in keys}
-    for k in keys:
-        os.environ[k] = "1"
-    try:
-        with mp.get_context("spawn").Pool(workers) as pool:
-            return pool.map(_batched_instance, [(i, m, n) for i, (m, n, _) in enumerate(shapes)],
-                            chunksize=16)
-    finally:
-        for k, v in saved.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
+    """Host matrices of the batched workload, generated on threads of this
+    process (no child processes: safe under rocprofv3)."""
+    from paper_0811_1081_amd import synth
+    return synth.map_threads(_batched_instance,
+                             [(i, m, n) for i, (m, n, _) in enumerate(shapes)], workers)
 
 
 def bench_batched(args):

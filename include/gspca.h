@@ -36,6 +36,11 @@
  *     some component stopped at max_iter; its outputs are the last iterate.
  *   - Calls on one stream are serialised; calls on different streams are
  *     independent as long as they use distinct workspaces.
+ *   - Graph capture: an entry point that reads results back to the host
+ *     (gspca_fit_ex, gspca_fit, gspca_fit_f32, gspca_quantize,
+ *     gspca_batched_prepare, gspca_batched_tune, gspca_fit_block) returns
+ *     GSPCA_EINVAL, enqueuing nothing, when `stream` is being captured into a
+ *     hipGraph.  Loop state is cleared by a kernel, never by a memset.
  */
 #ifndef GSPCA_H
 #define GSPCA_H
@@ -178,8 +183,10 @@ size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt
  * gspca_workspace_bytes() bytes, 256-byte aligned, owned by the caller and
  * not touched after the call returns.  All work is enqueued on `stream`; the
  * host reads a small status word once per batch of iterations to test
- * convergence, so the call returns only after the fit has completed on the
- * GPU (the stream is synchronised).  Returns OK, NOT_CONVERGED or an error. */
+ * convergence, so the call is blocking: it returns only after the fit has
+ * completed on the GPU (the stream is synchronised), and it returns
+ * GSPCA_EINVAL without enqueuing anything when `stream` is capturing.
+ * Returns OK, NOT_CONVERGED or an error. */
 gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
                           const gspca_result *res, void *ws, size_t ws_bytes, void *stream);
 

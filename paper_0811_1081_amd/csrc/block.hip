@@ -142,6 +142,9 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
     if (ws_bytes < L.total)
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cap = stream_capturing(s);
+    if (cap != 0) // reads the Ritz values back every iteration
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
     unsigned char *base = static_cast<unsigned char *>(ws);
     float *Y = reinterpret_cast<float *>(base + L.Y);
     float *Z = reinterpret_cast<float *>(base + L.Z);

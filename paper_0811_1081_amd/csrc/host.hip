@@ -239,8 +239,7 @@ gspca_status fit_two_pass(const gspca_problem *pr, const gspca_options *op, cons
         }
     };
 
-    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
-        return GSPCA_EDEVICE;
+    reset_state(st, s);
     L::copy_pad(X, pr->ldx, R, pl.ldr, M, N, st, s);
     if (!read_state())
         return GSPCA_EDEVICE;
@@ -520,8 +519,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         return hipStreamSynchronize(s) == hipSuccess;
     };
 
-    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
-        return GSPCA_EDEVICE;
+    reset_state(st, s);
     if constexpr (!quantised) {
         F::retile(static_cast<const E *>(pr->X), pr->ldx, M, N, f.NP, f.ldp, A, st, s);
         if (!read_state())
@@ -663,7 +661,15 @@ gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
         return v;
     if (!res || !res->T || !res->P || !res->lambda)
         return GSPCA_EINVAL;
+    if (!ws || ws_bytes < workspace_for(prob, opt))
+        return GSPCA_EWORKSPACE;
+    if (((uintptr_t)ws) % kAlign)
+        return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    // the fit reads its loop state back to the host: refuse graph capture
+    const int cap = stream_capturing(s);
+    if (cap != 0)
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
     if (use_fused(prob, opt)) {
         switch (prob->dtype) {
         case GSPCA_F64: return fit_fused<kFmtF64>(prob, opt, res, ws, ws_bytes, s);
@@ -691,6 +697,9 @@ static gspca_status fit_alloc(int32_t dtype, const void *X, int64_t M, int64_t N
         return v;
     if (!T || !P || !lambda)
         return GSPCA_EINVAL;
+    const int cap = stream_capturing(static_cast<hipStream_t>(stream));
+    if (cap != 0) // blocking, and allocates: never under capture
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
     const size_t bytes = gspca_workspace_bytes(&pr, &op);
     void *ws = nullptr;
     if (hipMalloc(&ws, bytes) != hipSuccess)
@@ -733,6 +742,9 @@ gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, i
     if (!ws || ws_bytes < sizeof(LoopState))
         return GSPCA_EWORKSPACE;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cap = stream_capturing(s);
+    if (cap != 0) // reads the non-finite flag back: blocking
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
     LoopState *st = static_cast<LoopState *>(ws);
     int cpt = 0, NT = 0;
     int64_t ldp = 0;
@@ -740,8 +752,7 @@ gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, i
     const int fmt = fmt_of(dtype);
     const int64_t NP = cdiv(M, fmt_rows(fmt));
     unsigned char *q = static_cast<unsigned char *>(Q);
-    if (hipMemsetAsync(st, 0, sizeof(LoopState), s) != hipSuccess)
-        return GSPCA_EDEVICE;
+    reset_state(st, s);
     if (fmt == kFmtBF16)
         Fused<kFmtBF16>::quantize(X, ldx, M, N, NP, ldp, col_scale, q, st, s);
     else

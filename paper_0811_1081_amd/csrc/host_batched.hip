@@ -86,11 +86,23 @@ void launch_plan(const PlanImpl *pl, hipStream_t s)
 }
 
 // ---- tune cache: one JSON object per line,
-//      {"key":"n,sumMN,maxM,maxN","threads":T,"occ":O,"ms":X}
+//      {"key":"n,sumMN,maxM,maxN,cus,version","threads":T,"occ":O,"ms":X}
+// The key carries the compute-unit count and the library version, so an
+// entry measured on another device or another build of the kernel is not
+// reused.
 void cache_key(const PlanImpl *pl, char *buf, size_t n)
 {
-    snprintf(buf, n, "%lld,%lld,%lld,%lld", (long long)pl->sig[0], (long long)pl->sig[1],
-             (long long)pl->sig[2], (long long)pl->sig[3]);
+    snprintf(buf, n, "%lld,%lld,%lld,%lld,%d,%d", (long long)pl->sig[0], (long long)pl->sig[1],
+             (long long)pl->sig[2], (long long)pl->sig[3], pl->ncu, gspca_version());
+}
+
+// The shapes the tuner measures: whole 64-lane waves, at most 1024 threads
+// (k_batched's launch bound), at most 32 waves per compute unit, and no more
+// workgroups per compute unit than the problems' LDS allows.
+bool valid_shape(int threads, int occ, size_t lds)
+{
+    const bool t_ok = threads == 256 || threads == 512 || threads == 1024;
+    return t_ok && occ >= 1 && threads * occ <= 2048 && occ <= max_occupancy(lds);
 }
 
 bool cache_lookup(const PlanImpl *pl, int *threads, int *occ)
@@ -108,7 +120,7 @@ bool cache_lookup(const PlanImpl *pl, int *threads, int *occ)
         char k[128];
         int t = 0, o = 0;
         if (sscanf(line, "{\"key\":\"%127[^\"]\",\"threads\":%d,\"occ\":%d", k, &t, &o) == 3 &&
-            strcmp(k, key) == 0 && t > 0 && o > 0) {
+            strcmp(k, key) == 0 && valid_shape(t, o, pl->lds)) {
             *threads = t;
             *occ = o;
             found = true;
@@ -174,6 +186,9 @@ gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t npr
         return GSPCA_EINVAL;
     unsigned char *base = static_cast<unsigned char *>(ws);
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cap = stream_capturing(s);
+    if (cap != 0) // uploads the table and synchronises: not capturable
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
 
     std::vector<BatchItem> items(nprob);
     size_t woff = L.off_W;
@@ -246,7 +261,7 @@ gspca_status gspca_batched_prepare(const gspca_batch_problem *probs, int32_t npr
     pl.sig[2] = max_m;
     pl.sig[3] = max_n;
     int t = 0, o = 0;
-    if (cache_lookup(&pl, &t, &o) && o <= max_occupancy(lds)) {
+    if (cache_lookup(&pl, &t, &o)) {
         pl.threads = t;
         pl.occ = o;
     }
@@ -276,6 +291,9 @@ gspca_status gspca_batched_tune(gspca_batch_plan *plan, void *stream)
     if (pl.magic != kPlanMagic)
         return GSPCA_EINVAL;
     hipStream_t s = static_cast<hipStream_t>(stream);
+    const int cap = stream_capturing(s);
+    if (cap != 0) // times launches with host-side event waits
+        return cap > 0 ? GSPCA_EINVAL : GSPCA_EDEVICE;
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return GSPCA_EDEVICE;
@@ -285,7 +303,7 @@ gspca_status gspca_batched_tune(gspca_batch_plan *plan, void *stream)
     gspca_status st = GSPCA_OK;
     for (int threads : {256, 512, 1024}) {
         for (int occ = 1; occ <= occ_max; ++occ) {
-            if (threads * occ > 2048) // at most 32 waves per compute unit
+            if (!valid_shape(threads, occ, pl.lds))
                 continue;
             PlanImpl c = pl;
             c.threads = threads;

@@ -189,6 +189,13 @@ inline int64_t score_rows(int64_t M, int kd)
     return r > kScoreRows ? kScoreRows : r;
 }
 
+// Zero the loop state on `s` with a one-thread kernel: no memset node is
+// recorded when the caller captures the stream into a graph.
+void reset_state(LoopState *st, hipStream_t s);
+// 1 when `s` is being captured into a graph, 0 when not, -1 when the query
+// failed.  Entry points that read results back to the host refuse capture.
+int stream_capturing(hipStream_t s);
+
 struct StartArgs {
     int32_t k;
     int32_t init;           // gspca_init

@@ -821,4 +821,19 @@ void Launch<E>::finalize_all(E *T, int64_t M, int K, const double *sigma, double
 template struct Launch<float>;
 template struct Launch<double>;
 
+__global__ void k_state_reset(LoopState *st) { *st = LoopState{}; }
+
+void reset_state(LoopState *st, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_state_reset, dim3(1), dim3(1), 0, s, st);
+}
+
+int stream_capturing(hipStream_t s)
+{
+    hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(s, &cs) != hipSuccess)
+        return -1;
+    return cs == hipStreamCaptureStatusNone ? 0 : 1;
+}
+
 }  // namespace gspca

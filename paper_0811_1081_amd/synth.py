@@ -155,3 +155,22 @@ def sketch_matrix(N: int = 256, r: int = 32) -> np.ndarray:
     """Fixed Gaussian test matrix Omega (N x r, row-major) for the warm-start sketch X*Omega."""
     rng = rng_for(5, 999_999)
     return np.ascontiguousarray(rng.standard_normal((N, r)).astype(np.float32))
+
+
+def map_threads(fn, items, workers: int = 8, log=None, every: int = 256):
+    """[fn(x) for x in items] on a pool of threads of this process (numpy's
+    QR, products and bulk random draws release the interpreter lock), with one
+    BLAS thread per worker.  No child process is started, so the call is safe
+    in a process that uses the GPU or runs under a profiler."""
+    items = list(items)
+    if workers <= 1 or len(items) < 4:
+        return [fn(x) for x in items]
+    from concurrent.futures import ThreadPoolExecutor
+    from threadpoolctl import threadpool_limits
+    out = []
+    with threadpool_limits(limits=1), ThreadPoolExecutor(max_workers=workers) as ex:
+        for r in ex.map(fn, items):
+            out.append(r)
+            if log and len(out) % every == 0:
+                log("generated %d / %d" % (len(out), len(items)))
+    return out

@@ -253,32 +253,11 @@ def _instance(args):
 
 
 def generate(indices, M, N, workers=8, log=None):
-    """Host matrices for the given instance numbers.  The worker pool starts
-    new interpreters, so call this before the process touches the GPU."""
-    import multiprocessing as mp
-    args = [(int(i), M, N) for i in indices]
-    if workers <= 1 or len(args) < 4:
-        return [_instance(a) for a in args]
-    out = []
-    # one BLAS thread per worker (the workers read these at start-up)
-    import os
-    keys = ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS")
-    saved = {k: os.environ.get(k) for k in keys}
-    for k in keys:
-        os.environ[k] = "1"
-    try:
-        with mp.get_context("spawn").Pool(workers) as pool:
-            for r in pool.imap(_instance, args, chunksize=8):
-                out.append(r)
-                if log and len(out) % 256 == 0:
-                    log("generated %d / %d" % (len(out), len(args)))
-    finally:
-        for k, v in saved.items():
-            if v is None:
-                os.environ.pop(k, None)
-            else:
-                os.environ[k] = v
-    return out
+    """Host matrices for the given instance numbers, generated on threads of
+    this process (no child processes, so it may run beside GPU work and under
+    a profiler)."""
+    from . import synth
+    return synth.map_threads(_instance, [(int(i), M, N) for i in indices], workers, log=log)
 
 
 def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512, power=1):
