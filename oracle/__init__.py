@@ -308,11 +308,16 @@ def quantize(X, fmt):
     return codes, scale
 
 
-def dequantize(codes, scale, fmt):
+def dequantize(codes, scale, fmt, out=None):
+    """x~ = decode(code) * s_j in FP64 (column-major); ``out`` may be a
+    preallocated Fortran-ordered float64 (M, N) array to write into."""
     fmt_i = {"bf16": FMT_BF16, "e4m3": FMT_E4M3}[fmt] if isinstance(fmt, str) else int(fmt)
     codes = np.asfortranarray(codes)
     M, N = codes.shape
-    out = np.zeros((M, N), order="F")
+    if out is None:
+        out = np.zeros((M, N), order="F")
+    elif (out.shape != (M, N) or out.dtype != np.float64 or not out.flags["F_CONTIGUOUS"]):
+        raise ValueError("out must be a Fortran-ordered float64 (M, N) array")
     sc = np.ascontiguousarray(scale, dtype=np.float32)
     lib().oracle_dequantize(_ptr(codes), _ptr(sc), M, N, fmt_i, _ptr(out))
     return out

@@ -54,10 +54,19 @@ double oracle_e4m3_decode(uint8_t c)
     return s ? -v : v;
 }
 
-/* Nearest representable magnitude by exhaustive search over the 127 finite
- * non-negative codes, ties to the code with an even fraction field; values
- * above 448 saturate to 448. */
-uint8_t oracle_e4m3_encode(float x)
+/* The 127 finite non-negative E4M3 values, indexed by code: they increase
+ * with the code (exponent field above fraction field). */
+static void e4m3_table(double tab[127])
+{
+    for (int c = 0; c <= 0x7E; ++c)
+        tab[c] = oracle_e4m3_decode((uint8_t)c);
+}
+
+/* Nearest representable magnitude, ties to the code with an even fraction
+ * field; values at or above 448 saturate to 448.  The bracketing pair
+ * tab[lo] <= |x| < tab[lo + 1] is found by bisection of the increasing table,
+ * and the nearer of the two is taken. */
+static uint8_t e4m3_encode_tab(float x, const double tab[127])
 {
     if (isnan(x))
         return 0x7F;
@@ -65,16 +74,30 @@ uint8_t oracle_e4m3_encode(float x)
     const double a = fabs((double)x);
     if (a >= 448.0)
         return (uint8_t)(0x7E | (neg << 7));
-    int best = 0;
-    double bestd = INFINITY;
-    for (int c = 0; c <= 0x7E; ++c) {
-        const double d = fabs(oracle_e4m3_decode((uint8_t)c) - a);
-        if (d < bestd || (d == bestd && (c & 1) == 0 && (best & 1) == 1)) {
-            bestd = d;
-            best = c;
-        }
+    int lo = 0, hi = 0x7E; /* tab[lo] <= a < tab[hi] */
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) / 2;
+        if (tab[mid] <= a)
+            lo = mid;
+        else
+            hi = mid;
     }
+    const double dlo = a - tab[lo], dhi = tab[hi] - a;
+    int best;
+    if (dlo < dhi)
+        best = lo;
+    else if (dhi < dlo)
+        best = hi;
+    else
+        best = (lo & 1) == 0 ? lo : hi;
     return (uint8_t)(best | (neg << 7));
+}
+
+uint8_t oracle_e4m3_encode(float x)
+{
+    double tab[127];
+    e4m3_table(tab);
+    return e4m3_encode_tab(x, tab);
 }
 
 /* fmt 0 = BF16 (codes uint16), 1 = E4M3 (codes uint8).  X binary32 column-major
@@ -85,6 +108,8 @@ int oracle_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int fmt,
     if (!X || !codes || !scale || M < 1 || N < 1 || ldx < M || (fmt != 0 && fmt != 1))
         return -1;
     const float qmax = fmt == 1 ? 448.0f : 1.0f;
+    double tab[127];
+    e4m3_table(tab);
     for (int64_t n = 0; n < N; ++n) {
         float amax = 0.0f;
         int bad = 0;
@@ -104,7 +129,7 @@ int oracle_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, int fmt,
             if (fmt == 0)
                 ((uint16_t *)codes)[m + n * M] = oracle_bf16_encode(q);
             else
-                ((uint8_t *)codes)[m + n * M] = oracle_e4m3_encode(q);
+                ((uint8_t *)codes)[m + n * M] = e4m3_encode_tab(q, tab);
         }
     }
     return 0;
@@ -116,10 +141,13 @@ int oracle_dequantize(const void *codes, const float *scale, int64_t M, int64_t 
 {
     if (!codes || !scale || !Xt || M < 1 || N < 1 || (fmt != 0 && fmt != 1))
         return -1;
+    double dec8[256];
+    for (int c = 0; c < 256; ++c)
+        dec8[c] = oracle_e4m3_decode((uint8_t)c);
     for (int64_t n = 0; n < N; ++n)
         for (int64_t m = 0; m < M; ++m) {
             const double d = fmt == 0 ? (double)oracle_bf16_decode(((const uint16_t *)codes)[m + n * M])
-                                      : oracle_e4m3_decode(((const uint8_t *)codes)[m + n * M]);
+                                      : dec8[((const uint8_t *)codes)[m + n * M]];
             Xt[m + n * M] = d * (double)scale[n];
         }
     return 0;

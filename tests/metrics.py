@@ -29,3 +29,16 @@ def orth_err(Q) -> float:
     """max |Q^T Q - I| in float64."""
     Q = np.asarray(Q, dtype=np.float64)
     return float(np.abs(Q.T @ Q - np.eye(Q.shape[1])).max())
+
+
+def gapped(sig, rel=0.02) -> np.ndarray:
+    """Mask of components whose relative gap to both neighbours is >= rel
+    (1 - s_(k+1)/s_k >= rel and 1 - s_k/s_(k-1) >= rel)."""
+    s = np.asarray(sig, dtype=np.float64)
+    ok = np.ones(len(s), dtype=bool)
+    for k in range(len(s)):
+        if k > 0 and s[k] > (1 - rel) * s[k - 1]:
+            ok[k] = False
+        if k + 1 < len(s) and s[k + 1] > (1 - rel) * s[k]:
+            ok[k] = False
+    return ok

@@ -84,3 +84,23 @@ def test_quantize_scales_and_roundtrip(orc, fmt):
     else:
         ref = torch.from_numpy(np.ascontiguousarray(q)).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
     assert np.array_equal(np.ascontiguousarray(codes), ref)
+
+
+def test_e4m3_encode_dense_sweep(orc):
+    """Every binary32 value in [-480, 480] whose low 13 bits are zero (about
+    half a million values, several per E4M3 interval, including every code
+    and every midpoint) encodes as the library conversion does (saturating
+    above 448, where the library's conversion is not defined)."""
+    bits = np.arange(0, 0x43F00000 >> 13, dtype=np.uint32) << 13   # 0 .. 480.0
+    x = bits.view(np.float32)
+    x = np.concatenate([x, -x])
+    inr = np.abs(x) <= 448.0
+    ref = torch.from_numpy(x[inr]).to(torch.float8_e4m3fn).view(torch.uint8).numpy()
+    ours = np.array([orc.e4m3_encode(float(v)) for v in x], dtype=np.uint8)
+    assert np.array_equal(ours[inr], ref)
+    sat = np.where(x[~inr] > 0, 0x7E, 0xFE).astype(np.uint8)
+    assert np.array_equal(ours[~inr], sat)
+    # the matrix quantiser (one column whose largest magnitude is 448: scale 1)
+    codes, scale = orc.quantize(np.asfortranarray(x[inr][:, None]), "e4m3")
+    assert scale[0] == 1.0
+    assert np.array_equal(np.asarray(codes).ravel(), ref)
