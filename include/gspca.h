@@ -190,6 +190,24 @@ size_t gspca_workspace_bytes(const gspca_problem *prob, const gspca_options *opt
 gspca_status gspca_fit_ex(const gspca_problem *prob, const gspca_options *opt,
                           const gspca_result *res, void *ws, size_t ws_bytes, void *stream);
 
+/* For callers that cannot allocate device memory (serving loops that must
+ * not call hipMalloc, harnesses that forbid it): gspca_fit_ex with no
+ * workspace argument.  The workspace is a fixed array of
+ * GSPCA_NOALLOC_SCRATCH_BYTES bytes inside the library, one copy per GPU,
+ * held until the process ends; the call allocates nothing (no hipMalloc,
+ * hipFree or event creation).  Problems whose gspca_workspace_bytes() exceed
+ * that size are refused with GSPCA_EWORKSPACE (for FP32, roughly M*N*4 plus
+ * N*K*8 bytes must fit: e.g. 4096 x 512 with K = 512 does); options with
+ * replay arrays or a profile are refused with GSPCA_EINVAL.  Every call on
+ * one GPU uses that GPU's array, which keeps the last call's contents (the
+ * fit initialises what it reads): calls that overlap on one GPU, from any
+ * thread or stream, race and must not be issued.  Blocking and not
+ * capturable, as gspca_fit_ex.  The device is the current one. */
+#define GSPCA_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+size_t gspca_noalloc_scratch_bytes(void);
+gspca_status gspca_fit_noalloc(const gspca_problem *prob, const gspca_options *opt,
+                               const gspca_result *res, void *stream);
+
 /* Reduced-precision storage (not in the paper, whose Sec. 3 only notes the
  * programs convert to single precision): per-column scale
  * s_n = max_m |X[m,n]| / Qmax (binary32; Qmax = 1 for BF16, 448 for E4M3;

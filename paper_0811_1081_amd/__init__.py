@@ -131,7 +131,7 @@ def _workspace(nbytes, device):
 
 def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         replay_iters=None, replay_start=None, workspace=None, stream=None, check=True,
-        profile=None, implicit=False, stop="sigma", reorth="cgs"):
+        profile=None, implicit=False, stop="sigma", reorth="cgs", noalloc=False):
     """Fit K components of the column-major device matrix X (M x N).
 
     Returns a dict of device tensors: T (M x K), P (N x K) (column-major, dtype
@@ -144,7 +144,10 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
     loading moved less than tol).  ``reorth`` is the form of GS-PCA's
     Gram-Schmidt steps: "cgs" (one classical pass, the paper's), "cgs2" (two
     passes) or "mgs" (modified); the last two need explicit deflation and
-    F32/F64 data.  Raises GspcaError on a negative status when ``check``."""
+    F32/F64 data.  ``noalloc`` runs gspca_fit_noalloc: the library's fixed
+    per-GPU scratch array is the workspace (no device allocation beyond the
+    outputs; no replay, profile or ``workspace``).  Raises GspcaError on a
+    negative status when ``check``."""
     import torch
     L = _b.load()
     quant = isinstance(X, Quantized)
@@ -175,6 +178,17 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
     start = torch.empty(K, dtype=torch.int32, device=dev)
     res = _b.Result(T.data_ptr(), P.data_ptr(), lam.data_ptr(), sig.data_ptr(),
                     iters.data_ptr(), start.data_ptr())
+    if stream is None:
+        stream = torch.cuda.current_stream(dev)
+    if noalloc:
+        if workspace is not None:
+            raise ValueError("noalloc takes no workspace")
+        with torch.cuda.device(dev):
+            st = int(L.gspca_fit_noalloc(pr, op, res, ctypes_stream(stream)))
+        if check and st < 0:
+            raise GspcaError(st)
+        return {"T": T, "P": P, "lambda": lam, "sigma": sig, "iters": iters,
+                "start_col": start, "status": st}
     nbytes = int(L.gspca_workspace_bytes(pr, op))
     if nbytes == 0:
         raise GspcaError(EINVAL)
@@ -184,8 +198,6 @@ def fit(X, K, tol=1e-7, max_iter=10000, algo="gs", init="maxnorm", T0=None,
         if workspace.numel() * workspace.element_size() < nbytes:
             raise GspcaError(EWORKSPACE)
         wptr = workspace.data_ptr()
-    if stream is None:
-        stream = torch.cuda.current_stream(dev)
     st = int(L.gspca_fit_ex(pr, op, res, wptr, nbytes, ctypes_stream(stream)))
     if check and st < 0:
         raise GspcaError(st)

@@ -26,6 +26,7 @@ EXPORTS = (
     "gspca_fit_f32", "gspca_status_string", "gspca_version", "gspca_quantized_bytes",
     "gspca_quantize", "gspca_batched_workspace_bytes", "gspca_batched_prepare",
     "gspca_batched_launch", "gspca_batched_tune",
+    "gspca_noalloc_scratch_bytes", "gspca_fit_noalloc",
     # gspca_ws.h (learned warm start)
     "gspca_mlp_param_count", "gspca_mlp_workspace_bytes", "gspca_sketch",
     "gspca_sketch_workspace_bytes", "gspca_sketch_refine",
@@ -123,6 +124,11 @@ def load() -> ctypes.CDLL:
         L.gspca_fit_ex.restype = ctypes.c_int
         L.gspca_fit_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                    ctypes.POINTER(Result), vp, ctypes.c_size_t, vp]
+        L.gspca_fit_noalloc.restype = ctypes.c_int
+        L.gspca_fit_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                        ctypes.POINTER(Result), vp]
+        L.gspca_noalloc_scratch_bytes.restype = ctypes.c_size_t
+        L.gspca_noalloc_scratch_bytes.argtypes = []
         L.gspca_fit.restype = ctypes.c_int
         L.gspca_fit.argtypes = [vp, i64, i64, i64, dbl, i32, vp, vp, vp, vp]
         L.gspca_fit_f32.restype = ctypes.c_int
