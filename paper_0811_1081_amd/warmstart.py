@@ -260,35 +260,48 @@ def generate(indices, M, N, workers=8, log=None):
     return synth.map_threads(_instance, [(int(i), M, N) for i in indices], workers, log=log)
 
 
-def prepare(instances, K, Omega, tol=1e-7, max_iter=3000, chunk=512, power=1):
-    """Device data for training: X (column-major), whitened sketch Z, and the
-    unit scores V of GS-PCA fits (column-major per matrix, K columns)."""
+def prepare(indices, M, N, K, Omega, tol=1e-7, max_iter=3000, chunk=512, power=1,
+            keep_x=False, workers=8, log=None):
+    """Device data for the instance numbers `indices`, made chunk by chunk
+    (host matrices are generated, uploaded and dropped per chunk): the
+    whitened sketch Z of each matrix, the unit scores V of its GS-PCA fit at
+    a tight tolerance (column-major per matrix, K columns, the training
+    targets), the generator's right factors (host, 64 columns) and, with
+    keep_x, the matrices themselves on the device."""
     import torch
     from . import Batch, column_major
-    Xs, Zs, Vs = [], [], []
-    for lo in range(0, len(instances), chunk):
+    indices = list(indices)
+    Xs, Zs, Vs, Vtrue = [], [], [], []
+    for lo in range(0, len(indices), chunk):
+        host = generate(indices[lo:lo + chunk], M, N, workers)
         part = [column_major(torch.from_numpy(np.ascontiguousarray(x)).cuda())
-                for x, _, _ in instances[lo:lo + chunk]]
+                for x, _, _ in host]
         b = Batch(part, K, tol=tol, max_iter=max_iter)
         b.launch()
         for i, X in enumerate(part):
             Zs.append(features(X, Omega, power))
             Vs.append((b.T[i] / b.sigma[i].clamp_min(1e-30).float()).t().contiguous())
-        Xs += part
-    torch.cuda.synchronize()
-    return Xs, Zs, Vs
+        Vtrue += [v for _, v, _ in host]
+        if keep_x:
+            Xs += part
+        torch.cuda.synchronize()
+        del b, part, host
+        if log:
+            log("prepared %d / %d" % (min(lo + chunk, len(indices)), len(indices)))
+    return Xs, Zs, Vs, Vtrue
 
 
 def evaluate(net, Xs, Zs, Vtrue, K, Omega, tol=1e-6, max_iter=3000, stop="sigma"):
-    """Iterations of batched fits from three starts -- max-norm column, the
-    un-learned sketch (first K whitened directions) and the network -- and the
-    final loading error (radians, sign-aligned) against the known factors."""
+    """Iterations of batched fits from three starts -- the max-norm column,
+    the network's skip path alone (the first K whitened sketch directions,
+    i.e. the untrained network) and the network -- and the final loading
+    error (radians, sign-aligned) against the generator's factors."""
     import torch
     from . import Batch
     M = Xs[0].shape[0]
     starts = {"maxnorm": None,
-              "sketch": [(z[:, :K] / np.sqrt(M)).t().contiguous().t() for z in Zs],
-              "learned": [net.forward(z)[:, :K] for z in Zs]}
+              "skip_only": [(z[:, :K] / np.sqrt(M)).t().contiguous().t() for z in Zs],
+              "trained": [net.forward(z)[:, :K] for z in Zs]}
     out = {}
     for name, T0 in starts.items():
         if T0 is not None:
@@ -325,6 +338,8 @@ def evaluate(net, Xs, Zs, Vtrue, K, Omega, tol=1e-6, max_iter=3000, stop="sigma"
 
 
 def main(argv=None):
+    """Train on instances 0 .. train-1 (the last `val` of them held out for
+    choosing the epoch), evaluate on instances 16000 .. 16000+eval-1."""
     import argparse
     import json
     import time
@@ -333,45 +348,50 @@ def main(argv=None):
     from . import synth
     ap = argparse.ArgumentParser(description="train and evaluate the learned warm start")
     ap.add_argument("--train", type=int, default=2000)
+    ap.add_argument("--val", type=int, default=256,
+                    help="training instances held out to choose the epoch (epoch 0 = the "
+                         "untrained network, whose output is its skip path)")
     ap.add_argument("--eval", type=int, default=500)
     ap.add_argument("--M", type=int, default=2048)
     ap.add_argument("--N", type=int, default=256)
     ap.add_argument("--K", type=int, default=16)
     ap.add_argument("--epochs", type=int, default=8)
     ap.add_argument("--batch", type=int, default=64, help="matrices per step")
-    ap.add_argument("--lr", type=float, default=1e-3)
+    ap.add_argument("--lr", type=float, default=3e-4)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--workers", type=int, default=8)
     ap.add_argument("--power", type=int, default=1, help="sketch refinement steps")
-    ap.add_argument("--save", default=None, help="write weights and Adam state (.npz)")
+    ap.add_argument("--save", default=None, help="write the chosen weights (.npz)")
     ap.add_argument("--out", default=None, help="write the summary JSON here too")
     a = ap.parse_args(argv)
     t0 = time.time()
     M, N, K = a.M, a.N, a.K
-    ntr, nev = a.train, a.eval
+    ntr, nval, nev = a.train - a.val, a.val, a.eval
 
     def log(msg):
         print("%s (%.1fs)" % (msg, time.time() - t0), flush=True)
 
-    # host data first: the generator pool must start before the GPU is in use.
-    # Instance numbers: training from 0, evaluation from 16000.
-    train_h = generate(range(ntr), M, N, a.workers, log)
-    eval_h = generate(range(16000, 16000 + nev), M, N, a.workers, log)
-    log("generated %d + %d matrices" % (ntr, nev))
     Om = torch.from_numpy(synth.sketch_matrix(N, RANK)).cuda()
-    Xtr, Ztr, Vtr = prepare(train_h, K, Om, power=a.power)
-    Xev, Zev, Vev = prepare(eval_h, K, Om, power=a.power)
-    del Xtr
-    print("targets and sketches ready at %.1fs" % (time.time() - t0), flush=True)
+    _, Ztr, Vtr, _ = prepare(range(ntr), M, N, K, Om, power=a.power, workers=a.workers, log=log)
+    _, Zva, Vva, _ = prepare(range(ntr, ntr + nval), M, N, K, Om, power=a.power,
+                             workers=a.workers)
+    Xev, Zev, _, Vtrue_ev = prepare(range(16000, 16000 + nev), M, N, K, Om, power=a.power,
+                                    keep_x=True, workers=a.workers, log=log)
+    log("targets and sketches ready")
     net = WarmStartNet(K=K, seed=0)
     Zall = torch.cat(Ztr)
     Vall = torch.stack(Vtr)
+    del Ztr, Vtr
+    Zva_all, Vva_all = torch.cat(Zva), torch.stack(Vva).reshape(-1)
     rng = np.random.default_rng([811, 14])
-    losses = []
-    ev_loss = []
-    Zev_all = torch.cat(Zev)
-    Vev_all = torch.stack(Vev)
-    for ep in range(a.epochs):
+
+    def val_loss():
+        return float(net.loss_grad(Zva_all, Vva_all, nval, M).item())
+
+    losses, val = [], [val_loss()]
+    best, best_ep, best_theta = val[0], 0, net.theta.clone()
+    log("epoch 0 (untrained: skip path) validation loss %.5f" % val[0])
+    for ep in range(1, a.epochs + 1):
         perm = rng.permutation(ntr)
         el = []
         for lo in range(0, ntr - a.batch + 1, a.batch):
@@ -380,13 +400,15 @@ def main(argv=None):
             vv = Vall[idx].reshape(-1)
             el.append(net.train_step(zz, vv, a.batch, M, lr=a.lr))
         losses.append(float(torch.stack(el).mean().item()))
-        l = net.loss_grad(Zev_all, Vev_all.reshape(-1), nev, M)
-        ev_loss.append(float(l.item()))
-        print("epoch %d train loss %.4f eval loss %.4f (%.1fs)" % (ep, losses[-1], ev_loss[-1],
-                                                                 time.time() - t0), flush=True)
-    res = {"M": M, "N": N, "K": K, "train": ntr, "eval": nev, "epochs": a.epochs, "power": a.power,
-           "train_loss": losses, "eval_loss": ev_loss, "tol": a.tol}
-    Vtrue_ev = [v for _, v, _ in eval_h]
+        val.append(val_loss())
+        if val[-1] < best:
+            best, best_ep, best_theta = val[-1], ep, net.theta.clone()
+        log("epoch %d train loss %.5f validation loss %.5f" % (ep, losses[-1], val[-1]))
+    net.theta.copy_(best_theta)
+    net.sync()
+    res = {"M": M, "N": N, "K": K, "train": ntr, "val": nval, "eval": nev, "epochs": a.epochs,
+           "lr": a.lr, "power": a.power, "train_loss": losses, "val_loss": val,
+           "chosen_epoch": best_ep, "tol": a.tol}
     res["sigma_stop"] = evaluate(net, Xev, Zev, Vtrue_ev, K, Om, tol=a.tol)
     res["loading_stop"] = evaluate(net, Xev, Zev, Vtrue_ev, K, Om, tol=1e-4, stop="loading")
     res["seconds"] = time.time() - t0
@@ -396,7 +418,19 @@ def main(argv=None):
         with open(a.out, "w") as f:
             f.write(line + "\n")
     if a.save:
-        np.savez(a.save, **net.state())
+        np.savez(a.save, dims=np.array(net.dims), theta=net.theta.cpu().numpy(),
+                 chosen_epoch=np.array(best_ep), power=np.array(a.power))
+
+
+def load_trained(path, device="cuda"):
+    """A WarmStartNet with the weights written by ``main(--save)``."""
+    st = np.load(path, allow_pickle=False)
+    dims = tuple(int(x) for x in st["dims"])
+    net = WarmStartNet(K=dims[3], hidden=(dims[1], dims[2]), seed=0, device=device)
+    import torch
+    net.theta.copy_(torch.from_numpy(np.asarray(st["theta"], dtype=np.float32)))
+    net.sync()
+    return net
 
 
 if __name__ == "__main__":
