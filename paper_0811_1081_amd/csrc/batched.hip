@@ -20,7 +20,7 @@
 //   q <- q - W d            W = X^T V_(k), so q = X^T (t - V d)
 //   c = P_(k)^T q, p = q - P c, p / |p|
 // t, q, p, the column norms and the coefficient vectors live in LDS.  A
-// problem with more than 32 columns per wave reads X twice instead (t = X p
+// problem with more than 64 columns per wave reads X twice instead (t = X p
 // with threads over rows, then q = X^T t with waves over columns).
 #include <float.h>
 #include <math.h>
@@ -30,19 +30,10 @@
 
 namespace gspca {
 
-template <typename T>
-__device__ inline T bwave_sum(T v)
-{
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
-    return v;
-}
-
 // Workgroup sum; every thread gets the result.  `red` holds one slot per wave.
 __device__ inline double bblock_sum(double v, double *red)
 {
-    v = bwave_sum(v);
+    v = fwave_sum(v);
     const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
     __syncthreads();
     if ((threadIdx.x & 63) == 0)
@@ -81,14 +72,15 @@ __device__ inline double lane_dot(const float *__restrict__ col, const double *_
 constexpr int kPassLdsFloats = 2 * 1024;
 
 // Column split of the single pass: CW waves share the columns of a row tile,
-// CPW (a power of two, 4..32) columns per wave; 0 when N needs more than 32
-// columns per wave or X's element offsets do not fit 32 bits.
+// CPW (a power of two, 4..64) columns per wave, at most 32 while the
+// workgroup has waves to spare; 0 when N needs more than 64 columns per wave
+// or X's byte offsets do not fit 31 bits.
 __device__ inline void pass_split(int N, int64_t ldx, int nw, int &CW, int &CPW)
 {
     int cw = 1;
-    while (cw * 32 < N)
+    while (cw * 32 < N && cw < nw)
         cw <<= 1;
-    if (cw > nw || ldx * (int64_t)N >= ((int64_t)1 << 31)) {
+    if (cw * 64 < N || ldx * (int64_t)N >= ((int64_t)1 << 29)) {
         CW = 0;
         CPW = 0;
         return;
@@ -109,9 +101,16 @@ __device__ inline void pass_split(int N, int64_t ldx, int nw, int &CW, int &CPW)
 // and the same registers then give the row's terms of q = X^T t, summed over
 // the wave's 64 rows with a reduce-scatter; each lane keeps the FP64 running
 // sum of one column.  Rows past M are read clamped and weigh 0; columns past
-// N are read clamped with p = 0 and dropped.  t and q are written to LDS.
-template <int CPW>
-__device__ void batch_pass(const float *__restrict__ X, int64_t ldx, int M, int N, int CW,
+// N are read clamped and meet p = 0 (pf is zero-padded) and are dropped.
+// t and q are written to LDS.  With AHEAD the next tile's loads are issued
+// before the workgroup barrier of the current one (a second set of CPW
+// registers), so they are in flight while the waves wait and form their q
+// terms; only the kernel built for at most 8 waves per compute unit (256
+// registers) does this: under the 128-register bound of 16 waves the
+// compiler spills inside the tile loop and the reload waits for the
+// prefetch (121.6 vs 114.0 ms per replay of the 2048-problem batch).
+template <int CPW, bool AHEAD>
+__device__ void batch_pass(const float *X, int64_t ldx, int M, int N, int CW,
                            const float *pf, float *xr, double *t, double *q)
 {
     const int tid = threadIdx.x, lane = tid & 63, NT = blockDim.x;
@@ -120,32 +119,61 @@ __device__ void batch_pass(const float *__restrict__ X, int64_t ldx, int M, int 
     const int cw = w % CW, rs = w / CW, RS = nw / CW;
     // a wave's columns may lie wholly past N (then it contributes zeros)
     const int cbase = cw * CPW;
-    const int ld = (int)ldx, navail = N - cbase;
-    // the wave's p values are re-read from LDS (one broadcast read each) in
-    // every tile rather than held in registers
+    const int ld = (int)ldx;
+    // buffer loads: the column's byte offset is a scalar operand, the row's
+    // a per-lane one (X spans less than 2 GiB: pass_split)
+    const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)X, (short)0, (int)(((int64_t)(N - 1) * ldx + M) * 4), 0x00020000);
+    // the wave's p values
+    float pv[CPW];
+#pragma unroll
+    for (int c = 0; c < CPW; ++c)
+        pv[c] = pf[cbase + c];
     const int tile = 64 * RS;
+    auto load = [&](float (&x)[CPW], int m0) {
+        const int row = m0 + rs * 64 + lane;
+        const int rowb = (row < M ? row : M - 1) * 4;
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            const int col = cbase + c < N ? cbase + c : N - 1;
+            x[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, rowb, col * ld * 4, 0));
+        }
+    };
     double qacc = 0.0;
     int slot = 0;
     int buf = 0;
-    for (int m0 = 0; m0 < M; m0 += tile) {
+    // one tile: t partials of x, the cross-wave sum, then x's q terms
+    auto body = [&](float (&x)[CPW], float (&xn)[CPW], int m0) {
         const int row = m0 + rs * 64 + lane;
-        const int rowc = row < M ? row : M - 1;
-        float x[CPW];
-#pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            x[c] = X[(c < navail ? cbase + c : N - 1) * ld + rowc];
         float ta = 0.f, tb = 0.f;
 #pragma unroll
         for (int c = 0; c < CPW; c += 2) {
-            ta += x[c] * (c < navail ? pf[cbase + c] : 0.f);
-            tb += x[c + 1] * (c + 1 < navail ? pf[cbase + c + 1] : 0.f);
+            ta += x[c] * pv[c];
+            tb += x[c + 1] * pv[c + 1];
         }
         float *red = xr + buf * 1024;
         red[cw * tile + rs * 64 + lane] = ta + tb;
+        if constexpr (AHEAD) {
+            if (m0 + tile < M)
+                load(xn, m0 + tile);
+        }
         __syncthreads();
+        // the CW shares in order, four reads in flight at a time
+        const float *rp = red + rs * 64 + lane;
         double tv = 0.0;
-        for (int g = 0; g < CW; ++g)
-            tv += (double)red[g * tile + rs * 64 + lane];
+        if (CW >= 4) {
+            for (int g = 0; g < CW; g += 4) {
+                const float r0 = rp[g * tile], r1 = rp[(g + 1) * tile];
+                const float r2 = rp[(g + 2) * tile], r3 = rp[(g + 3) * tile];
+                tv += (double)r0;
+                tv += (double)r1;
+                tv += (double)r2;
+                tv += (double)r3;
+            }
+        } else {
+            for (int g = 0; g < CW; ++g)
+                tv += (double)rp[g * tile];
+        }
         if (row >= M)
             tv = 0.0;
         else if (cw == 0)
@@ -156,6 +184,21 @@ __device__ void batch_pass(const float *__restrict__ X, int64_t ldx, int M, int 
             x[c] *= tf;
         qacc += (double)wave_scatter_sum<float, CPW>(x, lane, slot);
         buf ^= 1;
+    };
+    float xa[CPW];
+    if constexpr (AHEAD) {
+        float xb[CPW];
+        load(xa, 0);
+        for (int m0 = 0; m0 < M; m0 += 2 * tile) {
+            body(xa, xb, m0);
+            if (m0 + tile < M)
+                body(xb, xa, m0 + tile);
+        }
+    } else {
+        for (int m0 = 0; m0 < M; m0 += tile) {
+            load(xa, m0);
+            body(xa, xa, m0);
+        }
     }
     // q: the row groups' sums of each column, in order (the buffers are free
     // once every wave has passed this barrier)
@@ -195,10 +238,14 @@ __device__ inline double lane_sq(const float *__restrict__ col, int n, int lane)
 
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
 
-__global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ items, int nprob,
+// MAXT: the most threads per compute unit the build serves (1024: 128
+// registers per lane; 512: 256 registers, and the single pass prefetches).
+template <int MAXT>
+__global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ items, int nprob,
                                                   const int32_t *__restrict__ order,
                                                   uint32_t *__restrict__ queue, BatchArgs a)
 {
+    constexpr bool kAhead = MAXT <= 512;
     extern __shared__ double lds[];
     __shared__ double red[16];
     __shared__ int cur, bad;
@@ -225,24 +272,25 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
         const float *X = it.X;
         float *T = it.T, *P = it.P;
         double *W = it.W; // N x K: X^T v_i of finished components
-        // LDS: pass buffers | t[M] | q[N] | p[N] | pprev[N] | cn0[N] | sig[K] | dc[K]
-        //      | pf[N] (float)
+        // LDS: pass buffers | pf[npf] (float, zero past N) | t[M] | q[N] | p[N]
+        //      | pprev[N] | cn0[N] | sig[K] | dc[K]
         float *xr = reinterpret_cast<float *>(lds);
-        double *t = lds + kPassLdsFloats / 2;
+        float *pf = xr + kPassLdsFloats;
+        const int npf = batched_pf_floats(N);
+        double *t = reinterpret_cast<double *>(pf + npf);
         double *q = t + M;
         double *p = q + N;
         double *pprev = p + N;
         double *cn0 = pprev + N;
         double *sig = cn0 + N;
         double *dc = sig + K;
-        float *pf = reinterpret_cast<float *>(dc + K);
 
         // |X_j|^2: waves over columns, lanes over rows; NaN/Inf ends the problem
         if (tid == 0)
             bad = 0;
         __syncthreads();
         for (int j = w; j < N; j += nw) {
-            const double s = bwave_sum(lane_sq(X + (int64_t)j * ldx, M, lane));
+            const double s = fwave_sum(lane_sq(X + (int64_t)j * ldx, M, lane));
             if (lane == 0) {
                 cn0[j] = s;
                 if (!isfinite(s))
@@ -351,7 +399,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 __syncthreads();
                 if (!from_pass) {
                     for (int j = w; j < N; j += nw) {
-                        const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
+                        const double s = fwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
                         if (lane == 0)
                             q[j] = s;
                     }
@@ -365,7 +413,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 }
                 __syncthreads();
                 for (int i = w; i < k; i += nw) {
-                    const double s = bwave_sum(lane_dot(P + (int64_t)i * N, q, N, lane));
+                    const double s = fwave_sum(lane_dot(P + (int64_t)i * N, q, N, lane));
                     if (lane == 0)
                         dc[i] = s;
                 }
@@ -410,14 +458,15 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 ++iters;
                 // t = X p / |p|: threads over rows, FP32 products, four partial sums
                 __syncthreads();
-                for (int j = tid; j < N; j += NT)
-                    pf[j] = (float)(p[j] / pn);
+                for (int j = tid; j < npf; j += NT)
+                    pf[j] = j < N ? (float)(p[j] / pn) : 0.f;
                 __syncthreads();
                 switch (CPW) {
-                case 4: batch_pass<4>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 8: batch_pass<8>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 16: batch_pass<16>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 32: batch_pass<32>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 4: batch_pass<4, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 8: batch_pass<8, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 16: batch_pass<16, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 32: batch_pass<32, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 64: batch_pass<64, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
                 default: break;
                 }
                 for (int m = CPW ? M : tid; m < M; m += NT) {
@@ -445,7 +494,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
                 __syncthreads();
                 // d = V^T t, t <- t - V d, sigma
                 for (int i = w; i < k; i += nw) {
-                    const double s = bwave_sum(lane_dot(T + (int64_t)i * M, t, M, lane));
+                    const double s = fwave_sum(lane_dot(T + (int64_t)i * M, t, M, lane));
                     if (lane == 0)
                         dc[i] = s;
                 }
@@ -527,7 +576,7 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
             __syncthreads();
             if (k + 1 < K) {
                 for (int j = w; j < N; j += nw) {
-                    const double s = bwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
+                    const double s = fwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
                     if (lane == 0)
                         W[j + (int64_t)k * N] = degenerate ? 0.0 : s;
                 }
@@ -547,11 +596,16 @@ __global__ __launch_bounds__(1024) void k_batched(const BatchItem *__restrict__ 
 }
 
 void batched_launch(const BatchItem *items, int nprob, const int32_t *order, uint32_t *queue,
-                    BatchArgs a, int grid, int threads, size_t lds_bytes, hipStream_t s)
+                    BatchArgs a, int grid, int threads, int per_cu, size_t lds_bytes,
+                    hipStream_t s)
 {
     hipLaunchKernelGGL(k_batch_reset, dim3(1), dim3(1), 0, s, queue);
-    hipLaunchKernelGGL(k_batched, dim3(grid), dim3(threads), lds_bytes, s, items, nprob, order,
-                       queue, a);
+    if (threads * per_cu <= 512)
+        hipLaunchKernelGGL(k_batched<512>, dim3(grid), dim3(threads), lds_bytes, s, items, nprob,
+                           order, queue, a);
+    else
+        hipLaunchKernelGGL(k_batched<1024>, dim3(grid), dim3(threads), lds_bytes, s, items,
+                           nprob, order, queue, a);
 }
 
 }  // namespace gspca

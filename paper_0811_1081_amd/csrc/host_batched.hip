@@ -82,7 +82,7 @@ int max_occupancy(size_t lds)
 void launch_plan(const PlanImpl *pl, hipStream_t s)
 {
     batched_launch(pl->items, pl->nprob, pl->order, pl->queue, pl->args, pl->ncu * pl->occ,
-                   pl->threads, pl->lds, s);
+                   pl->threads, pl->occ, pl->lds, s);
 }
 
 // ---- tune cache: one JSON object per line,

@@ -325,11 +325,17 @@ struct BatchArgs {
     int32_t max_iter, init, stop, pad;
 };
 void batched_launch(const BatchItem *items, int nprob, const int32_t *order, uint32_t *queue,
-                    BatchArgs a, int grid, int threads, size_t lds_bytes, hipStream_t s);
+                    BatchArgs a, int grid, int threads, int per_cu, size_t lds_bytes,
+                    hipStream_t s);
+// Length of k_batched's FP32 copy of p: N values, then zeros past the last
+// column any wave of the single pass reads (the column split covers at most
+// 2 N + N / 8 + 30 columns), in whole 16-byte groups.
+__host__ __device__ inline int batched_pf_floats(int N) { return 4 * ((3 * N + 67) / 4); }
+
 inline size_t batched_lds_bytes(int64_t M, int64_t N, int64_t K)
 {
-    // 8 KiB of cross-wave sums for the single pass, then the vectors
-    return (size_t)8192 + (size_t)(M + 4 * N + 2 * K) * 8 + (size_t)N * 4;
+    // 8 KiB of cross-wave sums for the single pass, p in FP32, then the vectors
+    return (size_t)8192 + (size_t)batched_pf_floats((int)N) * 4 + (size_t)(M + 4 * N + 2 * K) * 8;
 }
 
 }  // namespace gspca

@@ -86,22 +86,130 @@ struct CodecFP8 {
     }
 };
 
+// ---- Cross-lane sums without the LDS crossbar.  Every exchange pairs lane l
+// with lane l ^ O, the pairs __shfl_xor(x, O) would form, so the sums (and
+// their rounding) are the same: distances 32 and 16 swap register halves
+// between lanes (v_permlane32_swap, v_permlane16_swap), 8 and 4 move values
+// between the lower and upper half of each group of 2 O lanes with
+// bank-masked DPP row shifts (a bank is 4 lanes of a 16-lane row), 2 and 1
+// use DPP quad permutes.  64-bit values move as two 32-bit words.
+
+template <typename T> struct LaneWords { static constexpr int n = sizeof(T) / 4; };
+
 template <typename T>
-__device__ inline T fwave_sum(T v)
+__device__ inline void to_words(T v, unsigned (&w)[LaneWords<T>::n])
 {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        v += __shfl_xor(v, o, 64);
+    __builtin_memcpy(w, &v, sizeof(T));
+}
+
+template <typename T>
+__device__ inline T from_words(const unsigned (&w)[LaneWords<T>::n])
+{
+    T v;
+    __builtin_memcpy(&v, w, sizeof(T));
     return v;
 }
 
+// For the pair (a, b): lanes whose index has bit O clear return
+// a + (the partner's a), lanes with the bit set (the partner's b) + b.
+template <int O, typename T>
+__device__ inline T pair_sum(T a, T b, int lane)
+{
+    constexpr int W = LaneWords<T>::n;
+    unsigned wa[W], wb[W];
+    to_words(a, wa);
+    to_words(b, wb);
+    if constexpr (O == 32 || O == 16) {
+        // lanes of the upper half of a's register trade places with lanes of
+        // the lower half of b's
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            const auto r = O == 32 ? __builtin_amdgcn_permlane32_swap(wa[i], wb[i], false, false)
+                                   : __builtin_amdgcn_permlane16_swap(wa[i], wb[i], false, false);
+            wa[i] = r[0];
+            wb[i] = r[1];
+        }
+        return from_words<T>(wa) + from_words<T>(wb);
+    } else if constexpr (O == 8 || O == 4) {
+        // row_shl:O (lane i reads lane i + O) into the lower-half banks,
+        // row_shr:O (lane i reads lane i - O) into the upper-half banks
+        constexpr int lo = O == 8 ? 0x3 : 0x5, hi = O == 8 ? 0xC : 0xA;
+        unsigned na[W], nb[W];
+#pragma unroll
+        for (int i = 0; i < W; ++i) {
+            nb[i] = (unsigned)__builtin_amdgcn_update_dpp((int)wb[i], (int)wa[i], 0x100 + O, 0xF,
+                                                          lo, false);
+            na[i] = (unsigned)__builtin_amdgcn_update_dpp((int)wa[i], (int)wb[i], 0x110 + O, 0xF,
+                                                          hi, false);
+        }
+        return from_words<T>(na) + from_words<T>(nb);
+    } else {
+        static_assert(O == 2 || O == 1, "lane distance");
+        const bool up = (lane & O) != 0;
+        const T keep = up ? b : a, send = up ? a : b;
+        unsigned ws[W];
+        to_words(send, ws);
+#pragma unroll
+        for (int i = 0; i < W; ++i) // quad_perm [2,3,0,1] / [1,0,3,2]
+            ws[i] = (unsigned)__builtin_amdgcn_mov_dpp((int)ws[i], O == 2 ? 0x4E : 0xB1, 0xF, 0xF,
+                                                       false);
+        return keep + from_words<T>(ws);
+    }
+}
+
+// x + (lane l ^ O's x) in every lane l.
+template <int O, typename T>
+__device__ inline T xor_add(T x)
+{
+    if constexpr (O >= 4) {
+        return pair_sum<O>(x, x, 0);
+    } else {
+        constexpr int W = LaneWords<T>::n;
+        unsigned ws[W];
+        to_words(x, ws);
+#pragma unroll
+        for (int i = 0; i < W; ++i)
+            ws[i] = (unsigned)__builtin_amdgcn_mov_dpp((int)ws[i], O == 2 ? 0x4E : 0xB1, 0xF, 0xF,
+                                                       false);
+        return x + from_words<T>(ws);
+    }
+}
+
+template <int O, typename T>
+__device__ inline T fold_from(T x)
+{
+    if constexpr (O >= 1)
+        return fold_from<O / 2>(xor_add<O>(x));
+    else
+        return x;
+}
+
+// Sum over the 64 lanes of a wave, in every lane (lane distances 32, 16, ..., 1).
+template <typename T>
+__device__ inline T fwave_sum(T v)
+{
+    return fold_from<32>(v);
+}
+
+template <int H, int O, typename T, int PR>
+__device__ inline void scatter_halve(T (&cur)[PR], int lane, int &r0)
+{
+    if constexpr (H >= 1) {
+#pragma unroll
+        for (int i = 0; i < H; ++i)
+            cur[i] = pair_sum<O>(cur[i], cur[i + H], lane);
+        r0 += (lane & O) ? H : 0;
+        scatter_halve<H / 2, O / 2>(cur, lane, r0);
+    }
+}
 
 // Sums of the PR values v[r] over the 64 lanes of a wave, scattered over the
-// lanes: the first log2(PR) exchange steps (lane offsets 32, 16, ...) each
-// keep half of the rows -- the lower half where the offset bit of the lane is
-// clear -- and add the partner's copy of that half; the remaining offsets
-// complete the one row left.  Lane l ends with the total of row `row` (read
-// from the offset bits of l); 6 + PR - 2 shuffles instead of 6 PR.
+// lanes: the first log2(PR) exchange steps (lane distances 32, 16, ...) each
+// keep half of the rows -- the lower half where the distance bit of the lane
+// is clear -- and add the partner's copy of that half; the remaining
+// distances complete the one row left.  Lane l ends with the total of row
+// `row` (read from the distance bits of l); PR - 1 + 6 - log2(PR) exchanges
+// instead of 6 PR.
 template <typename T, int PR>
 __device__ inline T wave_scatter_sum(const T (&v)[PR], int lane, int &row)
 {
@@ -110,24 +218,9 @@ __device__ inline T wave_scatter_sum(const T (&v)[PR], int lane, int &row)
     for (int r = 0; r < PR; ++r)
         cur[r] = v[r];
     int r0 = 0;
-    int o = 32;
-#pragma unroll
-    for (int h = PR / 2; h >= 1; h >>= 1, o >>= 1) {
-        const bool up = (lane & o) != 0;
-#pragma unroll
-        for (int i = 0; i < h; ++i) {
-            const T keep = up ? cur[i + h] : cur[i];
-            const T send = up ? cur[i] : cur[i + h];
-            cur[i] = keep + __shfl_xor(send, o, 64);
-        }
-        r0 += up ? h : 0;
-    }
-    T x = cur[0];
-#pragma unroll
-    for (int oo = 64 / PR / 2; oo > 0; oo >>= 1)
-        x += __shfl_xor(x, oo, 64);
+    scatter_halve<PR / 2, 32>(cur, lane, r0);
     row = r0;
-    return x;
+    return fold_from<64 / PR / 2>(cur[0]);
 }
 
 // Panels of at least this many rows (FP8) reduce t with wave_scatter_sum:

@@ -27,6 +27,20 @@ namespace gspca {
 // are held to 128 registers so that two workgroups share a compute unit (at
 // 65536 x 8192: BF16 206 -> 190 us, FP8 128 -> 118 us per pass, despite a few
 // spilled registers outside the panel loop).
+// The value `v` holds in lane r of the wave (r a compile-time constant),
+// uniform across the wave.
+__device__ inline float lane_value(float v, int r)
+{
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), r));
+}
+__device__ inline double lane_value(double v, int r)
+{
+    const long long b = __double_as_longlong(v);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffll), r);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), r);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 template <class C, bool PL, bool PIPE>
 constexpr int pass_waves_per_eu()
 {
@@ -139,13 +153,16 @@ __global__ __launch_bounds__(PL ? 1024 : 512, (pass_waves_per_eu<C, PL, PIPE>())
                         red[slot][w][r] = tp[r];
             }
             __syncthreads();
-#pragma unroll
-            for (int r = 0; r < PR; ++r) {
-                E s = E(0);
+            // lane r < PR of every wave adds row r over the waves (in wave
+            // order), then the PR totals are read from those lanes: PR LDS
+            // reads per wave instead of nw * PR broadcast reads per lane
+            E mine = E(0);
+            if (lane < PR)
                 for (int i = 0; i < nw; ++i)
-                    s += red[slot][i][r];
-                tb[r] = s;
-            }
+                    mine += red[slot][i][lane];
+#pragma unroll
+            for (int r = 0; r < PR; ++r)
+                tb[r] = lane_value(mine, r);
             if (tid < PR) {
                 const int64_t m = b * PR + tid;
                 const double tv = (double)tb[tid];

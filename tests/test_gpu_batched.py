@@ -219,14 +219,16 @@ def test_batched_given_start(orc):
 @pytest.mark.parametrize("threads", [256, 512, 1024])
 def test_batched_single_pass_column_splits(orc, tmp_path, threads):
     """Every workgroup size on shapes at the edges of the single pass's column
-    split (one column group, 32 columns per wave, groups past N, more than 32
-    columns per wave -> two reads) and of its row tiles (M below, at and past
-    multiples of 64): parity with the FP64 oracle on the same trajectory."""
+    split (one column group, 32 and 64 columns per wave, groups past N, more
+    than 64 columns per wave -> two reads) and of its row tiles (M below, at
+    and past multiples of 64): parity with the FP64 oracle on the same
+    trajectory."""
     import torch
     import paper_0811_1081_amd as gp
     from paper_0811_1081_amd import synth
     shapes = [(5, 4), (63, 16), (64, 31), (65, 32), (200, 33), (130, 64), (300, 65),
-              (129, 128), (700, 129), (257, 256), (1000, 257), (333, 300), (1100, 512)]
+              (129, 128), (700, 129), (257, 256), (1000, 257), (333, 300), (1100, 512),
+              (520, 513), (300, 1024)]
     probs = []
     for i, (M, N) in enumerate(shapes):
         r = min(M, N, 12)
