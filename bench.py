@@ -306,7 +306,8 @@ def bench_batched(args):
     import torch
     import paper_0811_1081_amd as gp
     gp.load()
-    Xs = [gp.column_major(torch.from_numpy(x).cuda()) for x in host]
+    # columns on 128-byte boundaries (leading dimension a multiple of 32)
+    Xs = [gp.column_major(torch.from_numpy(x).cuda(), align=32) for x in host]
     del host
     Ks = [k for _, _, k in shapes]
     b = gp.Batch(Xs, Ks, tol=args.tol, max_iter=args.max_iter)
@@ -338,10 +339,10 @@ def bench_batched(args):
     compulsory = float(mn.sum() * 4)              # every matrix read from HBM once
     # reads of each matrix: its column norms, per component the first loading
     # (q = X^T t0) and one read per iteration (t and q from one pass; two when
-    # a problem has more than 32 columns per wave), and W's column X^T v for
+    # a problem has more than 64 columns per wave), and W's column X^T v for
     # every component but the last
     nwaves = threads // 64
-    per_iter = np.array([1.0 if n <= 32 * nwaves else 2.0 for _, n, _ in shapes])
+    per_iter = np.array([1.0 if n <= 64 * nwaves else 2.0 for _, n, _ in shapes])
     kk = np.array([k for _, _, k in shapes], dtype=np.float64)
     reads = 1.0 + kk + per_iter * it_sum + (kk - 1.0)
     streamed = float((mn * 4 * reads).sum())

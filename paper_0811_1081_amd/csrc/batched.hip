@@ -216,24 +216,82 @@ __device__ void batch_pass(const float *X, int64_t ldx, int M, int N, int CW,
     }
 }
 
-// This lane's share of |col|^2 over n rows, in the same shape as lane_dot.
-__device__ inline double lane_sq(const float *__restrict__ col, int n, int lane)
+// out_j = X_j . v for every column (v in LDS, FP64), or with SQ the squared
+// column norms |X_j|^2 -- the products of the first loading (q = X^T t0), of
+// W (X^T v_k) and of the column norms.  Waves take chunks of CC = 8 columns
+// with the lanes over rows (the buffer loads and 256-byte column segments of
+// batch_pass), keep FP64 per-lane sums of their columns over the rows they
+// visit, TI = 4 row tiles (1 KiB of each column) in flight, and finish a
+// chunk with one reduce-scatter: no workgroup barrier inside, unlike
+// batch_pass (whose t sums need one per tile).  With fewer chunks than
+// waves, RP waves share a chunk by interleaved row tiles and their sums are
+// added in LDS (scr, RP x CC x chunks doubles) in a fixed order.  Rows and
+// columns out of range are read clamped; such rows weigh 0 and such columns
+// are not written.
+template <bool SQ>
+__device__ void batch_tpass(const float *X, int64_t ldx, int M, int N, const double *v,
+                            double *scr, double *out)
 {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int m = lane;
-    for (; m + 7 * 64 < n; m += 8 * 64) {
-        float x[8];
+    constexpr int CC = 8, TI = 4;
+    const int tid = threadIdx.x, lane = tid & 63, NT = blockDim.x;
+    const int nw = NT >> 6;
+    const int w = __builtin_amdgcn_readfirstlane(tid >> 6);
+    const int nch = (N + CC - 1) / CC;
+    int RP = 1;
+    while (RP * 2 * nch <= nw)
+        RP <<= 1;
+    const int rpart = w % RP, cstep = nw / RP, rstep = 64 * RP;
+    const int ld = (int)ldx;
+    const __amdgpu_buffer_rsrc_t xs = __builtin_amdgcn_make_buffer_rsrc(
+        (void *)X, (short)0, (int)(((int64_t)(N - 1) * ldx + M) * 4), 0x00020000);
+    for (int ch = w / RP; ch < nch; ch += cstep) {
+        const int cbase = ch * CC;
+        double acc[CC];
 #pragma unroll
-        for (int u = 0; u < 8; ++u)
-            x[u] = col[m + 64 * u];
-        s0 += (double)x[0] * (double)x[0] + (double)x[4] * (double)x[4];
-        s1 += (double)x[1] * (double)x[1] + (double)x[5] * (double)x[5];
-        s2 += (double)x[2] * (double)x[2] + (double)x[6] * (double)x[6];
-        s3 += (double)x[3] * (double)x[3] + (double)x[7] * (double)x[7];
+        for (int c = 0; c < CC; ++c)
+            acc[c] = 0.0;
+        for (int m0 = rpart * 64; m0 < M; m0 += TI * rstep) {
+            float x[TI][CC];
+#pragma unroll
+            for (int u = 0; u < TI; ++u) {
+                const int row = m0 + u * rstep + lane;
+                const int rowb = (row < M ? row : M - 1) * 4;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) {
+                    const int col = cbase + c < N ? cbase + c : N - 1;
+                    x[u][c] = __uint_as_float(
+                        __builtin_amdgcn_raw_buffer_load_b32(xs, rowb, col * ld * 4, 0));
+                }
+            }
+#pragma unroll
+            for (int u = 0; u < TI; ++u) {
+                const int row = m0 + u * rstep + lane;
+                const double wt = row < M ? (SQ ? 1.0 : v[row]) : 0.0;
+#pragma unroll
+                for (int c = 0; c < CC; ++c) {
+                    const double a = (double)x[u][c];
+                    acc[c] += (SQ ? a : 1.0) * a * wt;
+                }
+            }
+        }
+        int slot;
+        const double sum = wave_scatter_sum<double, CC>(acc, lane, slot);
+        if ((lane & (64 / CC - 1)) == 0 && cbase + slot < N) {
+            if (RP == 1)
+                out[cbase + slot] = sum;
+            else
+                scr[rpart * nch * CC + cbase + slot] = sum;
+        }
     }
-    for (; m < n; m += 64)
-        s0 += (double)col[m] * (double)col[m];
-    return (s0 + s1) + (s2 + s3);
+    if (RP > 1) {
+        __syncthreads();
+        for (int j = tid; j < N; j += NT) {
+            double s = 0.0;
+            for (int r = 0; r < RP; ++r)
+                s += scr[r * nch * CC + j];
+            out[j] = s;
+        }
+    }
 }
 
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
@@ -289,14 +347,11 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
         if (tid == 0)
             bad = 0;
         __syncthreads();
-        for (int j = w; j < N; j += nw) {
-            const double s = fwave_sum(lane_sq(X + (int64_t)j * ldx, M, lane));
-            if (lane == 0) {
-                cn0[j] = s;
-                if (!isfinite(s))
-                    bad = 1;
-            }
-        }
+        batch_tpass<true>(X, ldx, M, N, nullptr, reinterpret_cast<double *>(xr), cn0);
+        __syncthreads();
+        for (int j = tid; j < N; j += NT)
+            if (!isfinite(cn0[j]))
+                bad = 1;
         __syncthreads();
         if (bad) {
             if (tid == 0 && it.status)
@@ -398,11 +453,7 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
             auto loading = [&](int first, int from_pass) -> bool {
                 __syncthreads();
                 if (!from_pass) {
-                    for (int j = w; j < N; j += nw) {
-                        const double s = fwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
-                        if (lane == 0)
-                            q[j] = s;
-                    }
+                    batch_tpass<false>(X, ldx, M, N, t, reinterpret_cast<double *>(xr), q);
                 } else if (k > 0) {
                     for (int j = tid; j < N; j += NT) {
                         double wd = 0.0;
@@ -575,11 +626,11 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
             }
             __syncthreads();
             if (k + 1 < K) {
-                for (int j = w; j < N; j += nw) {
-                    const double s = fwave_sum(lane_dot(X + (int64_t)j * ldx, t, M, lane));
-                    if (lane == 0)
-                        W[j + (int64_t)k * N] = degenerate ? 0.0 : s;
-                }
+                // W[:, k] = X^T v_k (q is free here)
+                batch_tpass<false>(X, ldx, M, N, t, reinterpret_cast<double *>(xr), q);
+                __syncthreads();
+                for (int j = tid; j < N; j += NT)
+                    W[j + (int64_t)k * N] = degenerate ? 0.0 : q[j];
             }
             __syncthreads();
         }

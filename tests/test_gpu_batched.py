@@ -82,6 +82,36 @@ def test_batched_matches_oracle(orc):
         assert np.array_equal(b.lam[i].cpu().numpy(), b.sigma[i].cpu().numpy() ** 2)
 
 
+def test_batched_padded_leading_dimension():
+    """Columns padded to a 128-byte multiple (and odd paddings), NaN in the
+    padding rows: the kernel reads none of them, and the fit is bitwise the
+    one of the unpadded matrices."""
+    import torch
+    import paper_0811_1081_amd as gp
+    probs = _problems(12, seed=7, mmax=1500, nmax=300)
+    Ks = [k for _, k in probs]
+    dense = [_gh().to_device(X) for X, _ in probs]
+    padded = []
+    for i, (X, _) in enumerate(probs):
+        M, N = X.shape
+        ld = -(-M // 32) * 32 + (0 if i % 3 else 7)
+        store = torch.full((N, ld), float("nan"), dtype=torch.float32, device="cuda")
+        store[:, :M] = torch.from_numpy(np.ascontiguousarray(X.T)).cuda()
+        Xp = store.t()[:M]
+        assert Xp.stride() == (1, ld) and torch.equal(Xp, dense[i])
+        padded.append(Xp)
+    a = gp.Batch(dense, Ks, tol=1e-6, max_iter=1000)
+    b = gp.Batch(padded, Ks, tol=1e-6, max_iter=1000)
+    a.launch()
+    b.launch()
+    torch.cuda.synchronize()
+    assert np.all(a.status.cpu().numpy() == 0) and np.all(b.status.cpu().numpy() == 0)
+    for i in range(len(probs)):
+        for x, y in ((a.T[i], b.T[i]), (a.P[i], b.P[i]), (a.sigma[i], b.sigma[i]),
+                     (a.iters[i], b.iters[i]), (a.start_col[i], b.start_col[i])):
+            assert torch.equal(x, y), i
+
+
 def test_batched_equals_single_fit_trajectory(orc):
     """The batched kernel and the single-problem library path run the same
     method: with the same replayed counts their results agree."""
