@@ -45,6 +45,26 @@ __device__ inline double bblock_sum(double v, double *red)
     return r;
 }
 
+// Two workgroup sums for one pair of barriers (`red` holds two slots per wave).
+__device__ inline void bblock_sum2(double a, double b, double *red, double &ra, double &rb)
+{
+    a = fwave_sum(a);
+    b = fwave_sum(b);
+    const int w = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    __syncthreads();
+    if ((threadIdx.x & 63) == 0) {
+        red[w] = a;
+        red[16 + w] = b;
+    }
+    __syncthreads();
+    ra = 0.0;
+    rb = 0.0;
+    for (int i = 0; i < nw; ++i) {
+        ra += red[i];
+        rb += red[16 + i];
+    }
+}
+
 // This lane's share of col . v over n rows (lanes over rows, eight rows per
 // lane in flight; the wave sum finishes the product).
 __device__ inline double lane_dot(const float *__restrict__ col, const double *__restrict__ v,
@@ -305,7 +325,7 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
 {
     constexpr bool kAhead = MAXT <= 512;
     extern __shared__ double lds[];
-    __shared__ double red[16];
+    __shared__ double red[32];
     __shared__ int cur, bad;
     __shared__ int64_t sel, selmax;
     __shared__ double sred[16];
@@ -343,6 +363,10 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
         double *sig = cn0 + N;
         double *dc = sig + K;
 
+        // pf past N stays zero for the whole problem (the single pass's
+        // column groups may reach past N)
+        for (int j = N + tid; j < npf; j += NT)
+            pf[j] = 0.f;
         // |X_j|^2: waves over columns, lanes over rows; NaN/Inf ends the problem
         if (tid == 0)
             bad = 0;
@@ -481,10 +505,16 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
                     s2 += v * v;
                     dt += v * pprev[j];
                 }
-                const double nrm = sqrt(bblock_sum(s2, red));
-                const double dot = bblock_sum(dt, red);
+                double nrm, dot;
+                bblock_sum2(s2, dt, red, nrm, dot);
+                nrm = sqrt(nrm);
                 if (!(nrm >= a.tiny))
                     return false;
+                // FP32 copy of p / |p| for the pass (each thread its own j, as
+                // written above; the barrier at the top of the iteration
+                // publishes it)
+                for (int j = tid; j < N; j += NT)
+                    pf[j] = (float)(p[j] / nrm);
                 dp = INFINITY;
                 if (!first && a.stop == 1) {
                     const double ia = 1.0 / nrm, ib = (dot >= 0.0 ? 1.0 : -1.0) / pn;
@@ -507,10 +537,7 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
             }
             while (!degenerate && iters < limit) {
                 ++iters;
-                // t = X p / |p|: threads over rows, FP32 products, four partial sums
-                __syncthreads();
-                for (int j = tid; j < npf; j += NT)
-                    pf[j] = j < N ? (float)(p[j] / pn) : 0.f;
+                // t = X p / |p| (pf, written by the loading)
                 __syncthreads();
                 switch (CPW) {
                 case 4: batch_pass<4, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
