@@ -65,28 +65,6 @@ __device__ inline void bblock_sum2(double a, double b, double *red, double &ra, 
     }
 }
 
-// This lane's share of col . v over n rows (lanes over rows, eight rows per
-// lane in flight; the wave sum finishes the product).
-__device__ inline double lane_dot(const float *__restrict__ col, const double *__restrict__ v,
-                                  int n, int lane)
-{
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int m = lane;
-    for (; m + 7 * 64 < n; m += 8 * 64) {
-        float x[8];
-#pragma unroll
-        for (int u = 0; u < 8; ++u)
-            x[u] = col[m + 64 * u];
-        s0 += (double)x[0] * v[m] + (double)x[4] * v[m + 256];
-        s1 += (double)x[1] * v[m + 64] + (double)x[5] * v[m + 320];
-        s2 += (double)x[2] * v[m + 128] + (double)x[6] * v[m + 384];
-        s3 += (double)x[3] * v[m + 192] + (double)x[7] * v[m + 448];
-    }
-    for (; m < n; m += 64)
-        s0 += (double)col[m] * v[m];
-    return (s0 + s1) + (s2 + s3);
-}
-
 // LDS floats (at the start of the dynamic LDS) for the cross-wave sums of
 // batch_pass: two buffers of one value per thread of a 1024-thread workgroup.
 constexpr int kPassLdsFloats = 2 * 1024;
@@ -238,7 +216,8 @@ __device__ void batch_pass(const float *X, int64_t ldx, int M, int N, int CW,
 
 // out_j = X_j . v for every column (v in LDS, FP64), or with SQ the squared
 // column norms |X_j|^2 -- the products of the first loading (q = X^T t0), of
-// W (X^T v_k) and of the column norms.  Waves take chunks of CC = 8 columns
+// W (X^T v_k) and of the column norms, and with X = V_(k) or P_(k) the
+// Gram-Schmidt coefficients d = V^T t and c = P^T q.  Waves take chunks of CC = 8 columns
 // with the lanes over rows (the buffer loads and 256-byte column segments of
 // batch_pass), keep FP64 per-lane sums of their columns over the rows they
 // visit, TI = 4 row tiles (1 KiB of each column) in flight, and finish a
@@ -487,11 +466,8 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
                     }
                 }
                 __syncthreads();
-                for (int i = w; i < k; i += nw) {
-                    const double s = fwave_sum(lane_dot(P + (int64_t)i * N, q, N, lane));
-                    if (lane == 0)
-                        dc[i] = s;
-                }
+                if (k > 0)
+                    batch_tpass<false>(P, N, N, k, q, reinterpret_cast<double *>(xr), dc);
                 __syncthreads();
                 double s2 = 0.0, dt = 0.0;
                 for (int j = tid; j < N; j += NT) {
@@ -571,11 +547,8 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
                 }
                 __syncthreads();
                 // d = V^T t, t <- t - V d, sigma
-                for (int i = w; i < k; i += nw) {
-                    const double s = fwave_sum(lane_dot(T + (int64_t)i * M, t, M, lane));
-                    if (lane == 0)
-                        dc[i] = s;
-                }
+                if (k > 0)
+                    batch_tpass<false>(T, M, M, k, t, reinterpret_cast<double *>(xr), dc);
                 __syncthreads();
                 double s2 = 0.0;
                 for (int m = tid; m < M; m += NT) {
