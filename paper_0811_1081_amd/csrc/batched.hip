@@ -66,8 +66,9 @@ __device__ inline void bblock_sum2(double a, double b, double *red, double &ra, 
 }
 
 // LDS floats (at the start of the dynamic LDS) for the cross-wave sums of
-// batch_pass: two buffers of one value per thread of a 1024-thread workgroup.
-constexpr int kPassLdsFloats = 2 * 1024;
+// batch_pass: two buffers of two values per thread of a 1024-thread
+// workgroup (two row tiles per step).
+constexpr int kPassLdsFloats = 2 * 2 * 1024;
 
 // Column split of the single pass: CW waves share the columns of a row tile,
 // CPW (a power of two, 4..64) columns per wave, at most 32 while the
@@ -107,7 +108,7 @@ __device__ inline void pass_split(int N, int64_t ldx, int nw, int &CW, int &CPW)
 // registers) does this: under the 128-register bound of 16 waves the
 // compiler spills inside the tile loop and the reload waits for the
 // prefetch (121.6 vs 114.0 ms per replay of the 2048-problem batch).
-template <int CPW, bool AHEAD>
+template <int CPW, int TP, bool AHEAD>
 __device__ void batch_pass(const float *X, int64_t ldx, int M, int N, int CW,
                            const float *pf, float *xr, double *t, double *q)
 {
@@ -127,73 +128,93 @@ __device__ void batch_pass(const float *X, int64_t ldx, int M, int N, int CW,
 #pragma unroll
     for (int c = 0; c < CPW; ++c)
         pv[c] = pf[cbase + c];
-    const int tile = 64 * RS;
-    auto load = [&](float (&x)[CPW], int m0) {
-        const int row = m0 + rs * 64 + lane;
-        const int rowb = (row < M ? row : M - 1) * 4;
+    const int tile = 64 * RS, step = TP * tile;
+    // TP tiles of 64 RS rows per step: sub-tile u of the wave is rows
+    // m0 + u tile + 64 rs + [0, 64); its loads are issued together, so each
+    // column is read in runs of TP * 256 bytes
+    auto load = [&](float (&x)[TP][CPW], int m0) {
 #pragma unroll
-        for (int c = 0; c < CPW; ++c) {
-            const int col = cbase + c < N ? cbase + c : N - 1;
-            x[c] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(xs, rowb, col * ld * 4, 0));
+        for (int u = 0; u < TP; ++u) {
+            const int row = m0 + u * tile + rs * 64 + lane;
+            const int rowb = (row < M ? row : M - 1) * 4;
+#pragma unroll
+            for (int c = 0; c < CPW; ++c) {
+                const int col = cbase + c < N ? cbase + c : N - 1;
+                x[u][c] = __uint_as_float(
+                    __builtin_amdgcn_raw_buffer_load_b32(xs, rowb, col * ld * 4, 0));
+            }
         }
     };
     double qacc = 0.0;
     int slot = 0;
     int buf = 0;
-    // one tile: t partials of x, the cross-wave sum, then x's q terms
-    auto body = [&](float (&x)[CPW], float (&xn)[CPW], int m0) {
-        const int row = m0 + rs * 64 + lane;
-        float ta = 0.f, tb = 0.f;
+    // one step: t partials of the TP tiles, the cross-wave sums (one
+    // barrier), then the q terms of both tiles in one reduce-scatter
+    auto body = [&](float (&x)[TP][CPW], float (&xn)[TP][CPW], int m0) {
+        float *red = xr + buf * (TP * 1024);
 #pragma unroll
-        for (int c = 0; c < CPW; c += 2) {
-            ta += x[c] * pv[c];
-            tb += x[c + 1] * pv[c + 1];
+        for (int u = 0; u < TP; ++u) {
+            float ta = 0.f, tb = 0.f;
+#pragma unroll
+            for (int c = 0; c < CPW; c += 2) {
+                ta += x[u][c] * pv[c];
+                tb += x[u][c + 1] * pv[c + 1];
+            }
+            red[u * 1024 + cw * tile + rs * 64 + lane] = ta + tb;
         }
-        float *red = xr + buf * 1024;
-        red[cw * tile + rs * 64 + lane] = ta + tb;
         if constexpr (AHEAD) {
-            if (m0 + tile < M)
-                load(xn, m0 + tile);
+            if (m0 + step < M)
+                load(xn, m0 + step);
         }
         __syncthreads();
-        // the CW shares in order, four reads in flight at a time
-        const float *rp = red + rs * 64 + lane;
-        double tv = 0.0;
-        if (CW >= 4) {
-            for (int g = 0; g < CW; g += 4) {
-                const float r0 = rp[g * tile], r1 = rp[(g + 1) * tile];
-                const float r2 = rp[(g + 2) * tile], r3 = rp[(g + 3) * tile];
-                tv += (double)r0;
-                tv += (double)r1;
-                tv += (double)r2;
-                tv += (double)r3;
-            }
-        } else {
-            for (int g = 0; g < CW; ++g)
-                tv += (double)rp[g * tile];
-        }
-        if (row >= M)
-            tv = 0.0;
-        else if (cw == 0)
-            t[row] = tv;
-        const float tf = (float)tv;
+        float tf[TP];
 #pragma unroll
-        for (int c = 0; c < CPW; ++c)
-            x[c] *= tf;
-        qacc += (double)wave_scatter_sum<float, CPW>(x, lane, slot);
+        for (int u = 0; u < TP; ++u) {
+            // the CW shares in order, four reads in flight at a time
+            const float *rp = red + u * 1024 + rs * 64 + lane;
+            double tv = 0.0;
+            if (CW >= 4) {
+                for (int g = 0; g < CW; g += 4) {
+                    const float r0 = rp[g * tile], r1 = rp[(g + 1) * tile];
+                    const float r2 = rp[(g + 2) * tile], r3 = rp[(g + 3) * tile];
+                    tv += (double)r0;
+                    tv += (double)r1;
+                    tv += (double)r2;
+                    tv += (double)r3;
+                }
+            } else {
+                for (int g = 0; g < CW; ++g)
+                    tv += (double)rp[g * tile];
+            }
+            const int row = m0 + u * tile + rs * 64 + lane;
+            if (row >= M)
+                tv = 0.0;
+            else if (cw == 0)
+                t[row] = tv;
+            tf[u] = (float)tv;
+        }
+#pragma unroll
+        for (int c = 0; c < CPW; ++c) {
+            float y = x[0][c] * tf[0];
+#pragma unroll
+            for (int u = 1; u < TP; ++u)
+                y += x[u][c] * tf[u];
+            x[0][c] = y;
+        }
+        qacc += (double)wave_scatter_sum<float, CPW>(x[0], lane, slot);
         buf ^= 1;
     };
-    float xa[CPW];
+    float xa[TP][CPW];
     if constexpr (AHEAD) {
-        float xb[CPW];
+        float xb[TP][CPW];
         load(xa, 0);
-        for (int m0 = 0; m0 < M; m0 += 2 * tile) {
+        for (int m0 = 0; m0 < M; m0 += 2 * step) {
             body(xa, xb, m0);
-            if (m0 + tile < M)
-                body(xb, xa, m0 + tile);
+            if (m0 + step < M)
+                body(xb, xa, m0 + step);
         }
     } else {
-        for (int m0 = 0; m0 < M; m0 += tile) {
+        for (int m0 = 0; m0 < M; m0 += step) {
             load(xa, m0);
             body(xa, xa, m0);
         }
@@ -296,7 +317,9 @@ __device__ void batch_tpass(const float *X, int64_t ldx, int M, int N, const dou
 __global__ void k_batch_reset(uint32_t *counter) { *counter = 0u; }
 
 // MAXT: the most threads per compute unit the build serves (1024: 128
-// registers per lane; 512: 256 registers, and the single pass prefetches).
+// registers per lane; 512: 256 registers, and the single pass prefetches the
+// next two tiles up to 32 columns per wave).  The single pass takes two row
+// tiles per step except with 64 columns per wave in the 128-register build.
 template <int MAXT>
 __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ items, int nprob,
                                                   const int32_t *__restrict__ order,
@@ -516,11 +539,11 @@ __global__ __launch_bounds__(MAXT) void k_batched(const BatchItem *__restrict__ 
                 // t = X p / |p| (pf, written by the loading)
                 __syncthreads();
                 switch (CPW) {
-                case 4: batch_pass<4, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 8: batch_pass<8, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 16: batch_pass<16, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 32: batch_pass<32, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
-                case 64: batch_pass<64, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 4: batch_pass<4, 2, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 8: batch_pass<8, 2, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 16: batch_pass<16, 2, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 32: batch_pass<32, 2, kAhead>(X, ldx, M, N, CW, pf, xr, t, q); break;
+                case 64: batch_pass<64, kAhead ? 2 : 1, false>(X, ldx, M, N, CW, pf, xr, t, q); break;
                 default: break;
                 }
                 for (int m = CPW ? M : tid; m < M; m += NT) {

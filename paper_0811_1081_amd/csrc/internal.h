@@ -334,8 +334,8 @@ __host__ __device__ inline int batched_pf_floats(int N) { return 4 * ((3 * N + 6
 
 inline size_t batched_lds_bytes(int64_t M, int64_t N, int64_t K)
 {
-    // 8 KiB of cross-wave sums for the single pass, p in FP32, then the vectors
-    return (size_t)8192 + (size_t)batched_pf_floats((int)N) * 4 + (size_t)(M + 4 * N + 2 * K) * 8;
+    // 16 KiB of cross-wave sums for the single pass, p in FP32, then the vectors
+    return (size_t)16384 + (size_t)batched_pf_floats((int)N) * 4 + (size_t)(M + 4 * N + 2 * K) * 8;
 }
 
 }  // namespace gspca
