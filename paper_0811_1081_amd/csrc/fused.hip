@@ -190,6 +190,92 @@ __global__ __launch_bounds__(256) void k_deflate_panel(unsigned char *__restrict
             red[0][lane] + red[1][lane] + red[2][lane] + red[3][lane];
 }
 
+// The explicit deflation of component k fused with the first loading of
+// component k + 1: A <- A - t p^T (as k_deflate_panel, same arithmetic), the
+// squared column norms of the new A (partials cnpart[split][j]) and the
+// loading products q_part[split][j] = sum over the split's rows of
+// A'(m, j) t0(m), t0 being the next start (column c of A', formed beforehand
+// from the old A by k_start_fill).  One read and one write of A instead of
+// the deflation's read and write plus the first pass's read.  Grid: (column
+// blocks of 64) x (panel splits = the pass's workgroup count, so that the
+// loading side sums the partials as after a pass).
+template <class C>
+__global__ __launch_bounds__(256) void k_deflate_first(unsigned char *__restrict__ A, int64_t N,
+                                                       int64_t NP, int64_t ldp,
+                                                       const typename C::acc *__restrict__ t,
+                                                       const typename C::acc *__restrict__ pk,
+                                                       int update,
+                                                       const typename C::acc *__restrict__ t0,
+                                                       double *__restrict__ cnpart,
+                                                       typename C::acc *__restrict__ q_part)
+{
+    static_assert(!C::scaled, "explicit deflation is for plain storage");
+    using E = typename C::acc;
+    constexpr int PR = C::PR;
+    __shared__ double red[2][4][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int64_t j = (int64_t)blockIdx.x * 64 + lane;
+    const int64_t nsplit = gridDim.y;
+    const int64_t b0 = NP * blockIdx.y / nsplit, b1 = NP * (blockIdx.y + 1) / nsplit;
+    double s = 0.0, qa = 0.0;
+    if (j < N) {
+        const E pj = update ? pk[j] : E(0);
+        for (int64_t b = b0 + w; b < b1; b += 4) {
+            typename C::raw *ptr = reinterpret_cast<typename C::raw *>(A + (b * ldp + j) * 16);
+            typename C::raw v = *ptr;
+            if (update) {
+#pragma unroll
+                for (int r = 0; r < PR; ++r)
+                    v[r] = v[r] - t[b * PR + r] * pj;
+                *ptr = v;
+            }
+            double ss = 0.0, sq = 0.0;
+#pragma unroll
+            for (int r = 0; r < PR; ++r) {
+                const double e = (double)v[r];
+                ss += e * e;
+                sq += e * (double)t0[b * PR + r];
+            }
+            s += ss;
+            qa += sq;
+        }
+    }
+    red[0][w][lane] = s;
+    red[1][w][lane] = qa;
+    __syncthreads();
+    if (w == 0 && j < N) {
+        const int64_t o = (int64_t)blockIdx.y * N + j;
+        cnpart[o] = red[0][0][lane] + red[0][1][lane] + red[0][2][lane] + red[0][3][lane];
+        q_part[o] = (E)(red[1][0][lane] + red[1][1][lane] + red[1][2][lane] + red[1][3][lane]);
+    }
+}
+
+// Column norms of A - t p_k^T predicted from those of A before that
+// deflation: |A_j|^2 - 2 p_kj (A^T t)_j + p_kj^2 |t|^2, with A^T t = q' of
+// the component's last pass (q' = A^T t_pass - W d = A^T (t_pass - V d)) and
+// |t| = sigma.  Exact norms one deflation back plus this update choose the
+// next start before the deflation is carried out (k_deflate_first).  A
+// degenerate component (no deflation) keeps the norms.
+template <typename E>
+__global__ __launch_bounds__(256) void k_colnorm_predict(const double *__restrict__ cn,
+                                                         int64_t N, const E *__restrict__ pk,
+                                                         const double *__restrict__ qy,
+                                                         const LoopState *st,
+                                                         double *__restrict__ out)
+{
+    const int64_t j = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (j >= N)
+        return;
+    double v = cn[j];
+    if (!st->degenerate) {
+        const double p = (double)pk[j], s = st->sigma;
+        v += -2.0 * p * qy[j] + p * p * s * s;
+        if (v < 0.0)
+            v = 0.0;
+    }
+    out[j] = v;
+}
+
 // cn[j] = sum over splits of cnpart (fixed order); implicit mode: the norm of
 // the residual column A_j - T P[j,:]^T from |A_j|^2 and the finished
 // components, |A_j|^2 - 2 sum_i sigma_i P_ji (A^T v_i)_j + sum_i sigma_i^2 P_ji^2
@@ -407,7 +493,9 @@ __global__ __launch_bounds__(256) void k_start_fill(const unsigned char *__restr
                                                     const double *__restrict__ sig,
                                                     const typename C::acc *__restrict__ T0, int k,
                                                     typename C::acc *__restrict__ t,
-                                                    const LoopState *st)
+                                                    const LoopState *st,
+                                                    const typename C::acc *__restrict__ dt,
+                                                    const typename C::acc *__restrict__ dp)
 {
     using E = typename C::acc;
     const int64_t m = (int64_t)blockIdx.x * 256 + threadIdx.x;
@@ -418,6 +506,11 @@ __global__ __launch_bounds__(256) void k_start_fill(const unsigned char *__restr
     if (m < M) {
         if (c < 0) {
             v = T0[m + (int64_t)k * M];
+        } else if (dt) {
+            // column c of A - dt dp^T before that deflation is carried out,
+            // in the deflation's own arithmetic
+            const E a = panel_elem<C>(A, ldp, m, c, scale);
+            v = a - dt[m] * dp[c];
         } else {
             double s = (double)panel_elem<C>(A, ldp, m, c, scale);
             if (implicit)
@@ -841,7 +934,8 @@ template <int F>
 void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                      const float *scale, int implicit, const E *V, const E *P, const double *sig,
                      const double *cn, const E *T0, StartArgs a, double tiny, E *t,
-                     double *part, LoopState *st, hipStream_t s)
+                     double *part, LoopState *st, hipStream_t s, const E *defl_t,
+                     const E *defl_p)
 {
     using C = typename CodecOf<F>::type;
     const int nb = (int)fcdiv(M, kStartRows);
@@ -853,7 +947,26 @@ void Fused<F>::start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp,
     hipLaunchKernelGGL(k_start_panel<C>, dim3(1), dim3(1024), 0, s, A, N, NP, ldp, M, scale,
                        implicit, V, P, sig, cn, T0, a, tiny, part, nb, st);
     hipLaunchKernelGGL(k_start_fill<C>, dim3(fcdiv(NP * C::PR, 256)), dim3(256), 0, s, A, N, NP,
-                       ldp, M, scale, implicit, V, P, sig, T0, a.k, t, st);
+                       ldp, M, scale, implicit, V, P, sig, T0, a.k, t, st, defl_t, defl_p);
+}
+
+template <int F>
+void Fused<F>::deflate_first(unsigned char *A, int64_t N, int64_t NP, int64_t ldp, const E *t,
+                             const E *pk, int update, const E *t0, int nsplit, double *cnpart,
+                             E *q_part, hipStream_t s)
+{
+    using C = typename CodecOf<F>::type;
+    if constexpr (!C::scaled)
+        hipLaunchKernelGGL(k_deflate_first<C>, dim3(fcdiv(N, 64), nsplit), dim3(256), 0, s, A, N,
+                           NP, ldp, t, pk, update, t0, cnpart, q_part);
+}
+
+template <int F>
+void Fused<F>::colnorm_predict(const double *cn, int64_t N, const E *pk, const double *qy,
+                               const LoopState *st, double *out, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_colnorm_predict<E>, dim3(fcdiv(N, 256)), dim3(256), 0, s, cn, N, pk, qy,
+                       st, out);
 }
 
 template <int F>

@@ -338,7 +338,8 @@ struct FusedPlan {
     int plds, skew, pipe; // pass-kernel variant: loading in LDS (1024 threads), panel-order
                           // skew, register double buffering (else two workgroups per CU)
     size_t off_state, off_A, off_tE, off_td, off_tsq, off_qpart, off_d, off_c, off_qy, off_p,
-        off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_W, off_sig, total;
+        off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_cnx, off_t0, off_W,
+        off_sig, total;
 };
 
 int device_cu_count()
@@ -421,9 +422,13 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     f.off_pprev = o;  o = align_up(o + (size_t)N * 8);
     f.off_cpart = o;  o = align_up(o + (size_t)nbmax * (K + 1) * 8);
     f.off_sq = o;     o = align_up(o + (size_t)nbmax * 2 * 8);
-    f.off_cnpart = o; o = align_up(o + (size_t)f.nsplit_cn * N * 8);
+    // norm partials: the deflation's splits, or the pass's workgroups when
+    // the explicit deflation also forms the next first loading
+    f.off_cnpart = o; o = align_up(o + (size_t)std::max(f.nsplit_cn, f.G) * N * 8);
     f.off_cn = o;     o = align_up(o + (size_t)N * 8);
     f.off_cn0 = o;    o = align_up(o + (size_t)N * 8);
+    f.off_cnx = o;    o = align_up(o + (size_t)N * 8);
+    f.off_t0 = o;     o = align_up(o + (quantised ? 0 : len * esize));
     f.off_W = o;      o = align_up(o + (size_t)N * K * 8);
     f.off_sig = o;    o = align_up(o + (size_t)K * 8);
     f.total = o;
@@ -472,6 +477,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     double *cnpart = reinterpret_cast<double *>(base + f.off_cnpart);
     double *cn = reinterpret_cast<double *>(base + f.off_cn);
     double *cn0 = reinterpret_cast<double *>(base + f.off_cn0);
+    double *cnx = reinterpret_cast<double *>(base + f.off_cnx);
+    E *t0next = reinterpret_cast<E *>(base + f.off_t0);
     double *W = reinterpret_cast<double *>(base + f.off_W);
     double *sig = reinterpret_cast<double *>(base + f.off_sig);
     E *T = static_cast<E *>(rs->T);
@@ -530,17 +537,26 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     F::deflate(A, N, f.NP, f.ldp, nullptr, nullptr, 0, scale, f.nsplit_cn, cnpart, s);
     F::colnorm_finish(cnpart, f.nsplit_cn, N, cn0, cn, 0, 0, P, W, sig, s);
 
+    auto start_args = [&](int64_t k) {
+        const int32_t lim = replay ? rit[k] : op->max_iter;
+        return StartArgs{(int32_t)k, op->init, (replay && lim < 1) ? 1 : 0, gs ? 1 : 0,
+                         op->replay_start_col};
+    };
+    // explicit deflation: the start and first loading of component k + 1 are
+    // formed with the deflation that ends component k (k_deflate_first)
+    bool started = false;
     for (int64_t k = 0; k < K; ++k) {
         const int32_t limit = replay ? rit[k] : op->max_iter;
         const int kg = gs ? (int)k : 0;
-        StartArgs a{(int32_t)k, op->init, (replay && limit < 1) ? 1 : 0, gs ? 1 : 0,
-                    op->replay_start_col};
-        // the start's scratch (given-start products) shares cpart, idle here
-        F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, a, tiny, tE, cpart, st,
-                 s);
-        // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-        F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p, tE,
-                td, tsq, qpart, st, s);
+        if (!started) {
+            // the start's scratch (given-start products) shares cpart, idle here
+            F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, start_args(k),
+                     tiny, tE, cpart, st, s);
+            // first loading of the component: p = R^T t0, Gram-Schmidt, norm
+            F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p,
+                    tE, td, tsq, qpart, st, s);
+        }
+        started = false;
         // the loading side: one workgroup when N and the partials are small
         // (no cross-workgroup reductions; at most 256 KiB of partials, which
         // one workgroup reads in a few microseconds -- 512 x 256 FP64: 122 ->
@@ -608,9 +624,17 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                     gs ? W : nullptr, sig, rs->iters, rs->start_col, st, s);
         if (k + 1 < K) {
             if (!implicit) {
-                F::deflate(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, scale,
-                           f.nsplit_cn, cnpart, s);
-                F::colnorm_finish(cnpart, f.nsplit_cn, N, nullptr, cn, 0, 0, P, W, sig, s);
+                // next start on the norms this deflation leaves (predicted from
+                // the exact ones before it), its column taken from R - t p_k^T;
+                // then the deflation, the exact new norms and the first
+                // loading R'^T t0 in one read and write of R
+                F::colnorm_predict(cn, N, P + k * N, qy, st, cnx, s);
+                F::start(A, N, f.NP, f.ldp, M, scale, 0, T, P, sig, cnx, T0, start_args(k + 1),
+                         tiny, t0next, cpart, st, s, tE, P + k * N);
+                F::deflate_first(A, N, f.NP, f.ldp, tE, P + k * N, h.degenerate ? 0 : 1, t0next,
+                                 f.G, cnpart, qpart, s);
+                F::colnorm_finish(cnpart, f.G, N, nullptr, cn, 0, 0, P, W, sig, s);
+                started = true;
             } else {
                 F::colnorm_finish(nullptr, 1, N, cn0, cn, 1, (int)k + 1, P, W, sig, s);
             }

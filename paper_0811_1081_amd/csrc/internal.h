@@ -261,10 +261,19 @@ struct Fused {
     static void colnorm_finish(const double *cnpart, int nsplit, int64_t N, double *cn0,
                                double *cn, int implicit, int k, const E *P, const double *W,
                                const double *sig, hipStream_t s);
+    // defl_t, defl_p (explicit deflation pending): the start column is taken
+    // from A - defl_t defl_p^T
     static void start(const unsigned char *A, int64_t N, int64_t NP, int64_t ldp, int64_t M,
                       const float *scale, int implicit, const E *V, const E *P, const double *sig,
                       const double *cn, const E *T0, StartArgs a, double tiny, E *t,
-                      double *part, LoopState *st, hipStream_t s);
+                      double *part, LoopState *st, hipStream_t s, const E *defl_t = nullptr,
+                      const E *defl_p = nullptr);
+    // explicit deflation and the next component's first loading in one pass
+    static void deflate_first(unsigned char *A, int64_t N, int64_t NP, int64_t ldp, const E *t,
+                              const E *pk, int update, const E *t0, int nsplit, double *cnpart,
+                              E *q_part, hipStream_t s);
+    static void colnorm_predict(const double *cn, int64_t N, const E *pk, const double *qy,
+                                const LoopState *st, double *out, hipStream_t s);
     static void pass(int first, int cpt, int G, int NT, int plds, int skew, int pipe,
                      const unsigned char *A,
                      int64_t N, int64_t NP, int64_t ldp, int64_t M, const float *scale,
