@@ -803,6 +803,6 @@ const char *gspca_status_string(int status)
     }
 }
 
-int gspca_version(void) { return 100; }
+int gspca_version(void) { return 200; }
 
 }  // extern "C"
