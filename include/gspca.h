@@ -236,6 +236,9 @@ gspca_status gspca_quantize(const float *X, int64_t M, int64_t N, int64_t ldx, i
  * replay arrays are taken per problem.  All pointers are device pointers. */
 typedef struct {
     const float *X;
+    /* leading dimension, >= M; rows M..ldx-1 are never read.  A multiple of
+     * 32 (128-byte aligned columns) lets the kernel read whole cache lines:
+     * on a 2048-problem batch ldx = M costs ~10 % (104.5 vs 95.3 ms). */
     int64_t ldx;
     int64_t M, N, K;
     float *T;            /* M x K, leading dimension M                          */

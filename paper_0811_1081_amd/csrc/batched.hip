@@ -12,16 +12,18 @@
 //
 // Per iteration (FP32 data, FP64 Gram-Schmidt and norms, implicit deflation
 // R = X - T P^T on Gram-Schmidt-projected vectors):
-//   t = X p, q = X^T t      one read of X (batch_pass): a tile of rows is
-//                           held in registers while its t is summed across
-//                           the waves, then multiplied back into q
-//   d = V_(k)^T t           waves over components, lanes over rows
+//   t = X p, q = X^T t      one read of X (batch_pass): two tiles of rows
+//                           are held in registers while their t is summed
+//                           across the waves, then multiplied back into q
+//   d = V_(k)^T t           batch_tpass over the columns of V
 //   t <- t - V d, sigma = |t|, stop test (relative sigma, loading, replay)
 //   q <- q - W d            W = X^T V_(k), so q = X^T (t - V d)
-//   c = P_(k)^T q, p = q - P c, p / |p|
-// t, q, p, the column norms and the coefficient vectors live in LDS.  A
-// problem with more than 64 columns per wave reads X twice instead (t = X p
-// with threads over rows, then q = X^T t with waves over columns).
+//   c = P_(k)^T q (batch_tpass), p = q - P c, p / |p| (and its FP32 copy)
+// Per component: the first loading q = X^T t0 and W's column X^T v_k, and per
+// problem the column norms, also run on batch_tpass.  t, q, p, the column
+// norms and the coefficient vectors live in LDS.  A problem with more than 64
+// columns per wave reads X twice instead (t = X p with threads over rows, then
+// q = X^T t on batch_tpass).
 #include <float.h>
 #include <math.h>
 
