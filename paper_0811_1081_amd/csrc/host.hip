@@ -389,7 +389,13 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     const char *e_lds = getenv("GSPCA_PASS_LDS");
     const char *e_skew = getenv("GSPCA_PASS_SKEW");
     const char *e_pipe = getenv("GSPCA_PASS_PIPE");
-    f.plds = (e_lds && e_lds[0] == '1' && f.cpt >= 2 && f.NT <= 512) ? 1 : 0;
+    // FP8 codes keep the loading in LDS by default: their one-buffer pass at
+    // 128 registers reloads a spilled register inside the panel loop, while
+    // with half the columns per thread it does not (65536 x 8192: 4.96 ->
+    // 5.16 TB/s of codes; BF16 loses, 6.10 -> 5.91, and keeps registers)
+    const int lds_default = fmt == kFmtFP8 ? 1 : 0;
+    const int want_lds = e_lds ? (e_lds[0] == '1' ? 1 : 0) : lds_default;
+    f.plds = (want_lds && f.cpt >= 2 && f.NT <= 512) ? 1 : 0;
     f.skew = e_skew ? (e_skew[0] == '1' ? 1 : 0) : (fmt == kFmtBF16 ? 0 : 1);
     // Register double buffering pays for FP32 (318 vs 330 us per pass at 65536
     // x 8192); with decoded codes the second buffer spills (BF16 218 vs 185
