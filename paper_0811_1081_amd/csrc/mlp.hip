@@ -292,107 +292,6 @@ __global__ __launch_bounds__(256) void k_sketch(const float *__restrict__ X, int
     }
 }
 
-// The same product when X's columns are 16-byte aligned (ldx a multiple of
-// 4): workgroup b owns rows [64b, 64b + 64) (1024 workgroups at M = 65536);
-// 16-column chunks of X and the matching 16 rows of Omega are staged in LDS
-// with 16-byte loads, the next chunk's loads in flight while the current one
-// is multiplied (two LDS buffers, one barrier per chunk); each of the 256
-// threads accumulates a 4 x (R/16) block of Y in FP32, over j in the same
-// order as k_sketch.
-typedef float sf32x2_t __attribute__((ext_vector_type(2)));
-template <int R>
-__global__ __launch_bounds__(256) void k_sketch_v(const float *__restrict__ X, int64_t ldx,
-                                                  int64_t M, int64_t N,
-                                                  const float *__restrict__ Om,
-                                                  float *__restrict__ Y)
-{
-    constexpr int BM = 64, BK = 16, RB = R / 16, OQ = BK * R / 4;
-    __shared__ __align__(16) float xs[2][BK][BM];
-    __shared__ __align__(16) float os[2][BK][R];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4; // rows 4tx..4tx+3, sketch columns RB*ty..
-    const int64_t m0 = (int64_t)blockIdx.x * BM;
-    mf32x4_t xr, orr = {0.f, 0.f, 0.f, 0.f};
-    auto gload = [&](int64_t j0) {
-        { // column c, rows 4q..4q+3 of the tile
-            const int c = tid >> 4, q = tid & 15;
-            const int64_t m = m0 + 4 * q, j = j0 + c;
-            if (j < N && m + 3 < M) {
-                xr = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
-            } else {
-#pragma unroll
-                for (int u = 0; u < 4; ++u)
-                    xr[u] = (j < N && m + u < M) ? X[m + u + j * ldx] : 0.0f;
-            }
-        }
-        if (tid < OQ) { // Omega row c, columns 4u..4u+3
-            const int c = tid / (R / 4), u = tid % (R / 4);
-            const int64_t j = j0 + c;
-            if (j < N)
-                orr = *reinterpret_cast<const mf32x4_t *>(Om + j * R + 4 * u);
-            else
-                orr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
-        }
-    };
-    auto sstore = [&](int b) {
-        const int c = tid >> 4, q = tid & 15;
-        *reinterpret_cast<mf32x4_t *>(&xs[b][c][4 * q]) = xr;
-        if (tid < OQ) {
-            const int c2 = tid / (R / 4), u = tid % (R / 4);
-            *reinterpret_cast<mf32x4_t *>(&os[b][c2][4 * u]) = orr;
-        }
-    };
-    float acc[4][RB];
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < RB; ++b)
-            acc[a][b] = 0.0f;
-    gload(0);
-    sstore(0);
-    __syncthreads();
-    int buf = 0;
-    for (int64_t j0 = 0; j0 < N; j0 += BK) {
-        const bool more = j0 + BK < N;
-        if (more)
-            gload(j0 + BK); // in flight while this chunk is multiplied
-#pragma unroll 4
-        for (int c = 0; c < BK; ++c) {
-            const mf32x4_t x0 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][c][4 * tx]);
-            float ov[RB];
-            if constexpr (RB == 4) {
-                const mf32x4_t o = *reinterpret_cast<const mf32x4_t *>(&os[buf][c][RB * ty]);
-                ov[0] = o[0]; ov[1] = o[1]; ov[2] = o[2]; ov[3] = o[3];
-            } else {
-                const sf32x2_t o = *reinterpret_cast<const sf32x2_t *>(&os[buf][c][RB * ty]);
-                ov[0] = o[0]; ov[1] = o[1];
-            }
-            const float xv[4] = {x0[0], x0[1], x0[2], x0[3]};
-#pragma unroll
-            for (int a = 0; a < 4; ++a)
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-                    acc[a][b] += xv[a] * ov[b];
-        }
-        if (more)
-            sstore(buf ^ 1);
-        __syncthreads();
-        buf ^= 1;
-    }
-#pragma unroll
-    for (int a = 0; a < 4; ++a) {
-        const int64_t m = m0 + 4 * tx + a;
-        if (m < M) {
-            float *yr = Y + m * R + RB * ty;
-            if constexpr (RB == 4)
-                *reinterpret_cast<mf32x4_t *>(yr) =
-                    mf32x4_t{acc[a][0], acc[a][1], acc[a][2], acc[a][3]};
-            else
-                *reinterpret_cast<sf32x2_t *>(yr) = sf32x2_t{acc[a][0], acc[a][1]};
-        }
-    }
-}
-
 // W = s X^T Z (N x R, row-major) for a row-major M x R sketch Z, as partial
 // sums over row slices.  Workgroup (b, y) owns columns [64b, 64b + 64) of X
 // over row slice y: 32-row tiles of X (64 columns, read along the rows) and
@@ -459,23 +358,114 @@ __global__ __launch_bounds__(256) void k_sketch_t(const float *__restrict__ X, i
     }
 }
 
-// The same product when X's columns are 16-byte aligned (ldx a multiple of
-// 4): workgroup (b, y) owns columns [128b, 128b + 128) of X over row slice y;
-// 16-row chunks of X (16-byte loads along the rows, transposed into LDS) and
-// of Z are staged in two LDS buffers with the next chunk's loads in flight;
-// each thread accumulates an 8 x (R/16) block of W in FP32, over the rows in
-// the same order as k_sketch_t.
+// The two sketch products when X's columns are 16-byte aligned (ldx a
+// multiple of 4), on the FP32 matrix cores (v_mfma_f32_16x16x4f32:
+// D(16x16) += A(16x4) B(4x16), FP32 operands and accumulation; lane l
+// supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
+// D(4 (l / 16) + i, l % 16) in its i-th accumulator).  Chunks of 16 columns
+// (Y = X Om) or 16 rows (W = X^T Z) of X and the matching rows of Om or Z are
+// staged in two LDS buffers with 16-byte loads, the next chunk's loads in
+// flight while the current one is multiplied (one barrier per chunk), and
+// each chunk is four matrix-core steps of k = 4.  The products and sums are
+// FP32 as in k_sketch / k_sketch_t, in another order; at 65536 x 8192, r = 64
+// both take ~0.71 ms (~96 TFLOP/s) against 1.23 / 1.03 ms for the same tiling
+// on the vector ALU.
+
+// Y = X Om, X's columns 16-byte aligned: workgroup = 64 rows of Y; wave w
+// owns rows 16w..16w+15 and all R columns (R/16 tiles of 16).
 template <int R>
-__global__ __launch_bounds__(256) void k_sketch_t_v(const float *__restrict__ X, int64_t ldx,
+__global__ __launch_bounds__(256) void k_sketch_m(const float *__restrict__ X, int64_t ldx,
+                                                  int64_t M, int64_t N,
+                                                  const float *__restrict__ Om,
+                                                  float *__restrict__ Y)
+{
+    constexpr int BM = 64, BK = 16, RT = R / 16, OQ = BK * R / 4;
+    // rows padded by 16 floats: the four k rows a wave reads at once fall in
+    // different halves of the 32 banks
+    __shared__ __align__(16) float xs[2][BK][BM + 16];
+    __shared__ __align__(16) float os[2][BK][R + 16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
+    const int64_t m0 = (int64_t)blockIdx.x * BM;
+    mf32x4_t xr, orr = {0.f, 0.f, 0.f, 0.f};
+    auto gload = [&](int64_t j0) {
+        { // column c, rows 4q..4q+3 of the tile
+            const int c = tid >> 4, q = tid & 15;
+            const int64_t m = m0 + 4 * q, j = j0 + c;
+            if (j < N && m + 3 < M) {
+                xr = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
+            } else {
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    xr[u] = (j < N && m + u < M) ? X[m + u + j * ldx] : 0.0f;
+            }
+        }
+        if (tid < OQ) { // Omega row c, columns 4u..4u+3
+            const int c = tid / (R / 4), u = tid % (R / 4);
+            const int64_t j = j0 + c;
+            if (j < N)
+                orr = *reinterpret_cast<const mf32x4_t *>(Om + j * R + 4 * u);
+            else
+                orr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+        }
+    };
+    auto sstore = [&](int b) {
+        const int c = tid >> 4, q = tid & 15;
+        *reinterpret_cast<mf32x4_t *>(&xs[b][c][4 * q]) = xr;
+        if (tid < OQ) {
+            const int c2 = tid / (R / 4), u = tid % (R / 4);
+            *reinterpret_cast<mf32x4_t *>(&os[b][c2][4 * u]) = orr;
+        }
+    };
+    mf32x4_t acc[RT];
+#pragma unroll
+    for (int t = 0; t < RT; ++t)
+        acc[t] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+    gload(0);
+    sstore(0);
+    __syncthreads();
+    int buf = 0;
+    for (int64_t j0 = 0; j0 < N; j0 += BK) {
+        const bool more = j0 + BK < N;
+        if (more)
+            gload(j0 + BK); // in flight while this chunk is multiplied
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            const float a = xs[buf][kk + lk][16 * w + li];
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                acc[t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, os[buf][kk + lk][16 * t + li],
+                                                              acc[t], 0, 0, 0);
+        }
+        if (more)
+            sstore(buf ^ 1);
+        __syncthreads();
+        buf ^= 1;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+        const int64_t m = m0 + 16 * w + 4 * lk + i;
+        if (m < M)
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                Y[m * R + 16 * t + li] = acc[t][i];
+    }
+}
+
+// W = s X^T Z over row slice y (partial sums as k_sketch_t), X's columns
+// 16-byte aligned: workgroup (b, y) = 128 columns of X; wave w owns columns
+// 32w..32w+31 (two tiles of 16) and all R sketch columns.
+template <int R>
+__global__ __launch_bounds__(256) void k_sketch_t_m(const float *__restrict__ X, int64_t ldx,
                                                     int64_t M, int64_t N,
                                                     const float *__restrict__ Z, float s,
                                                     int64_t rows, float *__restrict__ W)
 {
-    constexpr int BN = 128, BK = 16, RB = R / 16, ZQ = BK * R / 4;
-    __shared__ __align__(16) float xs[2][BK][BN];
-    __shared__ __align__(16) float zs[2][BK][R];
-    const int tid = threadIdx.x;
-    const int tx = tid & 15, ty = tid >> 4; // X columns 8tx..8tx+7, sketch columns RB*ty..
+    constexpr int BN = 128, BK = 16, RT = R / 16, ZQ = BK * R / 4;
+    __shared__ __align__(16) float xs[2][BK][BN + 16]; // padded as in k_sketch_m
+    __shared__ __align__(16) float zs[2][BK][R + 16];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int li = lane & 15, lk = lane >> 4;
     const int64_t j0 = (int64_t)blockIdx.x * BN;
     const int64_t rb = (int64_t)blockIdx.y * rows;
     const int64_t re = M < rb + rows ? M : rb + rows;
@@ -516,12 +506,12 @@ __global__ __launch_bounds__(256) void k_sketch_t_v(const float *__restrict__ X,
             *reinterpret_cast<mf32x4_t *>(&zs[b][c][4 * u]) = zr;
         }
     };
-    float acc[8][RB];
+    mf32x4_t acc[2][RT];
 #pragma unroll
-    for (int a = 0; a < 8; ++a)
+    for (int h = 0; h < 2; ++h)
 #pragma unroll
-        for (int b = 0; b < RB; ++b)
-            acc[a][b] = 0.0f;
+        for (int t = 0; t < RT; ++t)
+            acc[h][t] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
     if (rb < re) {
         gload(rb);
         sstore(0);
@@ -532,24 +522,19 @@ __global__ __launch_bounds__(256) void k_sketch_t_v(const float *__restrict__ X,
         const bool more = r0 + BK < re;
         if (more)
             gload(r0 + BK); // in flight while this chunk is multiplied
-#pragma unroll 2
-        for (int i = 0; i < BK; ++i) {
-            const mf32x4_t x0 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][i][8 * tx]);
-            const mf32x4_t x1 = *reinterpret_cast<const mf32x4_t *>(&xs[buf][i][8 * tx + 4]);
-            float zv[RB];
-            if constexpr (RB == 4) {
-                const mf32x4_t z = *reinterpret_cast<const mf32x4_t *>(&zs[buf][i][RB * ty]);
-                zv[0] = z[0]; zv[1] = z[1]; zv[2] = z[2]; zv[3] = z[3];
-            } else {
-                const sf32x2_t z = *reinterpret_cast<const sf32x2_t *>(&zs[buf][i][RB * ty]);
-                zv[0] = z[0]; zv[1] = z[1];
+#pragma unroll
+        for (int kk = 0; kk < BK; kk += 4) {
+            float zb[RT];
+#pragma unroll
+            for (int t = 0; t < RT; ++t)
+                zb[t] = zs[buf][kk + lk][16 * t + li];
+#pragma unroll
+            for (int h = 0; h < 2; ++h) {
+                const float a = xs[buf][kk + lk][32 * w + 16 * h + li];
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    acc[h][t] = __builtin_amdgcn_mfma_f32_16x16x4f32(a, zb[t], acc[h][t], 0, 0, 0);
             }
-            const float xv[8] = {x0[0], x0[1], x0[2], x0[3], x1[0], x1[1], x1[2], x1[3]};
-#pragma unroll
-            for (int a = 0; a < 8; ++a)
-#pragma unroll
-                for (int b = 0; b < RB; ++b)
-                    acc[a][b] += xv[a] * zv[b];
         }
         if (more)
             sstore(buf ^ 1);
@@ -557,17 +542,15 @@ __global__ __launch_bounds__(256) void k_sketch_t_v(const float *__restrict__ X,
         buf ^= 1;
     }
 #pragma unroll
-    for (int a = 0; a < 8; ++a) {
-        const int64_t j = j0 + 8 * tx + a;
-        if (j < N) {
-            float *wr = W + j * R + RB * ty;
-            if constexpr (RB == 4)
-                *reinterpret_cast<mf32x4_t *>(wr) =
-                    mf32x4_t{acc[a][0] * s, acc[a][1] * s, acc[a][2] * s, acc[a][3] * s};
-            else
-                *reinterpret_cast<sf32x2_t *>(wr) = sf32x2_t{acc[a][0] * s, acc[a][1] * s};
+    for (int h = 0; h < 2; ++h)
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const int64_t j = j0 + 32 * w + 16 * h + 4 * lk + i;
+            if (j < N)
+#pragma unroll
+                for (int t = 0; t < RT; ++t)
+                    W[j * R + 16 * t + li] = acc[h][t][i] * s;
         }
-    }
 }
 
 // G_y = Y[rows of slice y]^T Y[rows of slice y] in FP64: 64-row tiles staged in
@@ -971,10 +954,10 @@ void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const floa
                          ((uintptr_t)Y) % 16 == 0;
     if (aligned) {
         if (r == 32)
-            hipLaunchKernelGGL(k_sketch_v<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
+            hipLaunchKernelGGL(k_sketch_m<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
                                Om, Y);
         else
-            hipLaunchKernelGGL(k_sketch_v<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
+            hipLaunchKernelGGL(k_sketch_m<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
                                Om, Y);
         return;
     }
@@ -995,10 +978,10 @@ void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const fl
     if (aligned) {
         const dim3 g(ucdiv(N, 128), (unsigned)P.st);
         if (r == 32)
-            hipLaunchKernelGGL(k_sketch_t_v<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+            hipLaunchKernelGGL(k_sketch_t_m<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
                                dst);
         else
-            hipLaunchKernelGGL(k_sketch_t_v<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
+            hipLaunchKernelGGL(k_sketch_t_m<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
                                dst);
     } else {
         const dim3 g(ucdiv(N, 64), (unsigned)P.st);
