@@ -35,14 +35,88 @@ __device__ inline __bf16 to_bf16(__bf16 x) { return x; }
 // C = A B (+ bias, relu, mask) with bf16 operands and FP32 accumulation.
 // A(i, k) = A[i*a_r + k*a_c] (M x Kd), B(k, j) = B[k*b_r + j*b_c] (Kd x N);
 // strides express the transposes of the backward pass.  FP32 operands are
-// rounded to bf16 as they are loaded.  One wave computes a 16 x 16 tile, a
-// workgroup of four waves a 32 x 32 tile.  blockIdx.z splits the k range into
-// chunks of `kchunk` (a multiple of 32):
+// rounded to bf16 as they are loaded.  A workgroup computes a 64 x 64 tile of
+// C, each of its four waves a 32 x 32 quarter as 2 x 2 matrix-core tiles
+// (v_mfma_f32_16x16x32_bf16).  Per 32-wide k chunk both operands are staged
+// in LDS in k-contiguous bf16 rows, read from global memory along whichever
+// index is contiguous (16-byte loads when the rows are aligned), so every
+// lane then takes its eight k values of A and of B with one 16-byte LDS
+// read.  blockIdx.z splits the k range into chunks of `kchunk` (a multiple
+// of 32):
 //   - split == 0: C(i, j) at Cf[i*c_r + j*c_c] (FP32, + bias, + skip(i, j) =
 //     skip[i*s_r + j], relu, mask, optionally added to the old value) or Cb
 //     (bf16); mask zeroes C(i, j) where the stored activation mask[i*m_r + j]
 //     is not positive;
 //   - split != 0: raw partial sums to part[z*M*N + i*N + j].
+constexpr int kGemmTile = 64, kGemmK = 32, kGemmLdk = kGemmK + 8; // LDS row: 80 bytes
+
+// Rows o0..o0+63 (outer index, stride so; bound no) by k0..k0+31 (stride sk;
+// bound kend) of an operand into dst[o][k] as bf16, zero outside.
+template <typename T>
+__device__ inline void gemm_stage(const T *__restrict__ X, int64_t so, int64_t sk, int64_t o0,
+                                  int64_t no, int64_t k0, int64_t kend,
+                                  __bf16 (*dst)[kGemmLdk], int tid)
+{
+    if (sk == 1) {
+        // k contiguous: thread -> outer row tid / 4, eight k from 8 (tid % 4)
+        const int o = tid >> 2, seg = tid & 3;
+        const int64_t og = o0 + o, kg = k0 + 8 * seg;
+        bf16x8_t v;
+        const T *src = X + (og < no ? og : 0) * so + kg;
+        if (og < no && kg + 8 <= kend && ((uintptr_t)src & 15) == 0) {
+            if constexpr (sizeof(T) == 2) {
+                v = *reinterpret_cast<const bf16x8_t *>(src);
+            } else {
+                const mf32x4_t lo = *reinterpret_cast<const mf32x4_t *>(src);
+                const mf32x4_t hi = *reinterpret_cast<const mf32x4_t *>(src + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = to_bf16(lo[e]);
+                    v[4 + e] = to_bf16(hi[e]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                v[e] = (og < no && kg + e < kend) ? to_bf16(src[e]) : (__bf16)0.0f;
+        }
+        *reinterpret_cast<bf16x8_t *>(&dst[o][8 * seg]) = v;
+    } else if (so == 1) {
+        // outer index contiguous: thread -> k row tid / 8, eight outer
+        // indices from 8 (tid % 8), written transposed
+        const int kk = tid >> 3, seg = tid & 7;
+        const int64_t kg = k0 + kk, og = o0 + 8 * seg;
+        const T *src = X + (kg < kend ? kg : 0) * sk + og;
+        bf16x8_t v;
+        if (kg < kend && og + 8 <= no && ((uintptr_t)src & 15) == 0) {
+            if constexpr (sizeof(T) == 2) {
+                v = *reinterpret_cast<const bf16x8_t *>(src);
+            } else {
+                const mf32x4_t lo = *reinterpret_cast<const mf32x4_t *>(src);
+                const mf32x4_t hi = *reinterpret_cast<const mf32x4_t *>(src + 4);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    v[e] = to_bf16(lo[e]);
+                    v[4 + e] = to_bf16(hi[e]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 8; ++e)
+                v[e] = (kg < kend && og + e < no) ? to_bf16(src[e]) : (__bf16)0.0f;
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e)
+            dst[8 * seg + e][kk] = v[e];
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int idx = tid + 256 * e, o = idx >> 5, kk = idx & 31;
+            const int64_t og = o0 + o, kg = k0 + kk;
+            dst[o][kk] = (og < no && kg < kend) ? to_bf16(X[og * so + kg * sk]) : (__bf16)0.0f;
+        }
+    }
+}
 
 template <typename TA, typename TB>
 __global__ __launch_bounds__(256) void k_gemm_bf16(
@@ -52,58 +126,72 @@ __global__ __launch_bounds__(256) void k_gemm_bf16(
     int64_t s_r, float *__restrict__ Cf, __bf16 *__restrict__ Cb, int64_t c_r, int64_t c_c,
     int accumulate, int split, float *__restrict__ part)
 {
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    const int64_t i0 = (int64_t)blockIdx.y * 32 + (w >> 1) * 16;
-    const int64_t j0 = (int64_t)blockIdx.x * 32 + (w & 1) * 16;
-    const int64_t ia = i0 + (lane & 15); // row of A this lane feeds
-    const int64_t jb = j0 + (lane & 15); // column of B this lane feeds
-    const int kq = (lane >> 4) * 8;      // its 8 consecutive k within a 32-chunk
+    __shared__ __align__(16) __bf16 As[kGemmTile][kGemmLdk];
+    __shared__ __align__(16) __bf16 Bs[kGemmTile][kGemmLdk];
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int64_t ib = (int64_t)blockIdx.y * kGemmTile, jb = (int64_t)blockIdx.x * kGemmTile;
+    const int wi = (w >> 1) * 32, wj = (w & 1) * 32; // the wave's quarter of the tile
+    const int li = lane & 15, kq = (lane >> 4) * 8;  // operand row/column, its 8 k
     const int64_t kbeg = (int64_t)blockIdx.z * kchunk;
     const int64_t kend = std::min<int64_t>(Kd, kbeg + kchunk);
-    const bool rowa = ia < M, colb = jb < N;
-    const TA *ap = A + (rowa ? ia : 0) * a_r;
-    const TB *bp = B + (colb ? jb : 0) * b_c;
-    mf32x4_t acc = {0.f, 0.f, 0.f, 0.f};
-    for (int64_t k0 = kbeg; k0 < kend; k0 += 32) {
-        bf16x8_t av, bv;
+    mf32x4_t acc[2][2];
 #pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            const int64_t k = k0 + kq + e;
-            const bool kin = k < kend;
-            av[e] = (rowa && kin) ? to_bf16(ap[k * a_c]) : (__bf16)0.0f;
-            bv[e] = (colb && kin) ? to_bf16(bp[k * b_r]) : (__bf16)0.0f;
-        }
-        acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av, bv, acc, 0, 0, 0);
-    }
-    // lane holds C(i0 + (lane/16)*4 + e, j0 + lane%16), e = 0..3
-    const int64_t j = j0 + (lane & 15);
-    if (j >= N)
-        return;
+    for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int e = 0; e < 4; ++e) {
-        const int64_t i = i0 + (lane >> 4) * 4 + e;
-        if (i >= M)
-            continue;
-        float v = acc[e];
-        if (split) {
-            part[(int64_t)blockIdx.z * M * N + i * N + j] = v;
-            continue;
+        for (int b = 0; b < 2; ++b)
+            acc[a][b] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+    for (int64_t k0 = kbeg; k0 < kend; k0 += kGemmK) {
+        __syncthreads(); // the previous chunk's operand reads are done
+        gemm_stage<TA>(A, a_r, a_c, ib, M, k0, kend, As, tid);
+        gemm_stage<TB>(B, b_c, b_r, jb, N, k0, kend, Bs, tid); // Bs[j][k] = B(k, j)
+        __syncthreads();
+        bf16x8_t av[2], bv[2];
+#pragma unroll
+        for (int t = 0; t < 2; ++t) {
+            av[t] = *reinterpret_cast<const bf16x8_t *>(&As[wi + 16 * t + li][kq]);
+            bv[t] = *reinterpret_cast<const bf16x8_t *>(&Bs[wj + 16 * t + li][kq]);
         }
-        if (bias)
-            v += bias[j];
-        if (skip)
-            v += skip[i * s_r + j];
-        if (relu && !(v > 0.0f))
-            v = 0.0f;
-        if (mask && !((float)mask[i * m_r + j] > 0.0f))
-            v = 0.0f;
-        if (Cf) {
-            float *dst = Cf + i * c_r + j * c_c;
-            *dst = accumulate ? *dst + v : v;
-        } else {
-            Cb[i * c_r + j * c_c] = to_bf16(v);
-        }
+#pragma unroll
+        for (int a = 0; a < 2; ++a)
+#pragma unroll
+            for (int b = 0; b < 2; ++b)
+                acc[a][b] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(av[a], bv[b], acc[a][b], 0, 0,
+                                                                     0);
     }
+    // lane holds C(i0 + (lane/16)*4 + e, j0 + lane%16), e = 0..3, per tile
+#pragma unroll
+    for (int ta = 0; ta < 2; ++ta)
+#pragma unroll
+        for (int tb = 0; tb < 2; ++tb) {
+            const int64_t i0 = ib + wi + 16 * ta, j = jb + wj + 16 * tb + li;
+            if (j >= N)
+                continue;
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                const int64_t i = i0 + (lane >> 4) * 4 + e;
+                if (i >= M)
+                    continue;
+                float v = acc[ta][tb][e];
+                if (split) {
+                    part[(int64_t)blockIdx.z * M * N + i * N + j] = v;
+                    continue;
+                }
+                if (bias)
+                    v += bias[j];
+                if (skip)
+                    v += skip[i * s_r + j];
+                if (relu && !(v > 0.0f))
+                    v = 0.0f;
+                if (mask && !((float)mask[i * m_r + j] > 0.0f))
+                    v = 0.0f;
+                if (Cf) {
+                    float *dst = Cf + i * c_r + j * c_c;
+                    *dst = accumulate ? *dst + v : v;
+                } else {
+                    Cb[i * c_r + j * c_c] = to_bf16(v);
+                }
+            }
+        }
 }
 
 // C(i, j) = sum_z part[z][i][j] in increasing z (FP32, row-major M x N out
@@ -867,7 +955,7 @@ void gemm_launch(const TA *A, int64_t a_r, int64_t a_c, const TB *B, int64_t b_r
 {
     // Split the k range when the output tiles alone cannot fill the chip
     // (weight gradients: small outputs, k = all rows).
-    const int64_t tiles = (int64_t)ucdiv(M, 32) * ucdiv(N, 32);
+    const int64_t tiles = (int64_t)ucdiv(M, kGemmTile) * ucdiv(N, kGemmTile);
     int nz = 1;
     if (part && tiles < 1024 && Kd >= 4096) {
         nz = (int)std::min<int64_t>(kMaxSplit, std::max<int64_t>(1, 2048 / tiles));
@@ -875,7 +963,7 @@ void gemm_launch(const TA *A, int64_t a_r, int64_t a_c, const TB *B, int64_t b_r
     }
     const int64_t kchunk = ((Kd + nz - 1) / nz + 31) / 32 * 32;
     nz = (int)((Kd + kchunk - 1) / kchunk);
-    dim3 g(ucdiv(N, 32), ucdiv(M, 32), nz);
+    dim3 g(ucdiv(N, kGemmTile), ucdiv(M, kGemmTile), nz);
     hipLaunchKernelGGL((k_gemm_bf16<TA, TB>), g, dim3(256), 0, s, A, a_r, a_c, B, b_r, b_c, M, N,
                        Kd, kchunk, bias, relu, mask, m_r, skip, s_r, Cf, Cb, c_r, c_c, 0,
                        nz > 1 ? 1 : 0, part);
