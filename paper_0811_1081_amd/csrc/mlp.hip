@@ -641,15 +641,19 @@ __global__ __launch_bounds__(256) void k_sketch_t_m(const float *__restrict__ X,
         }
 }
 
-// G_y = Y[rows of slice y]^T Y[rows of slice y] in FP64: 64-row tiles staged in
-// LDS, each of the 256 threads owns an (R/16) x (R/16) block of G_y.
+// G_y = Y[rows of slice y]^T Y[rows of slice y] in FP64 (products of FP32
+// values are exact in FP64; only the order of the sums rounds).  64-row tiles
+// are staged in LDS as doubles; four groups of 256 threads take rows i = g,
+// g + 4, ... of each tile, each thread an (R/16) x (R/16) block of G_y, and
+// the groups' blocks are added in group order at the end.
 template <int R>
-__global__ __launch_bounds__(256) void k_gram(const float *__restrict__ Y, int64_t M,
-                                              int64_t rows, double *__restrict__ part)
+__global__ __launch_bounds__(1024) void k_gram(const float *__restrict__ Y, int64_t M,
+                                               int64_t rows, double *__restrict__ part)
 {
-    constexpr int TB = R / 16;
-    __shared__ float ys[64][R + 1];
-    const int tid = threadIdx.x, ta = tid & 15, tb = tid >> 4;
+    constexpr int TB = R / 16, NG = 4;
+    __shared__ __align__(16) double ys[64][R + 2];
+    __shared__ double accs[NG - 1][R * R];
+    const int tid = threadIdx.x, g = tid >> 8, t = tid & 255, ta = t & 15, tb = t >> 4;
     const int64_t rb = (int64_t)blockIdx.x * rows;
     const int64_t re = M < rb + rows ? M : rb + rows;
     double acc[TB][TB];
@@ -660,20 +664,21 @@ __global__ __launch_bounds__(256) void k_gram(const float *__restrict__ Y, int64
             acc[a][b] = 0.0;
     for (int64_t r0 = rb; r0 < re; r0 += 64) {
         __syncthreads();
-        for (int e = tid; e < 64 * R; e += 256) {
+        for (int e = tid; e < 64 * R; e += 1024) {
             const int i = e / R, c = e % R;
             const int64_t m = r0 + i;
-            ys[i][c] = m < re ? Y[m * R + c] : 0.0f;
+            ys[i][c] = m < re ? (double)Y[m * R + c] : 0.0;
         }
         __syncthreads();
-        for (int i = 0; i < 64; ++i) {
+#pragma unroll 4
+        for (int i = g; i < 64; i += NG) {
             double ya[TB], yb[TB];
 #pragma unroll
             for (int a = 0; a < TB; ++a)
-                ya[a] = (double)ys[i][TB * ta + a];
+                ya[a] = ys[i][TB * ta + a];
 #pragma unroll
             for (int b = 0; b < TB; ++b)
-                yb[b] = (double)ys[i][TB * tb + b];
+                yb[b] = ys[i][TB * tb + b];
 #pragma unroll
             for (int a = 0; a < TB; ++a)
 #pragma unroll
@@ -681,87 +686,243 @@ __global__ __launch_bounds__(256) void k_gram(const float *__restrict__ Y, int64
                     acc[a][b] += ya[a] * yb[b];
         }
     }
-    double *g = part + (int64_t)blockIdx.x * R * R;
+    if (g > 0)
 #pragma unroll
-    for (int a = 0; a < TB; ++a)
+        for (int a = 0; a < TB; ++a)
 #pragma unroll
-        for (int b = 0; b < TB; ++b)
-            g[(TB * ta + a) * R + TB * tb + b] = acc[a][b];
+            for (int b = 0; b < TB; ++b)
+                accs[g - 1][(TB * ta + a) * R + TB * tb + b] = acc[a][b];
+    __syncthreads();
+    if (g == 0) {
+        double *out = part + (int64_t)blockIdx.x * R * R;
+#pragma unroll
+        for (int a = 0; a < TB; ++a)
+#pragma unroll
+            for (int b = 0; b < TB; ++b) {
+                const int idx = (TB * ta + a) * R + TB * tb + b;
+                double v = acc[a][b];
+#pragma unroll
+                for (int h = 0; h < NG - 1; ++h)
+                    v += accs[h][idx];
+                out[idx] = v;
+            }
+    }
 }
 
-// Z = Y QS (row-major, FP64 sums): 64-row tiles, QS (R x R) staged in LDS.
+// Z = Y QS (row-major, FP64 sums): 64-row tiles, QS (R x R) staged in LDS;
+// each thread a 4-row by (R/16)-column block of Z.
 template <int R>
 __global__ __launch_bounds__(256) void k_whiten_apply(const float *__restrict__ Y, int64_t M,
                                                       const double *__restrict__ QS,
                                                       float *__restrict__ Z)
 {
-    __shared__ double qs[R][R + 1];
-    __shared__ float ys[64][R + 1];
-    const int tid = threadIdx.x;
+    constexpr int TC = R / 16;
+    __shared__ double qs[R][R];
+    __shared__ double ys[64][R + 1];
+    const int tid = threadIdx.x, tc = tid & 15, tr = tid >> 4; // columns tc + 16 c, rows 4 tr + a
     const int64_t m0 = (int64_t)blockIdx.x * 64;
     for (int e = tid; e < R * R; e += 256)
         qs[e / R][e % R] = QS[e];
     for (int e = tid; e < 64 * R; e += 256) {
         const int i = e / R, c = e % R;
         const int64_t m = m0 + i;
-        ys[i][c] = m < M ? Y[m * R + c] : 0.0f;
+        ys[i][c] = m < M ? (double)Y[m * R + c] : 0.0;
     }
     __syncthreads();
-    for (int e = tid; e < 64 * R; e += 256) {
-        const int i = e / R, b = e % R;
-        const int64_t m = m0 + i;
-        if (m >= M)
-            continue;
-        double z = 0.0;
-        for (int r = 0; r < R; ++r)
-            z += (double)ys[i][r] * qs[r][b];
-        Z[m * R + b] = (float)z;
+    double z[4][TC];
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+            z[a][c] = 0.0;
+    for (int r = 0; r < R; ++r) {
+        double ya[4], qb[TC];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+            ya[a] = ys[4 * tr + a][r];
+#pragma unroll
+        for (int c = 0; c < TC; ++c)
+            qb[c] = qs[r][tc + 16 * c];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+                z[a][c] += ya[a] * qb[c];
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a) {
+        const int64_t m = m0 + 4 * tr + a;
+        if (m < M)
+#pragma unroll
+            for (int c = 0; c < TC; ++c)
+                Z[m * R + tc + 16 * c] = (float)z[a][c];
     }
 }
 
-// Eigen-decomposition of the sketch's Gram matrix by one workgroup of 1024
-// threads (R = 32 or 64): G = sum of the nslice partials from k_gram (fixed
-// order, FP64), parallel cyclic Jacobi (round-robin pairing: R/2 disjoint
-// rotations per round, applied to both sides of G in one step, R-1 rounds per
-// sweep; rotation of Golub & Van Loan's symmetric Schur step) until the
-// off-diagonal mass is below 1e-28 of |G|_F^2; eigenpairs by decreasing g,
-// each eigenvector's largest entry made positive.  Writes QS = sqrt(M) Q[:, perm] diag(g)^(-1/2) (R x R, row-major;
-// zero columns where g is not positive and finite), g, and the flag.
-template <int R>
-__global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ part, int nslice,
-                                                     int64_t M, double *__restrict__ QS,
+// G = the nslice partials from k_gram summed (FP64, fixed order), written
+// over the first partial.  A workgroup of 256 threads owns 64 entries; wave w
+// sums slices w, w + 4, w + 8, ... in increasing order and the four wave sums
+// are added in wave order.  Each entry's slices are read before the barrier
+// that precedes its write.
+__global__ __launch_bounds__(256) void k_gram_sum(double *__restrict__ part, int nslice, int n)
+{
+    __shared__ double red[3][64];
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    const int idx = blockIdx.x * 64 + lane;
+    double acc = 0.0;
+    if (idx < n) {
+#pragma unroll 8
+        for (int y = w; y < nslice; y += 4)
+            acc += part[(int64_t)y * n + idx];
+    }
+    if (w > 0)
+        red[w - 1][lane] = acc;
+    __syncthreads();
+    if (w == 0 && idx < n)
+        part[idx] = ((acc + red[0][lane]) + red[1][lane]) + red[2][lane];
+}
+
+// 1/sqrt(x) for x in [1, 2]: the hardware estimate refined by two Newton
+// steps y <- y + y (1/2 - (x/2) y^2).
+__device__ inline double newton_rsq(double x)
+{
+    double y = __builtin_amdgcn_rsq(x);
+    const double h = 0.5 * x;
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    y = fma(y, fma(-h * y, y, 0.5), y);
+    return y;
+}
+
+// 1/x for x in [1, 3]: the hardware estimate refined by two Newton steps
+// y <- y + y (1 - x y).
+__device__ inline double newton_rcp(double x)
+{
+    double y = __builtin_amdgcn_rcp(x);
+    y = fma(y, fma(-x, y, 1.0), y);
+    y = fma(y, fma(-x, y, 1.0), y);
+    return y;
+}
+
+// Rotation (c, s) that zeroes the (p, q) entry of a symmetric 2 x 2 block
+// (Golub & Van Loan's symmetric Schur step): with d = a_qq - a_pp and
+// b = 2 a_pq, t = sign(d) b / (|d| + sqrt(d^2 + b^2)) is the smaller root of
+// t^2 + 2 (d / b) t - 1 = 0, c = 1 / sqrt(1 + t^2), s = t c.  d and b are
+// first scaled by about 1 / max(|d|, |b|) (t does not depend on the scale),
+// so every square root and reciprocal below has its argument in [1, 3].
+// The identity when a_pq = 0 or the block is below the normal range.
+__device__ inline void jacobi_rotation(double app, double aqq, double apq, double &c, double &s)
+{
+    const double d = aqq - app, b = 2.0 * apq;
+    const double m = fmax(fabs(d), fabs(b));
+    const double im = __builtin_amdgcn_rcp(m);
+    const double ds = d * im, bs = b * im;
+    const double x = fma(ds, ds, bs * bs);
+    const double r = x * newton_rsq(x);
+    const double t = (ds >= 0.0 ? bs : -bs) * newton_rcp(fabs(ds) + r);
+    const double cc = newton_rsq(fma(t, t, 1.0));
+    const bool rot = apq != 0.0 && m >= 4.0 * DBL_MIN;
+    c = rot ? cc : 1.0;
+    s = rot ? t * cc : 0.0;
+}
+
+// Eigen-decomposition of the sketch's Gram matrix G (R x R, FP64, summed by
+// k_gram_sum) by one workgroup of 256 threads (R = 32 or 64): parallel cyclic
+// Jacobi, R/2 disjoint rotations per round applied to both sides of G in one
+// step, R-1 rounds per sweep in round-robin order (index 0 fixed, the others
+// advancing one place per round), until the off-diagonal mass is below 1e-28
+// of |G|_F^2; eigenpairs by decreasing g, each eigenvector's largest entry
+// made positive.  Writes QS = sqrt(M) Q[:, perm] diag(g)^(-1/2) (R x R,
+// row-major; zero columns where g is not positive and finite), g, and the
+// flag.
+// G and the columns of Q are kept in round-robin position order: rotation i
+// of every round acts on positions i and R-1-i, and the results are written,
+// double-buffered, to the places the next round's pairing gives them
+// (position u -> u - 1, position 1 -> R - 1, 0 fixed), so every LDS address
+// is the same in every round; after the R-1 rounds of a sweep the positions
+// are the indices again.  Every lane forms the rotation of pair
+// (lane mod R/2) itself, so a round has a single barrier.
+template <int R, int NT>
+__global__ __launch_bounds__(NT) void k_whiten_eig(const double *__restrict__ gsum, int64_t M,
+                                                     double *__restrict__ QS,
                                                      double *__restrict__ gout,
                                                      int32_t *__restrict__ flag)
 {
-    constexpr int NT = 1024, EPT = R * R / NT; // Gram entries per thread (1 or 4)
-    __shared__ double G[R][R + 1];
-    __shared__ double Q[R][R + 1];
-    __shared__ double cs[R / 2], sn[R / 2];
-    __shared__ int pa[R / 2], pb[R / 2];
+    constexpr int NP = R / 2, EPT = R * R / NT; // Gram entries per thread
+    constexpr int GB = NP * NP / NT, QB = R * NP / NT; // 2 x 2 blocks of G, Q row pairs per thread
+    __shared__ double Gb[2][R][R + 1];
+    __shared__ double Qb[2][R][R + 1];
     __shared__ double eig[R];
     __shared__ int perm[R];
     __shared__ double scale[R];
-    __shared__ double offsum[2];
     __shared__ double red[2][NT / 64];
-    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
+    const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6, my = lane % NP;
 #pragma unroll
     for (int e = 0; e < EPT; ++e) {
         const int idx = tid + e * NT, a = idx / R, b = idx % R;
-        double acc = 0.0;
-        for (int y = 0; y < nslice; ++y)
-            acc += part[(int64_t)y * R * R + idx];
-        G[a][b] = acc;
-        Q[a][b] = a == b ? 1.0 : 0.0;
+        Gb[0][a][b] = gsum[idx];
+        Qb[0][a][b] = a == b ? 1.0 : 0.0;
     }
+    // this lane's pair (positions p, q), the next round's places of positions
+    auto next = [](int u) { return u == 0 ? 0 : (u == 1 ? R - 1 : u - 1); };
+    const int p = my, q = R - 1 - my, np_ = next(p), nq = next(q);
+    int b1[GB];
+#pragma unroll
+    for (int k = 0; k < GB; ++k)
+        b1[k] = (tid + k * NT) / NP; // row pair of block k (column pair: my)
+    // one round: reads from (Gc, Qc), writes to (Gn, Qn), then the barrier
+    auto round_step = [&](const double(*Gc)[R + 1], double(*Gn)[R + 1],
+                          const double(*Qc)[R + 1], double(*Qn)[R + 1])
+        __attribute__((always_inline)) {
+        const double app = Gc[p][p], aqq = Gc[q][q], apq = Gc[p][q];
+        double g[GB][4], qv[QB][2];
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            const int p1 = b1[k], q1 = R - 1 - b1[k];
+            g[k][0] = Gc[p1][p];
+            g[k][1] = Gc[p1][q];
+            g[k][2] = Gc[q1][p];
+            g[k][3] = Gc[q1][q];
+        }
+#pragma unroll
+        for (int k = 0; k < QB; ++k) {
+            const int a = (tid + k * NT) / NP;
+            qv[k][0] = Qc[a][p];
+            qv[k][1] = Qc[a][q];
+        }
+        double c, sv;
+        jacobi_rotation(app, aqq, apq, c, sv);
+#pragma unroll
+        for (int k = 0; k < GB; ++k) {
+            // G <- J^T G J on the 2 x 2 block of row pair b1 and column pair
+            // my: the pairs are disjoint, so it depends on rotations b1 and
+            // my only (columns first, then rows)
+            const double c1 = __shfl(c, b1[k], 64), s1 = __shfl(sv, b1[k], 64);
+            const int p1 = next(b1[k]), q1 = next(R - 1 - b1[k]);
+            const double h00 = c * g[k][0] - sv * g[k][1], h01 = sv * g[k][0] + c * g[k][1];
+            const double h10 = c * g[k][2] - sv * g[k][3], h11 = sv * g[k][2] + c * g[k][3];
+            Gn[p1][np_] = c1 * h00 - s1 * h10;
+            Gn[q1][np_] = s1 * h00 + c1 * h10;
+            Gn[p1][nq] = c1 * h01 - s1 * h11;
+            Gn[q1][nq] = s1 * h01 + c1 * h11;
+        }
+#pragma unroll
+        for (int k = 0; k < QB; ++k) { // Q <- Q J (row a, pair my)
+            const int a = (tid + k * NT) / NP;
+            Qn[a][np_] = c * qv[k][0] - sv * qv[k][1];
+            Qn[a][nq] = sv * qv[k][0] + c * qv[k][1];
+        }
+        __syncthreads();
+    };
     __syncthreads();
+    int cur = 0;
     for (int sweep = 0; sweep < 60; ++sweep) {
         {   // off-diagonal and total mass: per-thread entries, wave sums, the
-            // waves in order (the same on every run)
+            // waves in order (the same on every run and in every thread)
             double off = 0.0, fro = 0.0;
 #pragma unroll
             for (int e = 0; e < EPT; ++e) {
                 const int idx = tid + e * NT, a = idx / R, b = idx % R;
-                const double v = G[a][b];
+                const double v = Gb[cur][a][b];
                 fro += v * v;
                 off += a != b ? v * v : 0.0;
             }
@@ -775,72 +936,34 @@ __global__ __launch_bounds__(1024) void k_whiten_eig(const double *__restrict__ 
                 red[1][w] = fro;
             }
             __syncthreads();
-            if (tid == 0) {
-                double so = 0.0, sf = 0.0;
-                for (int i = 0; i < NT / 64; ++i) {
-                    so += red[0][i];
-                    sf += red[1][i];
-                }
-                offsum[0] = so;
-                offsum[1] = sf;
+            double so = 0.0, sf = 0.0;
+            for (int i = 0; i < NT / 64; ++i) {
+                so += red[0][i];
+                sf += red[1][i];
             }
+            if (!(so > 1e-28 * sf))
+                break;
         }
-        __syncthreads();
-        if (!(offsum[0] > 1e-28 * offsum[1]))
-            break;
-        for (int round = 0; round < R - 1; ++round) {
-            if (tid < R / 2) {
-                // position 0 holds index 0; positions 1..R-1 rotate
-                const int i = tid;
-                const int pos_a = i, pos_b = R - 1 - i;
-                int p = pos_a == 0 ? 0 : 1 + (pos_a - 1 + round) % (R - 1);
-                int q = 1 + (pos_b - 1 + round) % (R - 1);
-                if (p > q) {
-                    const int tmp = p;
-                    p = q;
-                    q = tmp;
-                }
-                pa[i] = p;
-                pb[i] = q;
-                const double apq = G[p][q];
-                double c = 1.0, sv = 0.0;
-                if (apq != 0.0) {
-                    const double tau = (G[q][q] - G[p][p]) / (2.0 * apq);
-                    const double t =
-                        (tau >= 0.0 ? 1.0 : -1.0) / (fabs(tau) + sqrt(1.0 + tau * tau));
-                    c = 1.0 / sqrt(1.0 + t * t);
-                    sv = t * c;
-                }
-                cs[i] = c;
-                sn[i] = sv;
+        // R - 1 rounds alternating between the two buffers; each round is
+        // written out for both directions so that every LDS address is a
+        // fixed offset from a loop-invariant base.
+        if (cur == 0) {
+            for (int round = 0; round < R - 2; round += 2) {
+                round_step(Gb[0], Gb[1], Qb[0], Qb[1]);
+                round_step(Gb[1], Gb[0], Qb[1], Qb[0]);
             }
-            __syncthreads();
-            // G <- J^T G J in one step: the pairs are disjoint, so the 2 x 2
-            // block of row pair b1 and column pair b2 depends on rotations b1
-            // and b2 only (columns first, then rows, as two sweeps would)
-            for (int e = tid; e < (R / 2) * (R / 2); e += NT) {
-                const int b1 = e / (R / 2), b2 = e % (R / 2);
-                const int p1 = pa[b1], q1 = pb[b1], p2 = pa[b2], q2 = pb[b2];
-                const double c1 = cs[b1], s1 = sn[b1], c2 = cs[b2], s2 = sn[b2];
-                const double g00 = G[p1][p2], g01 = G[p1][q2], g10 = G[q1][p2], g11 = G[q1][q2];
-                const double h00 = c2 * g00 - s2 * g01, h01 = s2 * g00 + c2 * g01;
-                const double h10 = c2 * g10 - s2 * g11, h11 = s2 * g10 + c2 * g11;
-                G[p1][p2] = c1 * h00 - s1 * h10;
-                G[q1][p2] = s1 * h00 + c1 * h10;
-                G[p1][q2] = c1 * h01 - s1 * h11;
-                G[q1][q2] = s1 * h01 + c1 * h11;
+            round_step(Gb[0], Gb[1], Qb[0], Qb[1]);
+        } else {
+            for (int round = 0; round < R - 2; round += 2) {
+                round_step(Gb[1], Gb[0], Qb[1], Qb[0]);
+                round_step(Gb[0], Gb[1], Qb[0], Qb[1]);
             }
-            for (int e = tid; e < R * (R / 2); e += NT) { // Q <- Q J (row a, pair b)
-                const int a = e / (R / 2), b = e % (R / 2);
-                const int p = pa[b], q = pb[b];
-                const double c = cs[b], sv = sn[b];
-                const double qp = Q[a][p], qq = Q[a][q];
-                Q[a][p] = c * qp - sv * qq;
-                Q[a][q] = sv * qp + c * qq;
-            }
-            __syncthreads();
+            round_step(Gb[1], Gb[0], Qb[1], Qb[0]);
         }
+        cur ^= 1;
     }
+    const double(*G)[R + 1] = Gb[cur];
+    const double(*Q)[R + 1] = Qb[cur];
     // eigenvalues by decreasing g (rank of each, ties by index), then per
     // column the sign that makes its largest entry positive (first maximum in
     // row order) and the whitening scale
@@ -1085,6 +1208,8 @@ void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const fl
                            (int)P.st, N, (int64_t)r, W, (int64_t)r, (int64_t)1);
 }
 
+constexpr int kEig64Threads = 256;
+
 void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_t *flag,
                    unsigned char *ws, hipStream_t s)
 {
@@ -1092,14 +1217,20 @@ void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_
     double *gp = reinterpret_cast<double *>(ws + P.off_gpart);
     double *qs = reinterpret_cast<double *>(ws + P.off_qs);
     if (r == 32) {
-        hipLaunchKernelGGL(k_gram<32>, dim3((unsigned)P.sg), dim3(256), 0, s, Y, M, P.rows_g, gp);
-        hipLaunchKernelGGL(k_whiten_eig<32>, dim3(1), dim3(1024), 0, s, gp, (int)P.sg, M, qs, g,
+        hipLaunchKernelGGL(k_gram<32>, dim3((unsigned)P.sg), dim3(1024), 0, s, Y, M, P.rows_g,
+                           gp);
+        hipLaunchKernelGGL(k_gram_sum, dim3(ucdiv(32 * 32, 64)), dim3(256), 0, s, gp, (int)P.sg,
+                           32 * 32);
+        hipLaunchKernelGGL((k_whiten_eig<32, 256>), dim3(1), dim3(256), 0, s, gp, M, qs, g,
                            flag);
         hipLaunchKernelGGL(k_whiten_apply<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, Y, M, qs, Z);
     } else {
-        hipLaunchKernelGGL(k_gram<64>, dim3((unsigned)P.sg), dim3(256), 0, s, Y, M, P.rows_g, gp);
-        hipLaunchKernelGGL(k_whiten_eig<64>, dim3(1), dim3(1024), 0, s, gp, (int)P.sg, M, qs, g,
-                           flag);
+        hipLaunchKernelGGL(k_gram<64>, dim3((unsigned)P.sg), dim3(1024), 0, s, Y, M, P.rows_g,
+                           gp);
+        hipLaunchKernelGGL(k_gram_sum, dim3(ucdiv(64 * 64, 64)), dim3(256), 0, s, gp, (int)P.sg,
+                           64 * 64);
+        hipLaunchKernelGGL((k_whiten_eig<64, kEig64Threads>), dim3(1), dim3(kEig64Threads), 0, s,
+                           gp, M, qs, g, flag);
         hipLaunchKernelGGL(k_whiten_apply<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, Y, M, qs, Z);
     }
 }
