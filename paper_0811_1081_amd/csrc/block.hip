@@ -17,8 +17,11 @@ namespace {
 inline unsigned bcdiv(int64_t a, int64_t b) { return (unsigned)((a + b - 1) / b); }
 inline size_t balign(size_t x) { return (x + 255) & ~(size_t)255; }
 
+// Row slices of the vector-change sums (k_block_change_part).
+constexpr int kChangeSlices = 256;
+
 struct BlockLayout {
-    size_t Y, Z, Z2, W, g, flag, norms, sk, total;
+    size_t Y, Z, Z2, W, g, flag, norms, cpart, sk, total;
 };
 BlockLayout block_layout(int64_t M, int64_t N, int r)
 {
@@ -35,6 +38,7 @@ BlockLayout block_layout(int64_t M, int64_t N, int r)
     put(L.g, (size_t)2 * r * 8);
     put(L.flag, 8);
     put(L.norms, (size_t)r * 8);
+    put(L.cpart, (size_t)kChangeSlices * r * 8);
     put(L.sk, sketch_plan(M, N, r).total);
     L.total = o;
     return L;
@@ -62,26 +66,54 @@ __global__ __launch_bounds__(256) void k_block_norms(const float *__restrict__ W
         sig[i] = sqrt(((red[0] + red[1]) + red[2]) + red[3]);
 }
 
-// Change of the unit Ritz vector i = blockIdx.x between two whitened blocks
-// (columns of norm sqrt(M)): d_i = |v - s u| = sqrt(2 - 2 |u . v|), s the
-// sign of u . v, from an FP64 sum over the rows in a fixed order.
-__global__ __launch_bounds__(256) void k_block_change(const float *__restrict__ Zn,
-                                                      const float *__restrict__ Zo, int64_t M,
-                                                      int r, double *__restrict__ d)
+// Change of the unit Ritz vectors between two whitened blocks (row-major
+// M x r, columns of norm sqrt(M)): d_i = |v - s u| = sqrt(2 - 2 |u . v|), s
+// the sign of u . v.  The dot products are FP64 sums in a fixed order: row
+// slice y = blockIdx.x of `rows` rows, thread t on column t mod r and rows
+// t / r, t / r + 256 / r, ... of the slice (each wave reads whole rows), the
+// 256 / r row groups added in order into part[y][c]; then the slices in
+// order, four interleaved runs added at the end (k_block_change_fin).
+__global__ __launch_bounds__(256) void k_block_change_part(const float *__restrict__ Zn,
+                                                           const float *__restrict__ Zo,
+                                                           int64_t M, int r, int64_t rows,
+                                                           double *__restrict__ part)
 {
-    __shared__ double red[4];
-    const int i = blockIdx.x, tid = threadIdx.x;
+    __shared__ double red[256];
+    const int tid = threadIdx.x, rp = 256 / r, c = tid % r, ro = tid / r;
+    const int64_t rb = (int64_t)blockIdx.x * rows;
+    const int64_t re = M < rb + rows ? M : rb + rows;
     double a = 0.0;
-    for (int64_t m = tid; m < M; m += 256)
-        a += (double)Zn[m * r + i] * (double)Zo[m * r + i];
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1)
-        a += __shfl_xor(a, o, 64);
-    if ((tid & 63) == 0)
-        red[tid >> 6] = a;
+#pragma unroll 8
+    for (int64_t m = rb + ro; m < re; m += rp)
+        a += (double)Zn[m * r + c] * (double)Zo[m * r + c];
+    red[tid] = a;
     __syncthreads();
-    if (tid == 0) {
-        const double c = fabs(((red[0] + red[1]) + red[2]) + red[3]) / (double)M;
+    if (tid < r) {
+        double v = red[tid];
+        for (int g = 1; g < rp; ++g)
+            v += red[g * r + tid];
+        part[(int64_t)blockIdx.x * r + tid] = v;
+    }
+}
+
+// Wave w adds slices w, w + 4, ... in order; the four wave sums in wave order.
+__global__ __launch_bounds__(256) void k_block_change_fin(const double *__restrict__ part,
+                                                          int nslice, int64_t M, int r, int K,
+                                                          double *__restrict__ d)
+{
+    __shared__ double red[3][64];
+    const int i = threadIdx.x & 63, w = threadIdx.x >> 6;
+    double a = 0.0;
+    if (i < K) {
+#pragma unroll 8
+        for (int y = w; y < nslice; y += 4)
+            a += part[(int64_t)y * r + i];
+    }
+    if (w > 0)
+        red[w - 1][i] = a;
+    __syncthreads();
+    if (w == 0 && i < K) {
+        const double c = fabs(((a + red[0][i]) + red[1][i]) + red[2][i]) / (double)M;
         d[i] = sqrt(fmax(0.0, 2.0 - 2.0 * c));
     }
 }
@@ -154,6 +186,9 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
     double *dd = gd + r; // vector changes (loading stop)
     int32_t *flag = reinterpret_cast<int32_t *>(base + L.flag);
     double *norms = reinterpret_cast<double *>(base + L.norms);
+    double *cpart = reinterpret_cast<double *>(base + L.cpart);
+    const int64_t crows = (M + kChangeSlices - 1) / kChangeSlices;
+    const int cslices = (int)((M + crows - 1) / crows);
     unsigned char *sk = base + L.sk;
 
     // V_0: whitened X Omega, or whitened given start vectors
@@ -177,9 +212,12 @@ gspca_status gspca_fit_block(const float *X, int64_t ldx, int64_t M, int64_t N, 
         launch_sketch(X, ldx, M, N, W, r, Y, s);
         std::swap(Z, Zo);
         launch_whiten(Y, M, r, Z, gd, flag, sk, s);
-        if (vstop)
-            hipLaunchKernelGGL(k_block_change, dim3((unsigned)K), dim3(256), 0, s, Z, Zo, M, r,
-                               dd);
+        if (vstop) {
+            hipLaunchKernelGGL(k_block_change_part, dim3((unsigned)cslices), dim3(256), 0, s, Z,
+                               Zo, M, r, crows, cpart);
+            hipLaunchKernelGGL(k_block_change_fin, dim3(1), dim3(256), 0, s, cpart, cslices, M,
+                               r, (int)K, dd);
+        }
         if (hipMemcpyAsync(g.data(), gd, (size_t)(vstop ? 2 * r : r) * 8, hipMemcpyDeviceToHost,
                            s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
