@@ -450,24 +450,29 @@ __global__ __launch_bounds__(256) void k_sketch_t(const float *__restrict__ X, i
 // multiple of 4), on the FP32 matrix cores (v_mfma_f32_16x16x4f32:
 // D(16x16) += A(16x4) B(4x16), FP32 operands and accumulation; lane l
 // supplies A(l % 16, l / 16) and B(l / 16, l % 16) and holds
-// D(4 (l / 16) + i, l % 16) in its i-th accumulator).  Chunks of 16 columns
-// (Y = X Om) or 16 rows (W = X^T Z) of X and the matching rows of Om or Z are
+// D(4 (l / 16) + i, l % 16) in its i-th accumulator).  Chunks of BK columns
+// (Y = X Om) or BK rows (W = X^T Z) of X and the matching rows of Om or Z are
 // staged in two LDS buffers with 16-byte loads, the next chunk's loads in
 // flight while the current one is multiplied (one barrier per chunk), and
-// each chunk is four matrix-core steps of k = 4.  The products and sums are
-// FP32 as in k_sketch / k_sketch_t, in another order; at 65536 x 8192, r = 64
-// both take ~0.71 ms (~96 TFLOP/s) against 1.23 / 1.03 ms for the same tiling
-// on the vector ALU.
+// each chunk is BK / 4 matrix-core steps of k = 4.  The products and sums
+// are FP32 as in k_sketch / k_sketch_t, in another order.  At 65536 x 8192,
+// r = 64, Y = X Om takes ~0.80 ms with 32-column chunks against ~1.02 ms with
+// 16 (same process, calls separated by idle gaps); W = X^T Z keeps 16-row
+// chunks (~0.69 ms; 32 rows, which would read whole 128-byte lines of each
+// column, halve the workgroups per CU and were not faster).
 
 // Y = X Om, X's columns 16-byte aligned: workgroup = 64 rows of Y; wave w
-// owns rows 16w..16w+15 and all R columns (R/16 tiles of 16).
-template <int R>
+// owns rows 16w..16w+15 and all R columns (R/16 tiles of 16).  Chunks of BK
+// columns.
+template <int R, int BK>
 __global__ __launch_bounds__(256) void k_sketch_m(const float *__restrict__ X, int64_t ldx,
                                                   int64_t M, int64_t N,
                                                   const float *__restrict__ Om,
                                                   float *__restrict__ Y)
 {
-    constexpr int BM = 64, BK = 16, RT = R / 16, OQ = BK * R / 4;
+    constexpr int BM = 64, RT = R / 16;
+    constexpr int XL = BK * BM / 4 / 256;                // float4 loads of X per thread
+    constexpr int OQ = BK * R / 4, OL = (OQ + 255) / 256; // of Om
     // rows padded by 16 floats: the four k rows a wave reads at once fall in
     // different halves of the 32 banks
     __shared__ __align__(16) float xs[2][BK][BM + 16];
@@ -475,34 +480,49 @@ __global__ __launch_bounds__(256) void k_sketch_m(const float *__restrict__ X, i
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
     const int li = lane & 15, lk = lane >> 4;
     const int64_t m0 = (int64_t)blockIdx.x * BM;
-    mf32x4_t xr, orr = {0.f, 0.f, 0.f, 0.f};
+    mf32x4_t xr[XL], orr[OL];
+#pragma unroll
+    for (int u = 0; u < OL; ++u)
+        orr[u] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
     auto gload = [&](int64_t j0) {
-        { // column c, rows 4q..4q+3 of the tile
-            const int c = tid >> 4, q = tid & 15;
+#pragma unroll
+        for (int v = 0; v < XL; ++v) { // column c, rows 4q..4q+3 of the tile
+            const int e = tid + 256 * v, c = e >> 4, q = e & 15;
             const int64_t m = m0 + 4 * q, j = j0 + c;
             if (j < N && m + 3 < M) {
-                xr = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
+                xr[v] = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
             } else {
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    xr[u] = (j < N && m + u < M) ? X[m + u + j * ldx] : 0.0f;
+                    xr[v][u] = (j < N && m + u < M) ? X[m + u + j * ldx] : 0.0f;
             }
         }
-        if (tid < OQ) { // Omega row c, columns 4u..4u+3
-            const int c = tid / (R / 4), u = tid % (R / 4);
-            const int64_t j = j0 + c;
-            if (j < N)
-                orr = *reinterpret_cast<const mf32x4_t *>(Om + j * R + 4 * u);
-            else
-                orr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < OL; ++v) { // Omega row c, columns 4u..4u+3
+            const int e = tid + 256 * v;
+            if (e < OQ) {
+                const int c = e / (R / 4), u = e % (R / 4);
+                const int64_t j = j0 + c;
+                if (j < N)
+                    orr[v] = *reinterpret_cast<const mf32x4_t *>(Om + j * R + 4 * u);
+                else
+                    orr[v] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+            }
         }
     };
     auto sstore = [&](int b) {
-        const int c = tid >> 4, q = tid & 15;
-        *reinterpret_cast<mf32x4_t *>(&xs[b][c][4 * q]) = xr;
-        if (tid < OQ) {
-            const int c2 = tid / (R / 4), u = tid % (R / 4);
-            *reinterpret_cast<mf32x4_t *>(&os[b][c2][4 * u]) = orr;
+#pragma unroll
+        for (int v = 0; v < XL; ++v) {
+            const int e = tid + 256 * v, c = e >> 4, q = e & 15;
+            *reinterpret_cast<mf32x4_t *>(&xs[b][c][4 * q]) = xr[v];
+        }
+#pragma unroll
+        for (int v = 0; v < OL; ++v) {
+            const int e = tid + 256 * v;
+            if (e < OQ) {
+                const int c2 = e / (R / 4), u = e % (R / 4);
+                *reinterpret_cast<mf32x4_t *>(&os[b][c2][4 * u]) = orr[v];
+            }
         }
     };
     mf32x4_t acc[RT];
@@ -542,14 +562,18 @@ __global__ __launch_bounds__(256) void k_sketch_m(const float *__restrict__ X, i
 
 // W = s X^T Z over row slice y (partial sums as k_sketch_t), X's columns
 // 16-byte aligned: workgroup (b, y) = 128 columns of X; wave w owns columns
-// 32w..32w+31 (two tiles of 16) and all R sketch columns.
-template <int R>
+// 32w..32w+31 (two tiles of 16) and all R sketch columns.  Chunks of BK rows
+// (BK = 32: whole 128-byte lines of each column).
+template <int R, int BK>
 __global__ __launch_bounds__(256) void k_sketch_t_m(const float *__restrict__ X, int64_t ldx,
                                                     int64_t M, int64_t N,
                                                     const float *__restrict__ Z, float s,
                                                     int64_t rows, float *__restrict__ W)
 {
-    constexpr int BN = 128, BK = 16, RT = R / 16, ZQ = BK * R / 4;
+    constexpr int BN = 128, RT = R / 16;
+    constexpr int XL = BK * BN / 4 / 256;                 // float4 loads of X per thread
+    constexpr int ZQ = BK * R / 4, ZL = (ZQ + 255) / 256; // of Z
+    constexpr int QC = BK / 4;                            // float4 per column of a chunk
     __shared__ __align__(16) float xs[2][BK][BN + 16]; // padded as in k_sketch_m
     __shared__ __align__(16) float zs[2][BK][R + 16];
     const int tid = threadIdx.x, lane = tid & 63, w = tid >> 6;
@@ -558,11 +582,14 @@ __global__ __launch_bounds__(256) void k_sketch_t_m(const float *__restrict__ X,
     const int64_t rb = (int64_t)blockIdx.y * rows;
     const int64_t re = M < rb + rows ? M : rb + rows;
     W += (int64_t)blockIdx.y * N * R;
-    mf32x4_t xr[2], zr = {0.f, 0.f, 0.f, 0.f};
+    mf32x4_t xr[XL], zr[ZL];
+#pragma unroll
+    for (int u = 0; u < ZL; ++u)
+        zr[u] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
     auto gload = [&](int64_t r0) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) { // column c, rows 4q..4q+3 of the chunk
-            const int e = tid + 256 * h, c = e >> 2, q = e & 3;
+        for (int h = 0; h < XL; ++h) { // column c, rows 4q..4q+3 of the chunk
+            const int e = tid + 256 * h, c = e / QC, q = e % QC;
             const int64_t m = r0 + 4 * q, j = j0 + c;
             if (j < N && m + 3 < re) {
                 xr[h] = *reinterpret_cast<const mf32x4_t *>(X + m + j * ldx);
@@ -572,26 +599,34 @@ __global__ __launch_bounds__(256) void k_sketch_t_m(const float *__restrict__ X,
                     xr[h][u] = (j < N && m + u < re) ? X[m + u + j * ldx] : 0.0f;
             }
         }
-        if (tid < ZQ) { // Z row c, columns 4u..4u+3
-            const int c = tid / (R / 4), u = tid % (R / 4);
-            const int64_t m = r0 + c;
-            if (m < re)
-                zr = *reinterpret_cast<const mf32x4_t *>(Z + m * R + 4 * u);
-            else
-                zr = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+        for (int v = 0; v < ZL; ++v) { // Z row c, columns 4u..4u+3
+            const int e = tid + 256 * v;
+            if (e < ZQ) {
+                const int c = e / (R / 4), u = e % (R / 4);
+                const int64_t m = r0 + c;
+                if (m < re)
+                    zr[v] = *reinterpret_cast<const mf32x4_t *>(Z + m * R + 4 * u);
+                else
+                    zr[v] = mf32x4_t{0.f, 0.f, 0.f, 0.f};
+            }
         }
     };
     auto sstore = [&](int b) {
 #pragma unroll
-        for (int h = 0; h < 2; ++h) {
-            const int e = tid + 256 * h, c = e >> 2, q = e & 3;
+        for (int h = 0; h < XL; ++h) {
+            const int e = tid + 256 * h, c = e / QC, q = e % QC;
 #pragma unroll
             for (int u = 0; u < 4; ++u)
                 xs[b][4 * q + u][c] = xr[h][u];
         }
-        if (tid < ZQ) {
-            const int c = tid / (R / 4), u = tid % (R / 4);
-            *reinterpret_cast<mf32x4_t *>(&zs[b][c][4 * u]) = zr;
+#pragma unroll
+        for (int v = 0; v < ZL; ++v) {
+            const int e = tid + 256 * v;
+            if (e < ZQ) {
+                const int c = e / (R / 4), u = e % (R / 4);
+                *reinterpret_cast<mf32x4_t *>(&zs[b][c][4 * u]) = zr[v];
+            }
         }
     };
     mf32x4_t acc[2][RT];
@@ -1158,6 +1193,10 @@ SketchPlan sketch_plan(int64_t M, int64_t N, int r)
 
 bool valid_rank(int32_t r) { return r == 32 || r == GSPCA_WS_RMAX; }
 
+// Chunk depths of the matrix-core sketch products (columns of X per chunk
+// for Y = X Om, rows for W = X^T Z).
+constexpr int kSketchBK = 32, kSketchTBK = 16;
+
 void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
                    float *Y, hipStream_t s)
 {
@@ -1165,11 +1204,11 @@ void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const floa
                          ((uintptr_t)Y) % 16 == 0;
     if (aligned) {
         if (r == 32)
-            hipLaunchKernelGGL(k_sketch_m<32>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
-                               Om, Y);
+            hipLaunchKernelGGL((k_sketch_m<32, kSketchBK>), dim3(ucdiv(M, 64)), dim3(256), 0, s, X,
+                               ldx, M, N, Om, Y);
         else
-            hipLaunchKernelGGL(k_sketch_m<64>, dim3(ucdiv(M, 64)), dim3(256), 0, s, X, ldx, M, N,
-                               Om, Y);
+            hipLaunchKernelGGL((k_sketch_m<64, kSketchBK>), dim3(ucdiv(M, 64)), dim3(256), 0, s, X,
+                               ldx, M, N, Om, Y);
         return;
     }
     if (r == 32)
@@ -1185,15 +1224,15 @@ void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const fl
     const float sc = (float)(1.0 / sqrt((double)M));
     float *dst = P.st == 1 ? W : reinterpret_cast<float *>(ws + P.off_wpart);
     const bool aligned = ldx % 4 == 0 && ((uintptr_t)X) % 16 == 0 && ((uintptr_t)Z) % 16 == 0 &&
-                         ((uintptr_t)dst) % 16 == 0 && P.rows_t % 16 == 0;
+                         ((uintptr_t)dst) % 16 == 0 && P.rows_t % kSketchTBK == 0;
     if (aligned) {
         const dim3 g(ucdiv(N, 128), (unsigned)P.st);
         if (r == 32)
-            hipLaunchKernelGGL(k_sketch_t_m<32>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
-                               dst);
+            hipLaunchKernelGGL((k_sketch_t_m<32, kSketchTBK>), g, dim3(256), 0, s, X, ldx, M, N, Z,
+                               sc, P.rows_t, dst);
         else
-            hipLaunchKernelGGL(k_sketch_t_m<64>, g, dim3(256), 0, s, X, ldx, M, N, Z, sc, P.rows_t,
-                               dst);
+            hipLaunchKernelGGL((k_sketch_t_m<64, kSketchTBK>), g, dim3(256), 0, s, X, ldx, M, N, Z,
+                               sc, P.rows_t, dst);
     } else {
         const dim3 g(ucdiv(N, 64), (unsigned)P.st);
         if (r == 32)
