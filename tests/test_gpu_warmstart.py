@@ -67,6 +67,24 @@ def test_sketch_matches_oracle(orc, M):
     assert np.all(np.abs(Y.cpu().numpy() - Yo) <= bound + 1e-30)
 
 
+@pytest.mark.parametrize("r", [32, 64])
+def test_sketch_many_rows(r):
+    """Y = X Omega at 65572 rows (the form for many rows: 256-row workgroups,
+    36 rows in the last) and 150 columns (ragged 32-column chunks), against
+    the FP64 product within the FP32 accumulation bound."""
+    import torch
+    from paper_0811_1081_amd import synth, warmstart as ws
+    rng = np.random.default_rng(11 + r)
+    M, N = 65572, 150
+    X = rng.standard_normal((M, N)).astype(np.float32)
+    Om = synth.sketch_matrix(N, r)
+    Y = ws.sketch(_colmajor(X), _dev(Om))
+    torch.cuda.synchronize()
+    X64, O64 = X.astype(np.float64), Om.astype(np.float64)
+    bound = N * 2.0 ** -24 * (np.abs(X64) @ np.abs(O64))
+    assert np.all(np.abs(Y.cpu().numpy() - X64 @ O64) <= bound + 1e-30)
+
+
 @pytest.mark.parametrize("r,M", [(32, 900), (64, 900), (64, 903)])  # aligned columns, and not
 def test_refinement_step_matches_oracle(orc, r, M):
     import torch
