@@ -551,6 +551,20 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
     double a0 = 0.0, a1 = 0.0, a2 = 0.0, a3 = 0.0;
     if (j < N) {
         int64_t g = grp;
+        // sixteen loads in flight, added in the same order as the loop below
+        for (; g + 15 * NG < G; g += 16 * NG) {
+            E x[16];
+#pragma unroll
+            for (int u = 0; u < 16; ++u)
+                x[u] = q_part[(g + u * NG) * N + j];
+#pragma unroll
+            for (int u = 0; u < 16; u += 4) {
+                a0 += (double)x[u];
+                a1 += (double)x[u + 1];
+                a2 += (double)x[u + 2];
+                a3 += (double)x[u + 3];
+            }
+        }
         for (; g + 3 * NG < G; g += 4 * NG) {
             a0 += (double)q_part[g * N + j];
             a1 += (double)q_part[(g + NG) * N + j];
@@ -564,6 +578,7 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
     // W d, the W columns split over the groups
     double pr = 0.0;
     if (j < N)
+#pragma unroll 4
         for (int i = grp; i < kd; i += NG)
             pr += W[j + (int64_t)i * N] * d[i];
     __syncthreads();

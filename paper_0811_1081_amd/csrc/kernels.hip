@@ -442,11 +442,13 @@ __global__ __launch_bounds__(kBlock) void k_gs_apply(const double *__restrict__ 
             // eight independent sums so that the column loads overlap
             double a[8] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             int i = 0;
+#pragma unroll 4
             for (; i + 7 < n; i += 8) {
 #pragma unroll
                 for (int u = 0; u < 8; ++u)
                     a[u] += (double)Q[r + (int64_t)(i0 + i + u) * ldq] * cs[i + u];
             }
+#pragma unroll 8
             for (; i < n; ++i)
                 a[0] += (double)Q[r + (int64_t)(i0 + i) * ldq] * cs[i];
             proj += ((a[0] + a[1]) + (a[2] + a[3])) + ((a[4] + a[5]) + (a[6] + a[7]));
