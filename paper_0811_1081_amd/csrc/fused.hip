@@ -602,7 +602,23 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
     if (done || kg == 0)
         return;
     __syncthreads();
-    for (int i = grp; i < kg; i += NG) {
+    int i = grp;
+    // eight coefficients at a time: their loads are issued before the first
+    // wave sum (many earlier components: the loads would otherwise wait one
+    // after another behind each sum)
+    for (; i + 7 * NG < kg; i += 8 * NG) {
+        double sv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+            sv[u] = (j < N) ? (double)P[j + (int64_t)(i + u * NG) * N] * ys[lane] : 0.0;
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+            const double sum = fwave_sum(sv[u]);
+            if (lane == 0)
+                cpart[(int64_t)blockIdx.x * kg + i + u * NG] = sum;
+        }
+    }
+    for (; i < kg; i += NG) {
         const double sv = (j < N) ? (double)P[j + (int64_t)i * N] * ys[lane] : 0.0;
         const double sum = fwave_sum(sv);
         if (lane == 0)
