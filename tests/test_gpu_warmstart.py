@@ -133,6 +133,72 @@ def test_whitening_matches_oracle(orc, r):
     assert np.abs(Zg[:, ok].T @ Zg[:, ok] / M - np.eye(int(ok.sum()))).max() <= 1e-4
 
 
+@pytest.mark.parametrize("r", [32, 64])
+def test_whitening_equal_diagonal_pairs(r):
+    """Y = Q diag(s) B with orthonormal Q (M x r), distinct known s and B a
+    45-degree rotation of each index pair (2i, 2i + 1): Y^T Y = B^T diag(s^2) B
+    has diagonal entries equal within each pair (up to the FP32 rounding of
+    Y) and a non-zero off-diagonal entry in every pair block (the rotation's
+    |t| = 1 limit), eigenvalues s^2 and eigenvectors the columns of B.  Checked against the library eigenvalues of the FP32
+    Y's Gram matrix, the closed form s^2, and Z = +-sqrt(M) Q."""
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    rng = np.random.default_rng(5 + r)
+    M = 1000
+    Q, _ = np.linalg.qr(rng.standard_normal((M, r)))
+    s = np.geomspace(10.0, 0.5, r)
+    B = np.eye(r)
+    h = np.sqrt(0.5)
+    for i in range(0, r, 2):
+        B[i:i + 2, i:i + 2] = [[h, h], [-h, h]]
+    Y32 = ((Q * s) @ B).astype(np.float32)
+    Z, g, flag = ws.whiten(_dev(Y32))
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    g = g.cpu().numpy()
+    Y64 = Y32.astype(np.float64)
+    lib = np.sort(np.linalg.eigvalsh(Y64.T @ Y64))[::-1]
+    assert np.abs(g - lib).max() <= 1e-10 * lib[0]
+    assert np.abs(g / s ** 2 - 1.0).max() <= 1e-5
+    Zg = Z.cpu().numpy().astype(np.float64)
+    cosines = np.abs(np.sum(Zg * Q, axis=0)) / np.sqrt(M)
+    assert np.abs(cosines - 1.0).max() <= 1e-5
+    assert np.abs(Zg.T @ Zg / M - np.eye(r)).max() <= 1e-5
+
+
+@pytest.mark.parametrize("r", [32, 64])
+def test_whitening_exact_equal_diagonals(r):
+    """Integer columns y_2i = a_i e_2i + b_i e_2i+1, y_2i+1 = a_i e_2i - b_i e_2i+1
+    (all sums exact): each pair block of Y^T Y is [[a^2 + b^2, a^2 - b^2],
+    [a^2 - b^2, a^2 + b^2]] with exactly equal diagonal entries (d = 0, the
+    rotation's t = 1 case), the other entries are exactly zero, the
+    eigenvalues are 2 a_i^2 and 2 b_i^2 and the whitened columns are
+    +-sqrt(M) e_2i and +-sqrt(M) e_2i+1."""
+    import torch
+    from paper_0811_1081_amd import warmstart as ws
+    M, P = 1000, r // 2
+    a = 40.0 + 2.0 * np.arange(P)  # even, 40 .. 40 + 2(P - 1)
+    b = 1.0 + 2.0 * np.arange(P)   # odd: every value distinct
+    Y = np.zeros((M, r), dtype=np.float32)
+    for i in range(P):
+        Y[2 * i, 2 * i], Y[2 * i + 1, 2 * i] = a[i], b[i]
+        Y[2 * i, 2 * i + 1], Y[2 * i + 1, 2 * i + 1] = a[i], -b[i]
+    Z, g, flag = ws.whiten(_dev(Y))
+    torch.cuda.synchronize()
+    assert int(flag.item()) == 0
+    exact = np.sort(np.concatenate([2 * a ** 2, 2 * b ** 2]))[::-1]
+    g = g.cpu().numpy()
+    assert np.abs(g / exact - 1.0).max() <= 1e-13
+    Zg = np.abs(Z.cpu().numpy().astype(np.float64)) / np.sqrt(M)
+    # each whitened column is one unit vector: its row is 2i for eigenvalue
+    # 2 a_i^2 and 2i + 1 for 2 b_i^2
+    rows = [2 * int(np.where(a == np.sqrt(v / 2))[0][0]) if np.any(a == np.sqrt(v / 2))
+            else 2 * int(np.where(b == np.sqrt(v / 2))[0][0]) + 1 for v in exact]
+    expect = np.zeros((M, r))
+    expect[rows, np.arange(r)] = 1.0
+    assert np.abs(Zg - expect).max() <= 1e-6
+
+
 def test_forward_matches_oracle(orc):
     import torch
     from paper_0811_1081_amd import warmstart as ws
