@@ -641,11 +641,12 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
 constexpr int kFinApplyThreads = 1024;
 static_assert(kFinApplyMaxN == kFinApplyThreads, "one column per thread");
 template <typename E>
-__global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
-    const E *__restrict__ q_part, int64_t G, int64_t N, const double *__restrict__ W, int kd,
-    const double *__restrict__ d, const E *__restrict__ P, int kg, double *__restrict__ qy,
-    double *__restrict__ p, double *__restrict__ pprev, LoopState *st, int it, int stop,
-    double tiny)
+__device__ void fin_apply_body(const E *__restrict__ q_part, int64_t G, int64_t N,
+                               const double *__restrict__ W, int kd,
+                               const double *__restrict__ d, const E *__restrict__ P, int kg,
+                               double *__restrict__ qy, double *__restrict__ p,
+                               double *__restrict__ pprev, LoopState *st, int it, int stop,
+                               double tiny)
 {
     if (st->degenerate)
         return;
@@ -753,6 +754,16 @@ __global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
     }
 }
 
+template <typename E>
+__global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
+    const E *__restrict__ q_part, int64_t G, int64_t N, const double *__restrict__ W, int kd,
+    const double *__restrict__ d, const E *__restrict__ P, int kg, double *__restrict__ qy,
+    double *__restrict__ p, double *__restrict__ pprev, LoopState *st, int it, int stop,
+    double tiny)
+{
+    fin_apply_body<E>(q_part, G, N, W, kd, d, P, kg, qy, p, pprev, st, it, stop, tiny);
+}
+
 // Gram-Schmidt coefficients of the score, d = V_(k)^T t (FP64), from the
 // complete t of the pass: workgroup (b, y) takes `rows` consecutive rows of t
 // (staged in LDS, zero past M) and columns [32y, 32y + 32) of V, two columns
@@ -764,10 +775,12 @@ __global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
 // its partials in LDS and needs no arrival counter.
 constexpr int kScoreThreads = 1024;
 template <typename E>
-__global__ __launch_bounds__(kScoreThreads) void k_score_dot(
-    const double *__restrict__ t, int64_t M, const E *__restrict__ V, int kd, int64_t rows,
-    const double *__restrict__ tsq, int G, double *__restrict__ cpart, double *__restrict__ d,
-    LoopState *st, double tol, int32_t limit, int replay, double tiny, int stop)
+__device__ void score_dot_body(const double *__restrict__ t, int64_t M,
+                               const E *__restrict__ V, int kd, int64_t rows,
+                               const double *__restrict__ tsq, int G,
+                               double *__restrict__ cpart, double *__restrict__ d,
+                               LoopState *st, double tol, int32_t limit, int replay, double tiny,
+                               int stop)
 {
     if (st->done)
         return;
@@ -865,6 +878,36 @@ __global__ __launch_bounds__(kScoreThreads) void k_score_dot(
     // level once t has been formed from a loading orthogonal to P_(k))
     const double s2 = tt - dd;
     score_test(st, ss, s2 > 0.0 ? sqrt(s2) : 0.0, tol, limit, replay, tiny, stop);
+}
+
+template <typename E>
+__global__ __launch_bounds__(kScoreThreads) void k_score_dot(
+    const double *__restrict__ t, int64_t M, const E *__restrict__ V, int kd, int64_t rows,
+    const double *__restrict__ tsq, int G, double *__restrict__ cpart, double *__restrict__ d,
+    LoopState *st, double tol, int32_t limit, int replay, double tiny, int stop)
+{
+    score_dot_body<E>(t, M, V, kd, rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
+}
+
+// The score side and the loading side of an iteration in one launch when
+// each fits one workgroup (the score's rows in one block, N <= 1024 and the
+// q partials small): k_score_dot's steps, a barrier (d and the loop state,
+// written by this workgroup, are then visible to all its threads), then
+// k_fin_apply's steps -- the same arithmetic in the same order, one kernel
+// boundary fewer per iteration.
+static_assert(kScoreThreads == kFinApplyThreads, "one workgroup runs both steps");
+template <typename E>
+__global__ __launch_bounds__(kScoreThreads) void k_score_fin(
+    const double *__restrict__ t, int64_t M, const E *__restrict__ V, int kd, int64_t rows,
+    const double *__restrict__ tsq, int G, double *__restrict__ cpart, double *__restrict__ d,
+    double tol, int32_t limit, int replay, const E *__restrict__ q_part, int64_t Gq, int64_t N,
+    const double *__restrict__ W, const E *__restrict__ P, int kg, double *__restrict__ qy,
+    double *__restrict__ p, double *__restrict__ pprev, LoopState *st, int it, int stop,
+    double tiny)
+{
+    score_dot_body<E>(t, M, V, kd, rows, tsq, G, cpart, d, st, tol, limit, replay, tiny, stop);
+    __syncthreads();
+    fin_apply_body<E>(q_part, Gq, N, W, kd, d, P, kg, qy, p, pprev, st, it, stop, tiny);
 }
 
 // Finish component k: V[:,k] = t / sigma (GS) or T[:,k] = t (NIPALS),
@@ -1019,6 +1062,24 @@ void Fused<F>::fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int
     hipLaunchKernelGGL(k_fin_q<E>, dim3(fcdiv(N, 64)), dim3(64 * kFinGroups), 0, s, q_part, G, N,
                        W, kd, d, P,
                        kg, qy, cpart, c, st, it);
+}
+
+template <int F>
+bool Fused<F>::score_fin_fits(int64_t M, int kd)
+{
+    return fcdiv(M, score_rows(M, kd)) == 1 && (kd > 0 ? fcdiv(kd, 32) : 1) == 1;
+}
+
+template <int F>
+void Fused<F>::score_fin(const double *t, int64_t M, const E *V, int kd, const double *tsq,
+                         int G, double *cpart, double *d, double tol, int32_t limit, int replay,
+                         const E *q_part, int64_t Gq, int64_t N, const double *W, const E *P,
+                         int kg, double *qy, double *p, double *pprev, LoopState *st, int it,
+                         int stop, double tiny, hipStream_t s)
+{
+    hipLaunchKernelGGL(k_score_fin<E>, dim3(1), dim3(kScoreThreads), 0, s, t, M, V, kd,
+                       score_rows(M, kd), tsq, G, cpart, d, tol, limit, replay, q_part, Gq, N, W,
+                       P, kg, qy, p, pprev, st, it, stop, tiny);
 }
 
 template <int F>

@@ -581,6 +581,8 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
             }
         };
         loading_side(0, 0);
+        // both sides of an iteration in one workgroup launch when each fits
+        const bool score_fin = one_wg && F::score_fin_fits(M, kg);
         int32_t enq = 0;
         int batch = 4;
         bool have = false;
@@ -598,9 +600,14 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 // score side: d = V_(k)^T t (coalesced over the rows, kept out of
                 // the streaming pass), sigma = |t - V d| and the stop test; t - V d
                 // itself is formed once, when the component ends
-                F::score_dot(td, M, T, kg, tsq, f.G, cpart, dvec, st, tol, limit, replay, tiny,
-                             stop, s);
-                loading_side(gs ? kg : 0, it);
+                if (score_fin) {
+                    F::score_fin(td, M, T, kg, tsq, f.G, cpart, dvec, tol, limit, replay, qpart,
+                                 f.G, N, W, P, kg, qy, p, pprev, st, it, stop, tiny, s);
+                } else {
+                    F::score_dot(td, M, T, kg, tsq, f.G, cpart, dvec, st, tol, limit, replay,
+                                 tiny, stop, s);
+                    loading_side(gs ? kg : 0, it);
+                }
             }
             enq += n;
             if (!read_state())

@@ -285,6 +285,14 @@ struct Fused {
     static void fin_q(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                       const double *d, const E *P, int kg, double *qy, double *cpart, double *c,
                       LoopState *st, int it, hipStream_t s);
+    // score_dot and fin_apply in one launch of one workgroup, when both fit
+    // one (score_fin_fits(M, kd) and the fin_apply condition)
+    static bool score_fin_fits(int64_t M, int kd);
+    static void score_fin(const double *t, int64_t M, const E *V, int kd, const double *tsq,
+                          int G, double *cpart, double *d, double tol, int32_t limit,
+                          int replay, const E *q_part, int64_t Gq, int64_t N, const double *W,
+                          const E *P, int kg, double *qy, double *p, double *pprev,
+                          LoopState *st, int it, int stop, double tiny, hipStream_t s);
     // fin_q and the loading-side gs_apply in one workgroup (N <= 1024)
     static void fin_apply(const E *q_part, int64_t G, int64_t N, const double *W, int kd,
                           const double *d, const E *P, int kg, double *qy, double *p,
