@@ -641,7 +641,7 @@ __global__ __launch_bounds__(64 * kFinGroups) void k_fin_q(
 constexpr int kFinApplyThreads = 1024;
 static_assert(kFinApplyMaxN == kFinApplyThreads, "one column per thread");
 template <typename E>
-__device__ void fin_apply_body(const E *__restrict__ q_part, int64_t G, int64_t N,
+__device__ __attribute__((always_inline)) inline void fin_apply_body(const E *__restrict__ q_part, int64_t G, int64_t N,
                                const double *__restrict__ W, int kd,
                                const double *__restrict__ d, const E *__restrict__ P, int kg,
                                double *__restrict__ qy, double *__restrict__ p,
@@ -775,7 +775,7 @@ __global__ __launch_bounds__(kFinApplyThreads) void k_fin_apply(
 // its partials in LDS and needs no arrival counter.
 constexpr int kScoreThreads = 1024;
 template <typename E>
-__device__ void score_dot_body(const double *__restrict__ t, int64_t M,
+__device__ __attribute__((always_inline)) inline void score_dot_body(const double *__restrict__ t, int64_t M,
                                const E *__restrict__ V, int kd, int64_t rows,
                                const double *__restrict__ tsq, int G,
                                double *__restrict__ cpart, double *__restrict__ d,
