@@ -383,9 +383,11 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     panel_width(N, &f.cpt, &f.NT, &f.ldp);
     // Variant knobs (GSPCA_PASS_LDS=1: loading in LDS with twice the threads;
     // GSPCA_PASS_SKEW=0/1: contiguous or interleaved panel order); the panel
-    // width is unchanged.  Interleaved is the default except for BF16 codes:
-    // at 65536 x 8192 it measured 414 vs 451 us per FP32 pass and 281 vs 287
-    // us per FP8 pass, but 330 vs 323 us per BF16 pass.
+    // width is unchanged.  Interleaved is the default: at 65536 x 8192 it
+    // measured 414 vs 451 us per FP32 pass and 281 vs 287 us per FP8 pass in
+    // the first form of the pass, and with the current pass 103.7 vs 107.0 us
+    // (FP8) and 174.9 vs 175.7 us (BF16, which had measured 330 vs 323 us
+    // in the first form).
     const char *e_lds = getenv("GSPCA_PASS_LDS");
     const char *e_skew = getenv("GSPCA_PASS_SKEW");
     const char *e_pipe = getenv("GSPCA_PASS_PIPE");
@@ -396,7 +398,7 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     const int lds_default = fmt == kFmtFP8 ? 1 : 0;
     const int want_lds = e_lds ? (e_lds[0] == '1' ? 1 : 0) : lds_default;
     f.plds = (want_lds && f.cpt >= 2 && f.NT <= 512) ? 1 : 0;
-    f.skew = e_skew ? (e_skew[0] == '1' ? 1 : 0) : (fmt == kFmtBF16 ? 0 : 1);
+    f.skew = e_skew ? (e_skew[0] == '1' ? 1 : 0) : 1;
     // Register double buffering pays for FP32 (318 vs 330 us per pass at 65536
     // x 8192); with decoded codes the second buffer spills (BF16 218 vs 185
     // us, FP8 210 vs 140 us with one buffer and two workgroups per CU).
