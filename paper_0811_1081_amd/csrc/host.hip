@@ -340,7 +340,20 @@ struct FusedPlan {
     size_t off_state, off_A, off_tE, off_td, off_tsq, off_qpart, off_d, off_c, off_qy, off_p,
         off_pprev, off_cpart, off_sq, off_cnpart, off_cn, off_cn0, off_cnx, off_t0, off_W,
         off_sig, total;
+    // the first loadings of all given starts in one pass (implicit FP32, K <= 64):
+    // Q0 and its scratch after everything else; total_base excludes them
+    size_t off_q0, off_flw, total_base;
 };
+
+// Given starts whose first loadings X^T t0 (t0 = the given column: the start
+// takes it unmodified) can all be formed up front by one matrix-core pass:
+// FP32 data, implicit deflation (X itself is the operator), at most 64
+// components.
+bool first_loadings_apply(const gspca_problem *pr, const gspca_options *op)
+{
+    return pr->dtype == GSPCA_F32 && op->implicit_deflation && op->init == GSPCA_INIT_GIVEN &&
+           op->T0 && pr->K <= 64;
+}
 
 int device_cu_count()
 {
@@ -371,7 +384,7 @@ void panel_width(int64_t N, int *cpt, int *NT, int64_t *ldp)
     *ldp = (int64_t)(*NT) * (*cpt);
 }
 
-FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
+FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu, bool q0 = false)
 {
     FusedPlan f{};
     f.M = M;
@@ -439,6 +452,11 @@ FusedPlan make_fused_plan(int64_t M, int64_t N, int64_t K, int fmt, int ncu)
     f.off_t0 = o;     o = align_up(o + (quantised ? 0 : len * esize));
     f.off_W = o;      o = align_up(o + (size_t)N * K * 8);
     f.off_sig = o;    o = align_up(o + (size_t)K * 8);
+    f.total_base = o;
+    if (q0) {
+        f.off_q0 = o;     o = align_up(o + (size_t)N * K * 4);
+        f.off_flw = o;    o = align_up(o + first_loadings_bytes(M, N, K));
+    }
     f.total = o;
     return f;
 }
@@ -462,8 +480,12 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     using F = Fused<FM>;
     constexpr bool quantised = FM == kFmtBF16 || FM == kFmtFP8;
     const int64_t M = pr->M, N = pr->N, K = pr->K;
-    const FusedPlan f = make_fused_plan(M, N, K, FM, device_cu_count());
-    if (!ws || ws_bytes < f.total)
+    const bool want_q0 = first_loadings_apply(pr, op);
+    const FusedPlan f = make_fused_plan(M, N, K, FM, device_cu_count(), want_q0);
+    // the up-front first loadings need their own workspace; without it the
+    // fit forms each first loading with a pass, as for any other start
+    const bool use_q0 = want_q0 && ws && ws_bytes >= f.total;
+    if (!ws || ws_bytes < f.total_base)
         return GSPCA_EWORKSPACE;
     if (((uintptr_t)ws) % kAlign)
         return GSPCA_EINVAL;
@@ -544,6 +566,12 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     }
     F::deflate(A, N, f.NP, f.ldp, nullptr, nullptr, 0, scale, f.nsplit_cn, cnpart, s);
     F::colnorm_finish(cnpart, f.nsplit_cn, N, cn0, cn, 0, 0, P, W, sig, s);
+    E *Q0 = use_q0 ? reinterpret_cast<E *>(base + f.off_q0) : nullptr;
+    if constexpr (FM == kFmtF32) {
+        if (use_q0)
+            launch_first_loadings(static_cast<const float *>(pr->X), pr->ldx, M, N, T0, K, Q0,
+                                  base + f.off_flw, s);
+    }
 
     auto start_args = [&](int64_t k) {
         const int32_t lim = replay ? rit[k] : op->max_iter;
@@ -556,13 +584,28 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
     for (int64_t k = 0; k < K; ++k) {
         const int32_t limit = replay ? rit[k] : op->max_iter;
         const int kg = gs ? (int)k : 0;
+        // the source of the first loading's q: the pass's partials, or column
+        // k of Q0 when the given start was taken (implicit: R^T t0 = X^T t0)
+        const E *q_first = qpart;
+        int64_t g_first = f.G;
         if (!started) {
             // the start's scratch (given-start products) shares cpart, idle here
             F::start(A, N, f.NP, f.ldp, M, scale, implicit, T, P, sig, cn, T0, start_args(k),
                      tiny, tE, cpart, st, s);
-            // first loading of the component: p = R^T t0, Gram-Schmidt, norm
-            F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M, scale, p,
-                    tE, td, tsq, qpart, st, s);
+            bool from_q0 = false;
+            if (use_q0) {
+                if (!read_state())
+                    return GSPCA_EDEVICE;
+                from_q0 = h.start_col < 0 && !h.done && !h.degenerate;
+            }
+            if (from_q0) {
+                q_first = Q0 + k * N;
+                g_first = 1;
+            } else {
+                // first loading of the component: p = R^T t0, Gram-Schmidt, norm
+                F::pass(1, f.cpt, f.G, f.NT, f.plds, f.skew, f.pipe, A, N, f.NP, f.ldp, M,
+                        scale, p, tE, td, tsq, qpart, st, s);
+            }
         }
         started = false;
         // the loading side: one workgroup when N and the partials are small
@@ -572,17 +615,17 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
         // column-parallel reduction and apply kernels
         const bool one_wg =
             N <= kFinApplyMaxN && (int64_t)f.G * N * (int64_t)sizeof(E) <= (int64_t)256 * 1024;
-        auto loading_side = [&](int kdv, int it) {
+        auto loading_side = [&](int kdv, int it, const E *qsrc, int64_t gsrc) {
             if (one_wg) {
-                F::fin_apply(qpart, f.G, N, W, kdv, dvec, P, kg, qy, p, pprev, st, it, stop, tiny,
+                F::fin_apply(qsrc, gsrc, N, W, kdv, dvec, P, kg, qy, p, pprev, st, it, stop, tiny,
                              s);
             } else {
-                F::fin_q(qpart, f.G, N, W, kdv, dvec, P, kg, qy, cpart, cvec, st, it, s);
+                F::fin_q(qsrc, gsrc, N, W, kdv, dvec, P, kg, qy, cpart, cvec, st, it, s);
                 L::gs_apply(qy, 1, N, N, qy, P, N, kg, cvec, p, pprev, nullptr, sq, st, 0, tol,
                             limit, replay, tiny, stop, s);
             }
         };
-        loading_side(0, 0);
+        loading_side(0, 0, q_first, g_first);
         // both sides of an iteration in one workgroup launch when each fits
         const bool score_fin = one_wg && F::score_fin_fits(M, kg);
         int32_t enq = 0;
@@ -608,7 +651,7 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
                 } else {
                     F::score_dot(td, M, T, kg, tsq, f.G, cpart, dvec, st, tol, limit, replay,
                                  tiny, stop, s);
-                    loading_side(gs ? kg : 0, it);
+                    loading_side(gs ? kg : 0, it, qpart, f.G);
                 }
             }
             enq += n;
@@ -666,7 +709,9 @@ gspca_status fit_fused(const gspca_problem *pr, const gspca_options *op, const g
 size_t workspace_for(const gspca_problem *pr, const gspca_options *op)
 {
     if (use_fused(pr, op))
-        return make_fused_plan(pr->M, pr->N, pr->K, fmt_of(pr->dtype), device_cu_count()).total;
+        return make_fused_plan(pr->M, pr->N, pr->K, fmt_of(pr->dtype), device_cu_count(),
+                               first_loadings_apply(pr, op))
+            .total;
     return make_plan(pr->M, pr->N, pr->K, dtype_size(pr->dtype)).total;
 }
 

@@ -317,9 +317,17 @@ bool valid_rank(int32_t r); // sketch widths: 32 or 64
 // Y = X Om (X column-major, Om row-major N x r, Y row-major M x r)
 void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Om, int r,
                    float *Y, hipStream_t s);
-// W = X^T Z / sqrt(M) (Z row-major M x r, W row-major N x r)
+// W = X^T Z / sqrt(M) (Z row-major M x r, W row-major N x r); W = X^T Z when
+// unit_scale
 void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Z, int r,
-                     float *W, unsigned char *ws, hipStream_t s);
+                     float *W, unsigned char *ws, hipStream_t s, bool unit_scale = false);
+// The first loadings X^T T0 of all given starts (FP32, implicit deflation,
+// K <= 64) in one matrix-core pass over X: T0 (column-major M x K) into rows
+// of width r (zero-padded), W = X^T Z, then W's first K columns into Q0
+// (column-major N x K).  ws: first_loadings_bytes(M, N, K).
+size_t first_loadings_bytes(int64_t M, int64_t N, int64_t K);
+void launch_first_loadings(const float *X, int64_t ldx, int64_t M, int64_t N, const float *T0,
+                           int64_t K, float *Q0, unsigned char *ws, hipStream_t s);
 // Z = sqrt(M) Y Q diag(g)^(-1/2), g the eigenvalues of Y^T Y (decreasing)
 void launch_whiten(const float *Y, int64_t M, int r, float *Z, double *g, int32_t *flag,
                    unsigned char *ws, hipStream_t s);

@@ -1042,6 +1042,28 @@ __global__ __launch_bounds__(NT) void k_whiten_eig(const double *__restrict__ gs
     }
 }
 
+// T0 (column-major M x K) into Z (row-major M x R, columns K.. zero).
+__global__ __launch_bounds__(256) void k_t0_rows(const float *__restrict__ T0, int64_t M,
+                                                 int64_t K, int R, float *__restrict__ Z)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= M * R)
+        return;
+    const int64_t m = e / R, c = e % R;
+    Z[e] = c < K ? T0[m + c * M] : 0.0f;
+}
+
+// The first K columns of W (row-major N x R) into Q0 (column-major N x K).
+__global__ __launch_bounds__(256) void k_q0_cols(const float *__restrict__ W, int64_t N,
+                                                 int64_t K, int R, float *__restrict__ Q0)
+{
+    const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    if (e >= N * K)
+        return;
+    const int64_t j = e % N, c = e / N;
+    Q0[e] = W[j * R + c];
+}
+
 // ---------------------------------------------------------------------------
 // Host side.
 
@@ -1218,10 +1240,10 @@ void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const floa
 }
 
 void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Z, int r,
-                     float *W, unsigned char *ws, hipStream_t s)
+                     float *W, unsigned char *ws, hipStream_t s, bool unit_scale)
 {
     const SketchPlan P = sketch_plan(M, N, r);
-    const float sc = (float)(1.0 / sqrt((double)M));
+    const float sc = unit_scale ? 1.0f : (float)(1.0 / sqrt((double)M));
     float *dst = P.st == 1 ? W : reinterpret_cast<float *>(ws + P.off_wpart);
     const bool aligned = ldx % 4 == 0 && ((uintptr_t)X) % 16 == 0 && ((uintptr_t)Z) % 16 == 0 &&
                          ((uintptr_t)dst) % 16 == 0 && P.rows_t % kSketchTBK == 0;
@@ -1245,6 +1267,29 @@ void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const fl
     if (P.st > 1) // slice partials added in slice order
         hipLaunchKernelGGL(k_split_reduce, dim3(ucdiv(N * r, 256)), dim3(256), 0, s, dst,
                            (int)P.st, N, (int64_t)r, W, (int64_t)r, (int64_t)1);
+}
+
+namespace {
+inline int first_loadings_width(int64_t K) { return K <= 32 ? 32 : 64; }
+} // namespace
+
+size_t first_loadings_bytes(int64_t M, int64_t N, int64_t K)
+{
+    const int r = first_loadings_width(K);
+    return align256((size_t)M * r * 4) + align256((size_t)N * r * 4) +
+           sketch_plan(M, N, r).total;
+}
+
+void launch_first_loadings(const float *X, int64_t ldx, int64_t M, int64_t N, const float *T0,
+                           int64_t K, float *Q0, unsigned char *ws, hipStream_t s)
+{
+    const int r = first_loadings_width(K);
+    float *Z = reinterpret_cast<float *>(ws);
+    float *W = reinterpret_cast<float *>(ws + align256((size_t)M * r * 4));
+    unsigned char *sk = ws + align256((size_t)M * r * 4) + align256((size_t)N * r * 4);
+    hipLaunchKernelGGL(k_t0_rows, dim3(ucdiv(M * r, 256)), dim3(256), 0, s, T0, M, K, r, Z);
+    launch_sketch_t(X, ldx, M, N, Z, r, W, sk, s, true);
+    hipLaunchKernelGGL(k_q0_cols, dim3(ucdiv(N * K, 256)), dim3(256), 0, s, W, N, K, r, Q0);
 }
 
 constexpr int kEig64Threads = 256;

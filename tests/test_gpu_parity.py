@@ -162,6 +162,34 @@ def test_implicit_deflation_parity(orc, dtype, shape):
     assert np.array_equal(free.start_col, g["start_col"])
 
 
+@pytest.mark.parametrize("M", [3000, 3001])  # 16-byte aligned columns (matrix cores), and not
+def test_given_start_implicit_f32_first_loadings(orc, M):
+    """FP32, implicit deflation, given starts: the first loadings X^T t0 of
+    all K given columns come from one matrix-core pass before the first
+    component (instead of one pass per component); a zero column falls back
+    to the max-norm start (formed by a pass).  Compared with the oracle on
+    the same trajectory (replayed counts and start columns)."""
+    from paper_0811_1081_amd import synth
+    N, K = 203, 12
+    X = synth.haar_spectrum(M, N, 0.85 ** np.arange(40), 1e-4, seed=(12, M + N),
+                            dtype=np.float32)
+    rng = np.random.default_rng(M)
+    a = orc.fit(X.astype(np.float64), K, tol=1e-3, max_iter=50, implicit=True)
+    T0 = np.asfortranarray((a.T + 0.05 * rng.standard_normal(a.T.shape) * np.abs(a.T).max(axis=0))
+                           .astype(np.float32))
+    T0[:, 5] = 0.0  # falls back to the max-norm column
+    g = _gh().gpu_fit(X, K, tol=1e-6, max_iter=2000, implicit=True, init="given",
+                      T0=_gh().to_device(T0))
+    assert g["status"] == 0
+    assert g["start_col"][5] >= 0 and (np.delete(g["start_col"], 5) == -1).all()
+    o = orc.fit(X, K, tol=0.0, max_iter=int(g["iters"].max()), implicit=True, init="given",
+                T0=T0, replay_iters=g["iters"], replay_start=g["start_col"], tiny=orc.FLT_MIN)
+    ok = _gapped(o.sigma)
+    assert col_angles(g["P"], o.P)[ok].max() <= 1e-5
+    assert col_angles(g["T"], o.T)[ok].max() <= 1e-5
+    assert np.abs(g["sigma"] / o.sigma - 1).max() <= 1e-5
+
+
 def test_implicit_rejected_for_nipals():
     import paper_0811_1081_amd as gp
     X = np.ones((50, 10))
