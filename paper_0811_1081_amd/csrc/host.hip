@@ -346,13 +346,13 @@ struct FusedPlan {
 };
 
 // Given starts whose first loadings X^T t0 (t0 = the given column: the start
-// takes it unmodified) can all be formed up front by one matrix-core pass:
-// FP32 data, implicit deflation (X itself is the operator), at most 64
-// components.
+// takes it unmodified) can all be formed up front by matrix-core passes (one
+// per 64 components): FP32 data, implicit deflation (X itself is the
+// operator).
 bool first_loadings_apply(const gspca_problem *pr, const gspca_options *op)
 {
     return pr->dtype == GSPCA_F32 && op->implicit_deflation && op->init == GSPCA_INIT_GIVEN &&
-           op->T0 && pr->K <= 64;
+           op->T0;
 }
 
 int device_cu_count()

@@ -321,10 +321,11 @@ void launch_sketch(const float *X, int64_t ldx, int64_t M, int64_t N, const floa
 // unit_scale
 void launch_sketch_t(const float *X, int64_t ldx, int64_t M, int64_t N, const float *Z, int r,
                      float *W, unsigned char *ws, hipStream_t s, bool unit_scale = false);
-// The first loadings X^T T0 of all given starts (FP32, implicit deflation,
-// K <= 64) in one matrix-core pass over X: T0 (column-major M x K) into rows
-// of width r (zero-padded), W = X^T Z, then W's first K columns into Q0
-// (column-major N x K).  ws: first_loadings_bytes(M, N, K).
+// The first loadings X^T T0 of all given starts (FP32, implicit deflation)
+// by matrix-core passes over X, one per block of r = 32 or 64 columns of T0
+// (column-major M x K): the block into rows of width r (zero-padded),
+// W = X^T Z, then W's first columns into Q0 (column-major N x K).  ws:
+// first_loadings_bytes(M, N, K).
 size_t first_loadings_bytes(int64_t M, int64_t N, int64_t K);
 void launch_first_loadings(const float *X, int64_t ldx, int64_t M, int64_t N, const float *T0,
                            int64_t K, float *Q0, unsigned char *ws, hipStream_t s);

@@ -1042,26 +1042,30 @@ __global__ __launch_bounds__(NT) void k_whiten_eig(const double *__restrict__ gs
     }
 }
 
-// T0 (column-major M x K) into Z (row-major M x R, columns K.. zero).
+// Columns c0 .. c0 + Kc - 1 of T0 (column-major M x K) into Z (row-major
+// M x R, columns Kc .. zero).
 __global__ __launch_bounds__(256) void k_t0_rows(const float *__restrict__ T0, int64_t M,
-                                                 int64_t K, int R, float *__restrict__ Z)
+                                                 int64_t c0, int64_t Kc, int R,
+                                                 float *__restrict__ Z)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
     if (e >= M * R)
         return;
     const int64_t m = e / R, c = e % R;
-    Z[e] = c < K ? T0[m + c * M] : 0.0f;
+    Z[e] = c < Kc ? T0[m + (c0 + c) * M] : 0.0f;
 }
 
-// The first K columns of W (row-major N x R) into Q0 (column-major N x K).
+// The first Kc columns of W (row-major N x R) into columns c0 .. c0 + Kc - 1
+// of Q0 (column-major N x K).
 __global__ __launch_bounds__(256) void k_q0_cols(const float *__restrict__ W, int64_t N,
-                                                 int64_t K, int R, float *__restrict__ Q0)
+                                                 int64_t c0, int64_t Kc, int R,
+                                                 float *__restrict__ Q0)
 {
     const int64_t e = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    if (e >= N * K)
+    if (e >= N * Kc)
         return;
     const int64_t j = e % N, c = e / N;
-    Q0[e] = W[j * R + c];
+    Q0[(c0 + c) * N + j] = W[j * R + c];
 }
 
 // ---------------------------------------------------------------------------
@@ -1287,9 +1291,14 @@ void launch_first_loadings(const float *X, int64_t ldx, int64_t M, int64_t N, co
     float *Z = reinterpret_cast<float *>(ws);
     float *W = reinterpret_cast<float *>(ws + align256((size_t)M * r * 4));
     unsigned char *sk = ws + align256((size_t)M * r * 4) + align256((size_t)N * r * 4);
-    hipLaunchKernelGGL(k_t0_rows, dim3(ucdiv(M * r, 256)), dim3(256), 0, s, T0, M, K, r, Z);
-    launch_sketch_t(X, ldx, M, N, Z, r, W, sk, s, true);
-    hipLaunchKernelGGL(k_q0_cols, dim3(ucdiv(N * K, 256)), dim3(256), 0, s, W, N, K, r, Q0);
+    for (int64_t c0 = 0; c0 < K; c0 += r) { // blocks of r columns, one read of X each
+        const int64_t Kc = std::min<int64_t>(r, K - c0);
+        hipLaunchKernelGGL(k_t0_rows, dim3(ucdiv(M * r, 256)), dim3(256), 0, s, T0, M, c0, Kc,
+                           r, Z);
+        launch_sketch_t(X, ldx, M, N, Z, r, W, sk, s, true);
+        hipLaunchKernelGGL(k_q0_cols, dim3(ucdiv(N * Kc, 256)), dim3(256), 0, s, W, N, c0, Kc,
+                           r, Q0);
+    }
 }
 
 constexpr int kEig64Threads = 256;

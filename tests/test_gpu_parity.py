@@ -162,16 +162,18 @@ def test_implicit_deflation_parity(orc, dtype, shape):
     assert np.array_equal(free.start_col, g["start_col"])
 
 
-@pytest.mark.parametrize("M", [3000, 3001])  # 16-byte aligned columns (matrix cores), and not
-def test_given_start_implicit_f32_first_loadings(orc, M):
+# 16-byte aligned columns (matrix cores) and not; more than 64 components (two blocks)
+@pytest.mark.parametrize("M,K", [(3000, 12), (3001, 12), (3000, 70)])
+def test_given_start_implicit_f32_first_loadings(orc, M, K):
     """FP32, implicit deflation, given starts: the first loadings X^T t0 of
-    all K given columns come from one matrix-core pass before the first
-    component (instead of one pass per component); a zero column falls back
-    to the max-norm start (formed by a pass).  Compared with the oracle on
-    the same trajectory (replayed counts and start columns)."""
+    all K given columns come from matrix-core passes before the first
+    component (one per 64 columns, instead of one pass per component); a
+    zero column falls back to the max-norm start (formed by a pass).
+    Compared with the oracle on the same trajectory (replayed counts and
+    start columns)."""
     from paper_0811_1081_amd import synth
-    N, K = 203, 12
-    X = synth.haar_spectrum(M, N, 0.85 ** np.arange(40), 1e-4, seed=(12, M + N),
+    N = 203
+    X = synth.haar_spectrum(M, N, 0.9 ** np.arange(100), 1e-4, seed=(12, M + N),
                             dtype=np.float32)
     rng = np.random.default_rng(M)
     a = orc.fit(X.astype(np.float64), K, tol=1e-3, max_iter=50, implicit=True)
